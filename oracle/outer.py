@@ -1,0 +1,119 @@
+"""One outer (design) iteration of the first-order bilevel method (oracle).
+
+Alg. 1 alternates one low-level refinement of u with one projected
+gradient step on the design using the inexact displacement.  Order used
+here (the text of Sec. 4 uses the inexact result *after* the low-level
+step for the sensitivity):
+  1. rho = C(x)                      density filter (Remark, Sec. 3)
+  2. s, ds, diag(K) from rho          modified SIMP (Sec. 3)
+  3. u <- m Jacobi-PCG steps from u   low-level refinement (Alg. 1 / 3)
+  4. c = f^T u,  g_rho = -ds w        approximate sensitivity (Alg. 1)
+  5. g_x = C^T g_rho
+  6. g_x <- g_x - mean(g_x)           mean-projected gradient (Sec. 4.2)
+  7. y = x - alpha_k * g_x / 2,  alpha_k = alpha0 k^(-3/4)   (Sec. 5)
+     (the paper's objective is l = c/2, so its gradient is g_x / 2)
+  8. x <- Proj_X(y)                   Alg. 4
+  9. metrics ||x_new - x||_inf, ||r||_inf (recursive residual), c (Sec. 5)
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .density_filter import cone_filter_matrix, filter_forward, filter_transpose
+from .element import element_stiffness
+from .grid import Grid
+from .operator import apply_K, assemble_K, jacobi_diag, simp_dscale, simp_scale
+from .projection import project_alg4
+from .sensitivity import element_energy
+from .solve import pcg_ref
+
+
+def step_size(alpha0: float, k: int) -> float:
+    """alpha_k = alpha0 * k^(-3/4) (Sec. 5; the decay exponent satisfies the
+    step-size assumptions of Thm. 1)."""
+    return alpha0 * float(k) ** (-0.75)
+
+
+@dataclasses.dataclass
+class OuterRecord:
+    k: int
+    compliance: float
+    dx_inf: float
+    r_inf: float
+    lam: float
+    volume: float
+
+
+class OuterContext:
+    """Grid, element matrix and filter matrix of a problem, built once."""
+
+    def __init__(self, nx, ny, nz, filter_radius, fixed_mask, springs=(), young=1.0,
+                 poisson=0.3, penal=3.0, rho_min=1e-3, use_csr=None):
+        self.grid = Grid(nx, ny, nz)
+        self.KE = element_stiffness(young, poisson)
+        self.H, self.Hs = cone_filter_matrix(self.grid, filter_radius)
+        self.fixed = np.asarray(fixed_mask, dtype=np.uint8)
+        self.springs = springs
+        self.penal, self.rho_min = penal, rho_min
+        self.use_csr = (self.grid.E <= 70000) if use_csr is None else use_csr
+
+    def operator(self, s):
+        if self.use_csr:
+            K = assemble_K(self.grid, s, self.fixed, self.springs, self.KE)
+            return lambda v: K @ v
+        return lambda v: apply_K(self.grid, s, v, self.fixed, self.springs, self.KE)
+
+
+def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, vmax,
+                   mean_project=True):
+    """Returns (x_new, u_new, OuterRecord, g_x)."""
+    g = ctx.grid
+    rho = filter_forward(ctx.H, ctx.Hs, x)
+    s = simp_scale(rho, ctx.penal, ctx.rho_min)
+    ds = simp_dscale(rho, ctx.penal, ctx.rho_min)
+    D = jacobi_diag(g, s, ctx.fixed, ctx.springs, ctx.KE)
+    A = ctx.operator(s)
+    F = np.atleast_2d(f)
+    U = np.array(np.atleast_2d(u), dtype=np.float64, copy=True)
+    r_inf = 0.0
+    for r in range(F.shape[0]):
+        U[r], res = pcg_ref(A, D, F[r], U[r], inner_steps)
+        r_inf = max(r_inf, float(np.abs(res).max()))
+    c = float(sum(F[r] @ U[r] for r in range(F.shape[0])))
+    g_rho = -ds * element_energy(g, U, ctx.fixed, ctx.KE)
+    g_x = filter_transpose(ctx.H, ctx.Hs, g_rho)
+    if mean_project:
+        g_x = g_x - g_x.mean()
+    y = x - step_size(alpha0, k) * 0.5 * g_x
+    x_new, lam = project_alg4(y, lo, hi, vmax, return_lambda=True)
+    rec = OuterRecord(k=k, compliance=c, dx_inf=float(np.abs(x_new - x).max()),
+                      r_inf=r_inf, lam=float(lam), volume=float(x_new.sum()))
+    return x_new, (U if np.ndim(u) == 2 else U[0]), rec, g_x
+
+
+def run_outer_ref(ctx: OuterContext, x_init, f, iters, alpha0, inner_steps, lo, hi, vmax,
+                  mean_project=True, u0=None):
+    """x_0 = Proj_X(x_init), u_0 = 0 (or u0); then `iters` outer steps."""
+    x = project_alg4(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
+    F = np.atleast_2d(f)
+    u = np.zeros_like(F) if u0 is None else np.array(u0, dtype=np.float64)
+    recs, xs = [], [x.copy()]
+    for k in range(1, iters + 1):
+        x, u, rec, _ = outer_step_ref(ctx, x, u, F, k, alpha0, inner_steps, lo, hi, vmax,
+                                      mean_project)
+        recs.append(rec)
+        xs.append(x.copy())
+    return x, u, recs, xs
+
+
+def default_alpha0(ctx: OuterContext, x_init, f, inner_steps, lo, hi, vmax,
+                   max_move=0.2, mean_project=True):
+    """Step-size reading: alpha0 such that the first step moves no density
+    by more than `max_move`:  alpha0 = max_move / max|g_P(x_1) / 2|."""
+    x = project_alg4(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
+    F = np.atleast_2d(f)
+    _, _, _, g_x = outer_step_ref(ctx, x, np.zeros_like(F), F, 1, 0.0, inner_steps, lo, hi,
+                                  vmax, mean_project)
+    return max_move / float(np.abs(0.5 * g_x).max())

@@ -1,0 +1,52 @@
+"""Invariants of the oracle's outer iteration (CPU only): feasibility of
+every iterate, the mean-projected gradient sums to zero, the step size
+schedule, and agreement of a run with exact inner solves with plain
+projected gradient descent on the exact objective."""
+import numpy as np
+
+import oracle
+import synth
+from oracle.outer import OuterContext, outer_step_ref, run_outer_ref, step_size
+
+
+def _ctx(p, **kw):
+    return OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs, **kw)
+
+
+def test_step_size_schedule():
+    assert step_size(0.5, 1) == 0.5
+    assert abs(step_size(0.5, 16) - 0.5 / 8.0) < 1e-16
+
+
+def test_cfg1_run_is_feasible_and_mean_projected():
+    p = synth.config("cfg1")
+    ctx = _ctx(p)
+    x, u, recs, xs = run_outer_ref(ctx, p.x0, p.loads, 8, 0.05, p.inner_steps, 0.0, 1.0, p.vmax)
+    for xk in xs:
+        assert xk.min() >= 0.0 and xk.max() <= 1.0
+        assert xk.sum() <= p.vmax * (1 + 1e-12)
+    assert all(np.isfinite(r.compliance) and r.compliance > 0 for r in recs)
+    _, _, _, gx = outer_step_ref(ctx, xs[-1], u, p.loads, 9, 0.05, p.inner_steps, 0.0, 1.0, p.vmax)
+    assert abs(gx.sum()) <= 1e-12 * np.abs(gx).sum()
+
+
+def test_exact_inner_solve_gives_projected_gradient_descent():
+    """With enough inner CG steps the inexact gradient is the exact one, so
+    one outer step equals Proj(x - alpha/2 (g - mean g)) on the exact
+    compliance gradient (built from a direct solve)."""
+    p = synth.cantilever(4, 3, 3, volfrac=0.3, filter_radius=1.5, outer_iters=1,
+                         inner_steps=1, seed=1)
+    ctx = _ctx(p)
+    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    nfree = int((p.fixed_mask == 0).sum())
+    x1, u1, rec, _ = outer_step_ref(ctx, x, np.zeros_like(p.loads), p.loads, 1, 0.3, 3 * nfree,
+                                    0.0, 1.0, p.vmax)
+    rho = oracle.filter_forward(ctx.H, ctx.Hs, x)
+    s = oracle.simp_scale(rho)
+    K = oracle.assemble_K(ctx.grid, s, p.fixed_mask)
+    u = oracle.solve_direct(K, p.loads[0])
+    g = oracle.filter_transpose(ctx.H, ctx.Hs, oracle.compliance_gradient(ctx.grid, rho, u, p.fixed_mask))
+    g = g - g.mean()
+    ref = oracle.project_bisect(x - 0.3 * 0.5 * g, 0.0, 1.0, p.vmax)
+    assert np.abs(x1 - ref).max() < 1e-9
+    assert abs(rec.compliance - p.loads[0] @ u) < 1e-9 * abs(rec.compliance)
