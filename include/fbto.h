@@ -1,0 +1,222 @@
+/*
+ * fbto.h -- C ABI of the MI355X matrix-free SIMP hot path.
+ *
+ * Method: first-order bilevel topology optimization (arXiv 2204.06204).
+ * The design problem (Sec. 3, Eq. opt) is
+ *     min_{x in X}  c(x) = f^T K(rho(x))^{-1} f,
+ *     K(rho) = sum_e (rho_min + (1 - rho_min) rho_e^p) P_e^T KE P_e,
+ *     X = { lo <= x <= hi, 1^T x <= vmax },
+ * with rho = C(x) a linear density filter (Remark on modifiers, Sec. 3).
+ * Alg. 1 alternates an inexact low-level refinement of u (here: a few
+ * Jacobi-PCG steps) with one projected gradient step on x (Alg. 4 is the
+ * projection).  The grid is a structured nx*ny*nz voxel grid of unit-cube
+ * trilinear hex8 elements (the paper's regular-grid case, Sec. 4.3).
+ *
+ * Numbering (shared with every caller):
+ *   node n = i + (nx+1)*(j + (ny+1)*k)      (0 <= i <= nx, ...)
+ *   DOF 3*n + c                               (c = 0, 1, 2 for x, y, z)
+ *   element e = ex + nx*(ey + ny*ez)
+ *   multi-RHS vectors are [nrhs][3N], contiguous.
+ *
+ * Precision: `prec` selects the element type of every `void*` float array
+ * of a call: double for FBTO_F64, float for FBTO_F32.  Reductions (dot
+ * products, norms, sums of the projection) are always FP64, and every
+ * `double*` output is FP64.
+ *
+ * Ownership: every data pointer is a caller-owned HIP *device* pointer
+ * unless marked "host".  The library never frees or retains them beyond
+ * the call.  The library owns the grid handle and its workspace (created
+ * by fbto_setup_grid, released by fbto_destroy_grid).
+ *
+ * Streams: `stream` is a hipStream_t (NULL = default stream).  Calls are
+ * stream-ordered and asynchronous unless stated otherwise; results in
+ * device memory are valid once the stream reaches them.  One grid handle
+ * must not be used on two streams at once (its workspace is shared).
+ *
+ * Errors: each call returns FBTO_OK or an error code and never throws.
+ * Argument errors are detected on the host before any launch; the message
+ * is available from fbto_last_error() (thread-local).  Conditions found on
+ * the device (CG breakdown, non-finite values) are reported in the FP64
+ * status slot of the caller's info buffer (see fbto_inner_solve).
+ */
+#ifndef FBTO_H
+#define FBTO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fbto_grid_s* fbto_grid_t;
+
+typedef enum fbto_status {
+  FBTO_OK = 0,
+  FBTO_ERR_ARG = 1,          /* invalid argument (host check)             */
+  FBTO_ERR_ALLOC = 2,        /* device allocation failed                  */
+  FBTO_ERR_HIP = 3,          /* HIP runtime error                         */
+  FBTO_ERR_INFEASIBLE = 4,   /* vmax < lo * E: X is empty                 */
+  FBTO_ERR_BREAKDOWN = 5,    /* device: p^T K p <= 0 in CG                 */
+  FBTO_ERR_NONFINITE = 6,    /* device: NaN / Inf met                     */
+  FBTO_ERR_UNSUPPORTED = 7   /* valid request this build does not handle  */
+} fbto_status_t;
+
+typedef enum fbto_prec { FBTO_F64 = 0, FBTO_F32 = 1 } fbto_prec_t;
+
+/* Low-level update of Alg. 1 / 3 (Sec. 4).  PCG_JACOBI: conjugate
+ * gradients preconditioned by diag(K), restarted at every call and
+ * warm-started from u.  RICHARDSON: Alg. 1's u <- u - beta (K u - f).
+ * DAMPED_JACOBI: u <- u - omega diag(K)^{-1} (K u - f). */
+typedef enum fbto_method {
+  FBTO_PCG_JACOBI = 0,
+  FBTO_RICHARDSON = 1,
+  FBTO_DAMPED_JACOBI = 2
+} fbto_method_t;
+
+typedef struct fbto_grid_desc {
+  int32_t nx, ny, nz;        /* elements per axis, each >= 1              */
+  int32_t max_rhs;           /* right-hand sides per call, 1..4            */
+  double young, poisson;     /* E > 0, -1 < nu < 0.5                       */
+  double penal;              /* SIMP exponent p >= 1                        */
+  double rho_min;            /* 0 <= rho_min < 1 (stiffness floor)          */
+  double filter_radius;      /* cone-filter radius r in element widths;    */
+                             /* r <= 1 makes the filter the identity       */
+} fbto_grid_desc_t;
+
+/* Slots of the FP64 info record written by fbto_inner_solve (per RHS,
+ * FBTO_SOLVE_INFO doubles each) and by fbto_outer_step. */
+enum {
+  FBTO_SI_RNORM2 = 0,        /* ||r||_2 of the recursive residual          */
+  FBTO_SI_RNORMI = 1,        /* ||r||_inf                                  */
+  FBTO_SI_FNORM2 = 2,        /* ||f||_2                                    */
+  FBTO_SI_STEPS = 3,         /* steps taken                                */
+  FBTO_SI_STATUS = 4,        /* 0 or an fbto_status_t value                */
+  FBTO_SOLVE_INFO = 8
+};
+enum {
+  FBTO_OI_COMPLIANCE = 0,    /* c = sum_r f_r^T u_r after the inner solve   */
+  FBTO_OI_DX_INF = 1,        /* ||x_{k+1} - x_k||_inf                       */
+  FBTO_OI_R_INF = 2,         /* max_r ||r_r||_inf after the inner solve     */
+  FBTO_OI_LAMBDA = 3,        /* multiplier of the volume constraint         */
+  FBTO_OI_VOLUME = 4,        /* sum(x_{k+1})                                */
+  FBTO_OI_RREL = 5,          /* max_r ||r_r||_2 / ||f_r||_2                  */
+  FBTO_OI_STATUS = 6,        /* 0 or an fbto_status_t value                 */
+  FBTO_OI_GRAD_MEAN = 7,     /* mean of the filtered gradient (before the   */
+                             /* mean projection)                            */
+  FBTO_OUTER_INFO = 8
+};
+
+/* Create a grid handle.  Defines the operator of Sec. 3 on the voxel grid
+ * of Sec. 4.3: supports and springs are fixed here, densities are passed
+ * per call.
+ *   fixed_dof_mask  host, [3N] bytes, nonzero = DOF fixed.  A fixed DOF gets
+ *                   an identity row and column in K (y_i = u_i); callers
+ *                   keep f_i = 0 and u_i = 0 there.  May be NULL (none).
+ *   spring_dof/k    host, n_springs entries: K_ii += k on free DOF i
+ *                   (ignored on fixed DOFs).  May be NULL if n_springs = 0.
+ *   out             receives the handle.
+ * Allocates device workspace (FP32 and FP64 vectors for max_rhs RHS are
+ * allocated on first use of each precision).  Errors: FBTO_ERR_ARG,
+ * FBTO_ERR_ALLOC, FBTO_ERR_HIP. */
+fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* desc,
+                              const uint8_t* fixed_dof_mask,
+                              int32_t n_springs, const int64_t* spring_dof,
+                              const double* spring_k, fbto_grid_t* out);
+
+/* Release the handle and its workspace (synchronises the device). */
+fbto_status_t fbto_destroy_grid(fbto_grid_t g);
+
+/* Sizes of a grid: elements, nodes, DOFs (host pointers, any may be NULL). */
+fbto_status_t fbto_grid_sizes(fbto_grid_t g, int64_t* n_elem, int64_t* n_node,
+                              int64_t* n_dof);
+
+/* y = K(rho_phys) u for nrhs vectors (Sec. 3, K(v) = sum_e A_e K_e; the
+ * regular-grid matrix-free product of Sec. 4.3).  rho_phys: [E] physical
+ * (filtered) densities; u, y: [nrhs][3N]; 1 <= nrhs <= max_rhs.  u and y
+ * must not overlap.  Fixed DOFs: y_i = u_i; free rows ignore u at fixed
+ * DOFs. */
+fbto_status_t fbto_apply_K(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys,
+                           const void* u, void* y, int32_t nrhs, void* stream);
+
+/* Low-level refinement of u towards K(rho_phys) u = f (Alg. 1 / 3 low-level
+ * line), `steps` steps of `method` from the warm start in u, per RHS.
+ *   omega   step of RICHARDSON (beta) or DAMPED_JACOBI (omega); unused by PCG.
+ *   rtol    0: run exactly `steps` steps, asynchronously.  rtol > 0 (PCG
+ *           only): stop once ||r||_2 <= rtol ||f||_2 or after `steps`
+ *           steps; this mode synchronises the stream every 32 steps.
+ *   info    device, FP64 [nrhs][FBTO_SOLVE_INFO], may be NULL.
+ * Device-detected breakdown/non-finite values go to FBTO_SI_STATUS. */
+fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys,
+                               const void* f, void* u, int32_t nrhs,
+                               fbto_method_t method, int32_t steps, double omega,
+                               double rtol, double* info, void* stream);
+
+/* Mixed-precision solve with FP64 iterative refinement:
+ *   repeat: r = f - K64 u (FP64 operator);  stop if ||r||_2 <= rtol ||f||_2;
+ *           d = `inner_steps` steps of PCG in `inner_prec` on K d = r;  u += d
+ * rho_phys, f, u are FP64 ([E], [nrhs][3N], [nrhs][3N]).  Synchronises the
+ * stream after each refinement step.  info: device FP64
+ * [nrhs][FBTO_SOLVE_INFO] (STEPS counts inner steps), may be NULL.
+ * *refinements (host, may be NULL) receives the number of refinements. */
+fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec,
+                                 const double* rho_phys, const double* f, double* u,
+                                 int32_t nrhs, double rtol, int32_t max_refine,
+                                 int32_t inner_steps, double* info,
+                                 int32_t* refinements, void* stream);
+
+/* Sensitivity of Sec. 3 / Alg. 1, summed over the nrhs load cases:
+ *   dobj[e] = -ds_e sum_r lam_{r,e}^T KE u_{r,e},
+ *   ds_e = p (1 - rho_min) rho_e^(p-1),
+ * with lam = u when lam == NULL (then dobj = dc/drho for c = sum_r f_r.u_r).
+ * For a linear objective L = t^T u pass the adjoint lam = K^{-1} t.
+ * Element strains are recomputed from the nodal vectors (nothing stored).
+ *   rho_phys [E]; u, lam, f [nrhs][3N]; dobj [E].
+ *   f, obj  if both non-NULL, obj (device FP64 scalar) receives
+ *           sum_r f_r . u_r (the compliance). */
+fbto_status_t fbto_sensitivity(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys,
+                               const void* u, const void* lam, const void* f,
+                               int32_t nrhs, void* dobj, double* obj, void* stream);
+
+/* Linear cone filter (Remark on modifiers, Sec. 3):
+ *   transpose = 0:  out = (H in) / Hs          (x -> rho)
+ *   transpose = 1:  out = H^T (in / Hs)        (d/drho -> d/dx)
+ * H_ej = max(0, r - |c_e - c_j|), Hs_e = sum_j H_ej, boundary-truncated.
+ * in, out: [E], must not overlap. */
+fbto_status_t fbto_filter(fbto_grid_t g, fbto_prec_t prec, int32_t transpose,
+                          const void* in, void* out, void* stream);
+
+/* Euclidean projection onto X = {lo <= x <= hi, sum x <= vmax} (Sec. 4.2,
+ * Eq. piecewiseLinearEQ; Alg. 4 computes the same point by sorting).
+ * x = clamp(y - lambda, lo, hi) with lambda = 0 if clamp(y) is feasible,
+ * else the root of sum clamp(y - lambda, lo, hi) = vmax found on the device
+ * in FP64 (Newton steps on the piecewise-linear sum, safeguarded by
+ * bisection, finished by the exact solve on the final linear piece).
+ * y, x: [E] (may alias).  lambda (device FP64, may be NULL) receives lambda.
+ * Errors: FBTO_ERR_INFEASIBLE if vmax < lo * E. */
+fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y,
+                                  void* x, double lo, double hi, double vmax,
+                                  double* lambda, void* stream);
+
+/* One outer iteration k (1-based) of the first-order bilevel method
+ * (Alg. 1 with the Jacobi-PCG low-level step):
+ *   rho = C(x); u <- inner_steps PCG steps on K(rho) u = f from u;
+ *   g = C^T(dc/drho); g <- g - mean(g) if mean_project (Sec. 4.2);
+ *   x <- Proj_X(x - alpha_k g / 2),  alpha_k = alpha0 k^(-3/4) (Sec. 5).
+ * x: [E] in/out, u: [nrhs][3N] in/out, f: [nrhs][3N].  hi = 1.
+ * info: device FP64 [FBTO_OUTER_INFO] (may be NULL). */
+fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
+                              const void* f, int32_t nrhs, int32_t k, double alpha0,
+                              int32_t inner_steps, int32_t mean_project, double lo,
+                              double vmax, double* info, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* fbto_last_error(void);
+
+/* Library version string. */
+const char* fbto_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FBTO_H */

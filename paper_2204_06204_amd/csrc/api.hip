@@ -1,0 +1,581 @@
+// C ABI of the MI355X matrix-free SIMP hot path: argument checks, workspace,
+// and the order of kernel launches of each call (no arithmetic here beyond
+// the element-matrix constants and the filter stencil, both set up once).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "fbto.h"
+#include "internal.h"
+
+using namespace fbto;
+
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fbto_status_t fail(fbto_status_t s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+fbto_status_t ok() {
+  g_last_error.clear();
+  return FBTO_OK;
+}
+
+#define HIP_TRY(expr)                                                                       \
+  do {                                                                                      \
+    hipError_t _e = (expr);                                                                 \
+    if (_e != hipSuccess)                                                                   \
+      return fail(_e == hipErrorOutOfMemory ? FBTO_ERR_ALLOC : FBTO_ERR_HIP, "%s: %s", #expr, \
+                  hipGetErrorString(_e));                                                   \
+  } while (0)
+
+template <typename T>
+Vecs& vecs(fbto_grid_s* g);
+template <>
+Vecs& vecs<double>(fbto_grid_s* g) { return g->v64; }
+template <>
+Vecs& vecs<float>(fbto_grid_s* g) { return g->v32; }
+
+// Element stiffness of the unit-cube hex8 in the sum/difference basis.
+// Per axis the basis of the pair (u0 + u1, u1 - u0) is {1/2, t - 1/2}, whose
+// 1D integrals are M(m,m) = 1/4, M(d,d) = 1/12, G(d,d) = 1 and
+// int psi_d' psi_m = 1/2.  The isotropic bilinear form
+//   int lambda div u div v + mu (grad u : grad v + grad u : grad v^T)
+// then has, for component i and mode q (bit b set = difference mode along b),
+//   diagonal  (lambda + mu) [q_i] W_i(q) + mu sum_l [q_l] W_l(q),
+//             W_l(q) = prod_{k != l} M(q_k),
+//   coupling  to component j, mode q ^ (1<<i) ^ (1<<j) when q_i != q_j:
+//             lambda/4 M(q_k) if q_i = d, else mu/4 M(q_k).
+void modal_coefficients(double young, double poisson, Modal<double>& km, double& ke_diag) {
+  const double lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson));
+  const double mu = young / (2.0 * (1.0 + poisson));
+  const double M[2] = {0.25, 1.0 / 12.0};
+  for (int i = 0; i < 3; ++i) {
+    for (int q = 0; q < 8; ++q) {
+      double W[3];
+      for (int l = 0; l < 3; ++l) {
+        W[l] = 1.0;
+        for (int k = 0; k < 3; ++k)
+          if (k != l) W[l] *= M[(q >> k) & 1];
+      }
+      double d = ((q >> i) & 1) ? (lam + mu) * W[i] : 0.0;
+      for (int l = 0; l < 3; ++l)
+        if ((q >> l) & 1) d += mu * W[l];
+      km.dg[i][q] = q == 0 ? 0.0 : d;
+    }
+  }
+  for (int b = 0; b < 2; ++b) {
+    km.lam4[b] = 0.25 * lam * M[b];
+    km.mu4[b] = 0.25 * mu * M[b];
+  }
+  ke_diag = (lam + 4.0 * mu) / 9.0;
+}
+
+fbto_status_t check_grid(fbto_grid_t g) {
+  if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
+  return FBTO_OK;
+}
+fbto_status_t check_prec(fbto_prec_t p) {
+  if (p != FBTO_F64 && p != FBTO_F32) return fail(FBTO_ERR_ARG, "unknown precision %d", (int)p);
+  return FBTO_OK;
+}
+fbto_status_t check_nrhs(fbto_grid_t g, int nrhs) {
+  if (nrhs < 1 || nrhs > g->desc.max_rhs)
+    return fail(FBTO_ERR_ARG, "nrhs = %d outside [1, %d]", nrhs, g->desc.max_rhs);
+  return FBTO_OK;
+}
+
+template <typename T>
+fbto_status_t ensure_vecs(fbto_grid_s* g) {
+  Vecs& V = vecs<T>(g);
+  if (V.ready) return FBTO_OK;
+  const int64_t nd = g->geo.ndof * g->desc.max_rhs, E = g->geo.E;
+  HIP_TRY(hipMalloc(&V.r, nd * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.p, nd * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.q, nd * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.invD, g->geo.ndof * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.rho, E * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.ge, E * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.gx, E * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.y, E * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.Hs, E * sizeof(T)));
+  HIP_TRY(launch_hs<T>(g, (T*)V.Hs, nullptr));
+  HIP_TRY(hipDeviceSynchronize());
+  V.ready = true;
+  return FBTO_OK;
+}
+
+void free_vecs(Vecs& V) {
+  void* ps[] = {V.r, V.p, V.q, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  V = Vecs{};
+}
+
+// Per-grid buffers of the mixed-precision refinement (allocated on demand).
+struct IrBufs {
+  void* f = nullptr;   // inner right-hand side
+  void* d = nullptr;   // inner correction
+  double* r64 = nullptr;
+};
+struct GridExtra {
+  IrBufs ir32, ir64;
+};
+std::vector<std::pair<fbto_grid_s*, GridExtra*>>& extras() {
+  static std::vector<std::pair<fbto_grid_s*, GridExtra*>> v;
+  return v;
+}
+GridExtra* extra_of(fbto_grid_s* g) {
+  for (auto& p : extras())
+    if (p.first == g) return p.second;
+  auto* e = new GridExtra();
+  extras().push_back({g, e});
+  return e;
+}
+void drop_extra(fbto_grid_s* g) {
+  auto& v = extras();
+  for (size_t i = 0; i < v.size(); ++i) {
+    if (v[i].first == g) {
+      GridExtra* e = v[i].second;
+      for (IrBufs* b : {&e->ir32, &e->ir64}) {
+        if (b->f) (void)hipFree(b->f);
+        if (b->d) (void)hipFree(b->d);
+        if (b->r64) (void)hipFree(b->r64);
+      }
+      delete e;
+      v.erase(v.begin() + i);
+      return;
+    }
+  }
+}
+
+// PCG on K(rho) u = f from the warm start u (steps iterations; rtol > 0 stops
+// early, checked on the host every 32 steps).
+template <typename T>
+fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps,
+                      double rtol, hipStream_t st) {
+  Vecs& V = vecs<T>(g);
+  T* r = (T*)V.r;
+  T* p = (T*)V.p;
+  T* q = (T*)V.q;
+  T* invD = (T*)V.invD;
+  HIP_TRY(launch_diag<T>(g, rho, invD, st));
+  HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
+  HIP_TRY(launch_pcg_init<T>(g, r, p, invD, nrhs, f, rtol, st));
+  for (int s = 0; s < steps; ++s) {
+    HIP_TRY(launch_apply<T>(g, rho, p, q, nullptr, nrhs, 2, st));
+    HIP_TRY(launch_pcg_update<T>(g, u, r, p, q, invD, nrhs, st));
+    if (s + 1 < steps) HIP_TRY(launch_pcg_pupdate<T>(g, r, p, invD, nrhs, st));
+    if (rtol > 0.0 && ((s + 1) % 32 == 0)) {
+      Scalars host;
+      HIP_TRY(hipMemcpyAsync(&host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      bool all = true;
+      for (int R = 0; R < nrhs; ++R) all = all && host.done[R] != 0.0;
+      if (all) break;
+    }
+  }
+  return FBTO_OK;
+}
+
+__global__ void k_set_steps(Scalars* sc, int nrhs, double steps) {
+  for (int R = 0; R < nrhs; ++R) sc->steps[R] = steps;
+}
+
+template <typename T>
+fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps,
+                        double omega, int use_diag, hipStream_t st) {
+  Vecs& V = vecs<T>(g);
+  T* r = (T*)V.r;
+  T* invD = (T*)V.invD;
+  HIP_TRY(launch_diag<T>(g, rho, invD, st));
+  for (int s = 0; s < steps; ++s) {
+    HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
+    HIP_TRY(launch_relax_update<T>(g, u, r, invD, nrhs, omega, use_diag, st));
+  }
+  HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
+  HIP_TRY(launch_pcg_init<T>(g, r, (T*)V.p, invD, nrhs, f, 0.0, st));
+  hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, g->sc, nrhs, (double)steps);
+  HIP_TRY(hipGetLastError());
+  return FBTO_OK;
+}
+
+template <typename T>
+fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k, double alpha0,
+                        int inner_steps, int mean_project, double lo, double vmax, double* info,
+                        hipStream_t st) {
+  Vecs& V = vecs<T>(g);
+  T* rho = (T*)V.rho;
+  HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st);
+  if (s != FBTO_OK) return s;
+  HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, st));
+  HIP_TRY(launch_dot<T>(g, f, u, g->geo.ndof, nrhs, &g->sc->dot[0], st));
+  HIP_TRY(launch_filter<T>(g, 1, (const T*)V.ge, (T*)V.gx, 1, st));
+  const double alpha_k = alpha0 * std::pow((double)k, -0.75);
+  HIP_TRY(launch_step_v<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, vmax,
+                           st));
+  HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, info, st));
+  if (info) HIP_TRY(launch_outer_info(g, info, nrhs, st));
+  return FBTO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fbto_last_error(void) { return g_last_error.c_str(); }
+
+const char* fbto_version(void) { return "fbto-mi355x 0.1 (gfx950)"; }
+
+fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_dof_mask,
+                              int32_t n_springs, const int64_t* spring_dof, const double* spring_k,
+                              fbto_grid_t* out) {
+  if (!d || !out) return fail(FBTO_ERR_ARG, "desc and out must be non-NULL");
+  *out = nullptr;
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1)
+    return fail(FBTO_ERR_ARG, "grid %d x %d x %d: every axis needs >= 1 element", d->nx, d->ny, d->nz);
+  if (d->nx > 65534 || d->ny > 65534 || d->nz > 65534)
+    return fail(FBTO_ERR_ARG, "grid axis longer than 65534 elements");
+  const int64_t N = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
+  if (N > ((int64_t)1 << 31))
+    return fail(FBTO_ERR_ARG, "grid has %lld nodes (limit 2^31)", (long long)N);
+  if (d->max_rhs < 1 || d->max_rhs > 4) return fail(FBTO_ERR_ARG, "max_rhs = %d outside [1, 4]", d->max_rhs);
+  if (!(d->young > 0.0) || !std::isfinite(d->young)) return fail(FBTO_ERR_ARG, "young must be > 0");
+  if (!(d->poisson > -1.0 && d->poisson < 0.5)) return fail(FBTO_ERR_ARG, "poisson must be in (-1, 0.5)");
+  if (!(d->penal >= 1.0) || !std::isfinite(d->penal)) return fail(FBTO_ERR_ARG, "penal must be >= 1");
+  if (!(d->rho_min >= 0.0 && d->rho_min < 1.0)) return fail(FBTO_ERR_ARG, "rho_min must be in [0, 1)");
+  if (!(d->filter_radius >= 0.0) || !(d->filter_radius <= 16.0))
+    return fail(FBTO_ERR_ARG, "filter_radius must be in [0, 16]");
+  if (n_springs < 0 || (n_springs > 0 && (!spring_dof || !spring_k)))
+    return fail(FBTO_ERR_ARG, "n_springs = %d with NULL spring arrays", n_springs);
+  if (n_springs > 4096) return fail(FBTO_ERR_ARG, "at most 4096 springs");
+  for (int s = 0; s < n_springs; ++s) {
+    if (spring_dof[s] < 0 || spring_dof[s] >= 3 * N)
+      return fail(FBTO_ERR_ARG, "spring %d: DOF %lld out of range", s, (long long)spring_dof[s]);
+    if (!(spring_k[s] >= 0.0) || !std::isfinite(spring_k[s]))
+      return fail(FBTO_ERR_ARG, "spring %d: stiffness must be finite and >= 0", s);
+  }
+
+  fbto_grid_s* g = new (std::nothrow) fbto_grid_s();
+  if (!g) return fail(FBTO_ERR_ALLOC, "host allocation failed");
+  g->desc = *d;
+  Geo& G = g->geo;
+  G.nx = d->nx;
+  G.ny = d->ny;
+  G.nz = d->nz;
+  G.nxn = d->nx + 1;
+  G.nyn = d->ny + 1;
+  G.nzn = d->nz + 1;
+  G.N = N;
+  G.E = (int64_t)d->nx * d->ny * d->nz;
+  G.ndof = 3 * N;
+  modal_coefficients(d->young, d->poisson, g->km64, g->ke_diag);
+  for (int i = 0; i < 3; ++i)
+    for (int q = 0; q < 8; ++q) g->km32.dg[i][q] = (float)g->km64.dg[i][q];
+  for (int b = 0; b < 2; ++b) {
+    g->km32.lam4[b] = (float)g->km64.lam4[b];
+    g->km32.mu4[b] = (float)g->km64.mu4[b];
+  }
+  g->simp.penal = d->penal;
+  g->simp.rho_min = d->rho_min;
+  g->simp.cubic = d->penal == 3.0 ? 1 : 0;
+
+  // cone-filter stencil: offsets with r - |d| > 0
+  std::vector<int> off;
+  std::vector<double> w64;
+  const double r = d->filter_radius;
+  const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
+  for (int dz = -R; dz <= R; ++dz)
+    for (int dy = -R; dy <= R; ++dy)
+      for (int dx = -R; dx <= R; ++dx) {
+        const double dist = std::sqrt((double)(dx * dx + dy * dy + dz * dz));
+        double w = r - dist;
+        if (r <= 1.0) w = (dx == 0 && dy == 0 && dz == 0) ? 1.0 : 0.0;
+        if (w > 0.0) {
+          off.push_back(dx);
+          off.push_back(dy);
+          off.push_back(dz);
+          w64.push_back(w);
+        }
+      }
+  std::vector<float> w32(w64.begin(), w64.end());
+  g->n_stencil = (int)w64.size();
+
+  std::vector<uint8_t> nm(N, 0);
+  if (fixed_dof_mask)
+    for (int64_t n = 0; n < N; ++n)
+      nm[n] = (uint8_t)((fixed_dof_mask[3 * n] ? 1 : 0) | (fixed_dof_mask[3 * n + 1] ? 2 : 0) |
+                        (fixed_dof_mask[3 * n + 2] ? 4 : 0));
+
+  auto cleanup_fail = [&](fbto_status_t s) {
+    fbto_destroy_grid(g);
+    return s;
+  };
+#define SETUP_TRY(expr)                                                                      \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return cleanup_fail(fail(_e == hipErrorOutOfMemory ? FBTO_ERR_ALLOC : FBTO_ERR_HIP,     \
+                               "%s: %s", #expr, hipGetErrorString(_e)));                     \
+  } while (0)
+
+  SETUP_TRY(hipGetDevice(&g->device));
+  int ncu = 0;
+  SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device));
+  g->n_cu = ncu > 0 ? ncu : 256;
+  SETUP_TRY(hipMalloc(&g->mask, N));
+  SETUP_TRY(hipMemcpy(g->mask, nm.data(), N, hipMemcpyHostToDevice));
+  g->n_springs = n_springs;
+  if (n_springs > 0) {
+    std::vector<float> k32(spring_k, spring_k + n_springs);
+    SETUP_TRY(hipMalloc(&g->spring_dof, n_springs * sizeof(int64_t)));
+    SETUP_TRY(hipMalloc(&g->spring_k64, n_springs * sizeof(double)));
+    SETUP_TRY(hipMalloc(&g->spring_k32, n_springs * sizeof(float)));
+    SETUP_TRY(hipMemcpy(g->spring_dof, spring_dof, n_springs * sizeof(int64_t), hipMemcpyHostToDevice));
+    SETUP_TRY(hipMemcpy(g->spring_k64, spring_k, n_springs * sizeof(double), hipMemcpyHostToDevice));
+    SETUP_TRY(hipMemcpy(g->spring_k32, k32.data(), n_springs * sizeof(float), hipMemcpyHostToDevice));
+  }
+  SETUP_TRY(hipMalloc(&g->stencil_off, off.size() * sizeof(int)));
+  SETUP_TRY(hipMalloc(&g->stencil_w64, w64.size() * sizeof(double)));
+  SETUP_TRY(hipMalloc(&g->stencil_w32, w32.size() * sizeof(float)));
+  SETUP_TRY(hipMemcpy(g->stencil_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice));
+  SETUP_TRY(hipMemcpy(g->stencil_w64, w64.data(), w64.size() * sizeof(double), hipMemcpyHostToDevice));
+  SETUP_TRY(hipMemcpy(g->stencil_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
+  SETUP_TRY(hipMalloc(&g->sc, sizeof(Scalars)));
+  SETUP_TRY(hipMemset(g->sc, 0, sizeof(Scalars)));
+  SETUP_TRY(hipMalloc(&g->counters, CNT_COUNT * sizeof(unsigned)));
+  SETUP_TRY(hipMemset(g->counters, 0, CNT_COUNT * sizeof(unsigned)));
+  g->max_partials = std::max(apply_max_blocks(G, g->n_cu), g->n_cu * 8);
+  SETUP_TRY(hipMalloc(&g->partials, (size_t)g->max_partials * 16 * sizeof(double)));
+  SETUP_TRY(hipDeviceSynchronize());
+#undef SETUP_TRY
+  *out = g;
+  return ok();
+}
+
+fbto_status_t fbto_destroy_grid(fbto_grid_t g) {
+  if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
+  (void)hipDeviceSynchronize();
+  void* ps[] = {g->mask, g->spring_dof, g->spring_k64, g->spring_k32, g->stencil_off,
+                g->stencil_w64, g->stencil_w32, g->sc, g->counters, g->partials};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  free_vecs(g->v64);
+  free_vecs(g->v32);
+  drop_extra(g);
+  delete g;
+  return ok();
+}
+
+fbto_status_t fbto_grid_sizes(fbto_grid_t g, int64_t* n_elem, int64_t* n_node, int64_t* n_dof) {
+  if (check_grid(g)) return FBTO_ERR_ARG;
+  if (n_elem) *n_elem = g->geo.E;
+  if (n_node) *n_node = g->geo.N;
+  if (n_dof) *n_dof = g->geo.ndof;
+  return ok();
+}
+
+fbto_status_t fbto_apply_K(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys, const void* u,
+                           void* y, int32_t nrhs, void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!rho_phys || !u || !y) return fail(FBTO_ERR_ARG, "rho_phys, u and y must be non-NULL");
+  if (u == y) return fail(FBTO_ERR_ARG, "u and y must not overlap");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == FBTO_F64)
+    HIP_TRY(launch_apply<double>(g, (const double*)rho_phys, (const double*)u, (double*)y, nullptr, nrhs, 0, st));
+  else
+    HIP_TRY(launch_apply<float>(g, (const float*)rho_phys, (const float*)u, (float*)y, nullptr, nrhs, 0, st));
+  return ok();
+}
+
+fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys, const void* f,
+                               void* u, int32_t nrhs, fbto_method_t method, int32_t steps,
+                               double omega, double rtol, double* info, void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!rho_phys || !f || !u) return fail(FBTO_ERR_ARG, "rho_phys, f and u must be non-NULL");
+  if (steps < 0) return fail(FBTO_ERR_ARG, "steps must be >= 0");
+  if (!(rtol >= 0.0)) return fail(FBTO_ERR_ARG, "rtol must be >= 0");
+  if (method != FBTO_PCG_JACOBI && method != FBTO_RICHARDSON && method != FBTO_DAMPED_JACOBI)
+    return fail(FBTO_ERR_ARG, "unknown method %d", (int)method);
+  if (method != FBTO_PCG_JACOBI && rtol > 0.0)
+    return fail(FBTO_ERR_UNSUPPORTED, "rtol > 0 is supported for PCG only");
+  if (method != FBTO_PCG_JACOBI && !(std::isfinite(omega) && omega > 0.0))
+    return fail(FBTO_ERR_ARG, "omega must be finite and > 0");
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    s = method == FBTO_PCG_JACOBI
+            ? pcg_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, rtol, st)
+            : relax_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, omega,
+                                method == FBTO_DAMPED_JACOBI, st);
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    s = method == FBTO_PCG_JACOBI
+            ? pcg_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, rtol, st)
+            : relax_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, omega,
+                               method == FBTO_DAMPED_JACOBI, st);
+  }
+  if (s) return s;
+  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, st));
+  return ok();
+}
+
+fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const double* rho_phys,
+                                 const double* f, double* u, int32_t nrhs, double rtol,
+                                 int32_t max_refine, int32_t inner_steps, double* info,
+                                 int32_t* refinements, void* stream) {
+  if (check_grid(g) || check_prec(inner_prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!rho_phys || !f || !u) return fail(FBTO_ERR_ARG, "rho_phys, f and u must be non-NULL");
+  if (!(rtol > 0.0)) return fail(FBTO_ERR_ARG, "rtol must be > 0");
+  if (max_refine < 1 || inner_steps < 1) return fail(FBTO_ERR_ARG, "max_refine and inner_steps must be >= 1");
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if ((s = ensure_vecs<double>(g))) return s;
+  if (inner_prec == FBTO_F32 && (s = ensure_vecs<float>(g))) return s;
+  GridExtra* ex = extra_of(g);
+  IrBufs& B = inner_prec == FBTO_F32 ? ex->ir32 : ex->ir64;
+  const size_t es = inner_prec == FBTO_F32 ? sizeof(float) : sizeof(double);
+  const int64_t nd = g->geo.ndof * g->desc.max_rhs;
+  if (!B.f) HIP_TRY(hipMalloc(&B.f, nd * es));
+  if (!B.d) HIP_TRY(hipMalloc(&B.d, nd * es));
+  if (!B.r64) HIP_TRY(hipMalloc(&B.r64, nd * sizeof(double)));
+  const int64_t n = g->geo.ndof * nrhs;
+  float* rho32 = (float*)g->v32.rho;
+  if (inner_prec == FBTO_F32) HIP_TRY(launch_convert<float>(rho_phys, rho32, g->geo.E, 0, st));
+  int it = 0;
+  double total_inner = 0.0;
+  std::vector<double> fn(nrhs, 0.0);
+  for (;;) {
+    // FP64 residual r = f - K64 u and its norms
+    HIP_TRY(launch_apply<double>(g, rho_phys, u, B.r64, f, nrhs, 1, st));
+    HIP_TRY(launch_pcg_init<double>(g, B.r64, (double*)g->v64.p, (double*)g->v64.invD, nrhs, f, 0.0, st));
+    Scalars h;
+    HIP_TRY(hipMemcpyAsync(&h, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    bool conv = true;
+    for (int R = 0; R < nrhs; ++R) {
+      fn[R] = h.fnorm2[R];
+      if (!std::isfinite(h.rnorm2[R])) return fail(FBTO_ERR_NONFINITE, "non-finite refinement residual");
+      conv = conv && h.rnorm2[R] <= rtol * h.fnorm2[R];
+    }
+    if (conv || it >= max_refine) break;
+    ++it;
+    if (inner_prec == FBTO_F32) {
+      HIP_TRY(launch_ir_scale(g, B.r64, (float*)B.f, nrhs, st));
+      HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(float), st));
+      if ((s = pcg_run<float>(g, rho32, (const float*)B.f, (float*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      HIP_TRY(launch_ir_accum(g, u, (const float*)B.d, nrhs, st));
+    } else {
+      HIP_TRY(hipMemcpyAsync(B.f, B.r64, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+      HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(double), st));
+      if ((s = pcg_run<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      HIP_TRY(launch_axpy64(u, (const double*)B.d, n, st));
+    }
+    total_inner += inner_steps;
+  }
+  // final norms are in the scalars (from the last FP64 residual)
+  hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, g->sc, nrhs, total_inner);
+  HIP_TRY(hipGetLastError());
+  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, st));
+  if (refinements) *refinements = it;
+  return ok();
+}
+
+fbto_status_t fbto_sensitivity(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys, const void* u,
+                               const void* lam, const void* f, int32_t nrhs, void* dobj, double* obj,
+                               void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!rho_phys || !u || !dobj) return fail(FBTO_ERR_ARG, "rho_phys, u and dobj must be non-NULL");
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == FBTO_F64) {
+    HIP_TRY(launch_sens<double>(g, (const double*)rho_phys, (const double*)u, (const double*)lam, nrhs,
+                                (double*)dobj, st));
+    if (f && obj) HIP_TRY(launch_dot<double>(g, (const double*)f, (const double*)u, g->geo.ndof, nrhs, obj, st));
+  } else {
+    HIP_TRY(launch_sens<float>(g, (const float*)rho_phys, (const float*)u, (const float*)lam, nrhs,
+                               (float*)dobj, st));
+    if (f && obj) HIP_TRY(launch_dot<float>(g, (const float*)f, (const float*)u, g->geo.ndof, nrhs, obj, st));
+  }
+  return ok();
+}
+
+fbto_status_t fbto_filter(fbto_grid_t g, fbto_prec_t prec, int32_t transpose, const void* in, void* out,
+                          void* stream) {
+  if (check_grid(g) || check_prec(prec)) return FBTO_ERR_ARG;
+  if (!in || !out) return fail(FBTO_ERR_ARG, "in and out must be non-NULL");
+  if (in == out) return fail(FBTO_ERR_ARG, "in and out must not overlap");
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    HIP_TRY(launch_filter<double>(g, transpose ? 1 : 0, (const double*)in, (double*)out, 0, st));
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    HIP_TRY(launch_filter<float>(g, transpose ? 1 : 0, (const float*)in, (float*)out, 0, st));
+  }
+  return ok();
+}
+
+fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y, void* x, double lo,
+                                  double hi, double vmax, double* lambda, void* stream) {
+  if (check_grid(g) || check_prec(prec)) return FBTO_ERR_ARG;
+  if (!y || !x) return fail(FBTO_ERR_ARG, "y and x must be non-NULL");
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo <= hi)) return fail(FBTO_ERR_ARG, "need finite lo <= hi");
+  if (!std::isfinite(vmax)) return fail(FBTO_ERR_ARG, "vmax must be finite");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g: the feasible set is empty", vmax,
+                lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == FBTO_F64)
+    HIP_TRY(launch_project<double>(g, (const double*)y, (double*)x, lo, hi, vmax, 0, nullptr, lambda, nullptr, st));
+  else
+    HIP_TRY(launch_project<float>(g, (const float*)y, (float*)x, lo, hi, vmax, 0, nullptr, lambda, nullptr, st));
+  return ok();
+}
+
+fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u, const void* f,
+                              int32_t nrhs, int32_t k, double alpha0, int32_t inner_steps,
+                              int32_t mean_project, double lo, double vmax, double* info,
+                              void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!x || !u || !f) return fail(FBTO_ERR_ARG, "x, u and f must be non-NULL");
+  if (k < 1) return fail(FBTO_ERR_ARG, "k is 1-based");
+  if (inner_steps < 0) return fail(FBTO_ERR_ARG, "inner_steps must be >= 0");
+  if (!(std::isfinite(alpha0) && alpha0 >= 0.0)) return fail(FBTO_ERR_ARG, "alpha0 must be finite and >= 0");
+  if (!(std::isfinite(lo) && lo <= 1.0)) return fail(FBTO_ERR_ARG, "need lo <= 1");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g", vmax, lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    s = outer_run<double>(g, (double*)x, (double*)u, (const double*)f, nrhs, k, alpha0, inner_steps,
+                          mean_project, lo, vmax, info, st);
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, inner_steps,
+                         mean_project, lo, vmax, info, st);
+  }
+  if (s) return s;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Internal declarations shared by the kernels (kernels.hip) and the C ABI
+// layer (api.cpp).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fbto.h"
+
+namespace fbto {
+
+// Grid geometry, passed to every kernel by value.
+struct Geo {
+  int nx, ny, nz;      // elements per axis
+  int nxn, nyn, nzn;   // nodes per axis (n + 1)
+  int64_t N, E;        // nodes, elements
+  int64_t ndof;        // 3N
+};
+
+// Element stiffness in the sum/difference ("modal") basis.  Per axis the
+// two nodal values (u0, u1) map to (u0 + u1, u1 - u0); on the unit cube the
+// 24x24 KE becomes a 45-entry sparse matrix:
+//   diagonal  dg[i][q]                      (component i, mode q)
+//   coupling  component i, mode q  <-  component j, mode q ^ (1<<i) ^ (1<<j)
+//             whenever bits i and j of q differ, with weight
+//             lam4[bit k of q] if bit i of q is set, else mu4[bit k of q]
+// (k the third axis).  Mode q has bit b set when it is the difference mode
+// along axis b.  Derived from the 1D integrals of the basis {1/2, t - 1/2}.
+template <typename T>
+struct Modal {
+  T dg[3][8];
+  T lam4[2];
+  T mu4[2];
+};
+
+struct Simp {
+  double penal;
+  double rho_min;
+  int cubic;           // penal == 3 exactly: rho^3 by multiplication
+};
+
+// Device-resident scalars of one grid handle (FP64).  Indexed per RHS
+// where marked [4].
+struct Scalars {
+  double rz[4];        // r . z of the current CG iterate
+  double pq[4];
+  double alpha[4];
+  double beta[4];
+  double rnorm2[4];    // ||r||_2
+  double rinf[4];      // ||r||_inf
+  double fnorm2[4];
+  double tol[4];       // convergence threshold on ||r||_2 (0: none)
+  double steps[4];
+  double done[4];      // 1 once converged
+  double status[4];    // fbto_status_t of the RHS
+  double dot[4];       // scratch dot results
+  // projection
+  double lam;          // current multiplier / iterate
+  double lam_prev;     // last solution (warm start)
+  double br_a, br_b;   // bracket: f(a) > vmax >= f(b)
+  double proj_done;
+  double proj_status;
+  double sum0;         // sum clamp(y)
+  double ymax, ymin;
+  double gsum;         // sum of the filtered gradient
+  double gmean;
+  double work[8];
+};
+
+enum CounterSlot {
+  CNT_APPLY = 0, CNT_INIT, CNT_UPDATE, CNT_DOT, CNT_PROJ, CNT_PROJF, CNT_FILT,
+  CNT_STEP, CNT_MISC, CNT_COUNT
+};
+
+// Workspace vectors of one precision.
+struct Vecs {
+  void* r = nullptr;      // [max_rhs][3N]
+  void* p = nullptr;
+  void* q = nullptr;
+  void* invD = nullptr;   // [3N]
+  void* rho = nullptr;    // [E]  filtered density
+  void* ge = nullptr;     // [E]  element gradient
+  void* gx = nullptr;     // [E]  design gradient
+  void* y = nullptr;      // [E]  step / projection input
+  void* Hs = nullptr;     // [E]  filter normalisation
+  bool ready = false;
+};
+
+struct StencilPt {
+  int dx, dy, dz;
+  double w;
+};
+
+}  // namespace fbto
+
+struct fbto_grid_s {
+  fbto_grid_desc_t desc;
+  fbto::Geo geo;
+  fbto::Modal<double> km64;
+  fbto::Modal<float> km32;
+  fbto::Simp simp;
+  double ke_diag;            // every diagonal entry of KE: (lambda + 4 mu) / 9
+  uint8_t* mask = nullptr;   // [N] bit c: DOF c of the node fixed
+  int n_springs = 0;
+  int64_t* spring_dof = nullptr;
+  double* spring_k64 = nullptr;
+  float* spring_k32 = nullptr;
+  int n_stencil = 0;
+  int* stencil_off = nullptr;      // [n_stencil][3]
+  double* stencil_w64 = nullptr;
+  float* stencil_w32 = nullptr;
+  fbto::Scalars* sc = nullptr;     // device
+  unsigned* counters = nullptr;    // device [CNT_COUNT]
+  double* partials = nullptr;      // device [max_partials * 8]
+  int max_partials = 0;
+  fbto::Vecs v64, v32;
+  int device = 0;
+  int n_cu = 256;
+};
+
+namespace fbto {
+
+// ---- launchers (kernels.hip) ----------------------------------------------
+// All return hipSuccess or the launch error; none synchronises.
+template <typename T>
+hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, const T* f,
+                        int nrhs, int mode, hipStream_t st);
+template <typename T>
+hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_init(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs,
+                           const T* f, double rtol, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_update(fbto_grid_s* g, T* u, T* r, const T* p, const T* q,
+                             const T* invD, int nrhs, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_pupdate(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_relax_update(fbto_grid_s* g, T* u, const T* r, const T* invD, int nrhs,
+                               double omega, int use_diag, hipStream_t st);
+template <typename T>
+hipError_t launch_norms(fbto_grid_s* g, const T* r, int nrhs, hipStream_t st);
+template <typename T>
+hipError_t launch_sens(fbto_grid_s* g, const T* rho, const T* u, const T* lam, int nrhs,
+                       T* dobj, hipStream_t st);
+template <typename T>
+hipError_t launch_dot(fbto_grid_s* g, const T* a, const T* b, int64_t n, int nrhs,
+                      double* out, hipStream_t st);
+template <typename T>
+hipError_t launch_filter(fbto_grid_s* g, int transpose, const T* in, T* out, int want_sum,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_step_v(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
+                         int mean_project, double lo, double hi, double vmax, hipStream_t st);
+template <typename T>
+hipError_t launch_hs(fbto_grid_s* g, T* Hs, hipStream_t st);
+int apply_max_blocks(const Geo& G, int n_cu);
+template <typename T>
+hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi,
+                          double vmax, int have_sum, const T* x_old, double* lam_out,
+                          double* info, hipStream_t st);
+template <typename T>
+hipError_t launch_convert(const void* in, void* out, int64_t n, int to_double, hipStream_t st);
+hipError_t launch_axpy64(double* u, const double* d, int64_t n, hipStream_t st);
+hipError_t launch_ir_scale(fbto_grid_s* g, const double* r64, float* r32, int nrhs,
+                           hipStream_t st);
+hipError_t launch_ir_accum(fbto_grid_s* g, double* u64, const float* d32, int nrhs,
+                           hipStream_t st);
+hipError_t launch_outer_info(fbto_grid_s* g, double* info, int nrhs, hipStream_t st);
+hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, hipStream_t st);
+hipError_t launch_scalar_reset(fbto_grid_s* g, int nrhs, hipStream_t st);
+
+}  // namespace fbto

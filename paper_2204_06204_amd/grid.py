@@ -1,0 +1,187 @@
+"""Python binding of the C ABI (include/fbto.h): one method per entry point,
+same names, argument marshalling only.  Tensors are torch tensors on the HIP
+device; torch supplies device memory and the current stream, every step of
+the computation runs in libfbto.so.
+
+Precision follows the tensors' dtype: float64 -> FBTO_F64, float32 -> FBTO_F32.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import FbtoError, check
+
+
+def _prec(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return _lib.FBTO_F64
+    if t.dtype == torch.float32:
+        return _lib.FBTO_F32
+    raise TypeError(f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=None, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected {dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} entries, expected {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Grid:
+    """A structured hex8 voxel grid with supports and springs (fbto_setup_grid)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, *, fixed_mask: Optional[np.ndarray] = None,
+                 springs: Sequence[Tuple[int, float]] = (), young: float = 1.0,
+                 poisson: float = 0.3, penal: float = 3.0, rho_min: float = 1e-3,
+                 filter_radius: float = 1.5, max_rhs: int = 1):
+        self.lib = _lib.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.E = self.nx * self.ny * self.nz
+        self.N = (self.nx + 1) * (self.ny + 1) * (self.nz + 1)
+        self.ndof = 3 * self.N
+        self.max_rhs = int(max_rhs)
+        desc = _lib.GridDesc(self.nx, self.ny, self.nz, self.max_rhs, young, poisson, penal,
+                             rho_min, filter_radius)
+        mask_p = None
+        if fixed_mask is not None:
+            m = np.ascontiguousarray(np.asarray(fixed_mask, dtype=np.uint8))
+            if m.size != self.ndof:
+                raise ValueError("fixed_mask must have 3N entries")
+            self._mask = m
+            mask_p = m.ctypes.data_as(C.c_void_p)
+        dof = np.ascontiguousarray([s[0] for s in springs], dtype=np.int64)
+        kk = np.ascontiguousarray([s[1] for s in springs], dtype=np.float64)
+        self._springs = (dof, kk)
+        h = C.c_void_p()
+        check(self.lib.fbto_setup_grid(C.byref(desc), mask_p, len(dof),
+                                       dof.ctypes.data_as(C.c_void_p) if len(dof) else None,
+                                       kk.ctypes.data_as(C.c_void_p) if len(dof) else None,
+                                       C.byref(h)), self.lib)
+        self.handle = h
+
+    @classmethod
+    def from_problem(cls, p, max_rhs: Optional[int] = None) -> "Grid":
+        return cls(p.nx, p.ny, p.nz, fixed_mask=p.fixed_mask, springs=p.springs, young=p.young,
+                   poisson=p.poisson, penal=p.penal, rho_min=p.rho_min,
+                   filter_radius=p.filter_radius, max_rhs=max_rhs or p.nrhs)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fbto_destroy_grid(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def grid_sizes(self):
+        e, n, d = C.c_int64(), C.c_int64(), C.c_int64()
+        check(self.lib.fbto_grid_sizes(self.handle, C.byref(e), C.byref(n), C.byref(d)), self.lib)
+        return e.value, n.value, d.value
+
+    # ------------------------------------------------------------------
+    def _nrhs(self, v: torch.Tensor) -> int:
+        if v.numel() % self.ndof:
+            raise ValueError("vector length must be a multiple of 3N")
+        return v.numel() // self.ndof
+
+    def apply_K(self, rho: torch.Tensor, u: torch.Tensor, y: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty_like(u)
+        nr = self._nrhs(u)
+        check(self.lib.fbto_apply_K(self.handle, _prec(u), _ptr(rho, u.dtype, self.E, "rho"),
+                                    _ptr(u, name="u"), _ptr(y, u.dtype, u.numel(), "y"), nr,
+                                    _stream(stream)), self.lib)
+        return y
+
+    def inner_solve(self, rho, f, u, steps: int, method: str = "pcg", omega: float = 0.0,
+                    rtol: float = 0.0, info: Optional[torch.Tensor] = None, stream=None):
+        meth = {"pcg": _lib.FBTO_PCG_JACOBI, "richardson": _lib.FBTO_RICHARDSON,
+                "jacobi": _lib.FBTO_DAMPED_JACOBI}[method]
+        nr = self._nrhs(u)
+        check(self.lib.fbto_inner_solve(self.handle, _prec(u), _ptr(rho, u.dtype, self.E, "rho"),
+                                        _ptr(f, u.dtype, u.numel(), "f"), _ptr(u, name="u"), nr,
+                                        meth, int(steps), float(omega), float(rtol),
+                                        _ptr(info, torch.float64, None, "info"), _stream(stream)),
+              self.lib)
+        return u
+
+    def solve_refined(self, rho64, f64, u64, rtol: float, max_refine: int, inner_steps: int,
+                      inner_dtype=torch.float32, info: Optional[torch.Tensor] = None, stream=None):
+        prec = _lib.FBTO_F32 if inner_dtype == torch.float32 else _lib.FBTO_F64
+        nr = self._nrhs(u64)
+        nref = C.c_int32(0)
+        check(self.lib.fbto_solve_refined(self.handle, prec, _ptr(rho64, torch.float64, self.E, "rho"),
+                                          _ptr(f64, torch.float64, u64.numel(), "f"),
+                                          _ptr(u64, torch.float64, None, "u"), nr, float(rtol),
+                                          int(max_refine), int(inner_steps),
+                                          _ptr(info, torch.float64, None, "info"), C.byref(nref),
+                                          _stream(stream)), self.lib)
+        return nref.value
+
+    def sensitivity(self, rho, u, lam=None, f=None, dobj=None, obj=None, stream=None):
+        if dobj is None:
+            dobj = torch.empty(self.E, dtype=u.dtype, device=u.device)
+        nr = self._nrhs(u)
+        check(self.lib.fbto_sensitivity(self.handle, _prec(u), _ptr(rho, u.dtype, self.E, "rho"),
+                                        _ptr(u, name="u"), _ptr(lam, u.dtype, u.numel(), "lam"),
+                                        _ptr(f, u.dtype, u.numel(), "f"), nr,
+                                        _ptr(dobj, u.dtype, self.E, "dobj"),
+                                        _ptr(obj, torch.float64, None, "obj"), _stream(stream)),
+              self.lib)
+        return dobj
+
+    def filter(self, x, out=None, transpose: bool = False, stream=None):
+        if out is None:
+            out = torch.empty_like(x)
+        check(self.lib.fbto_filter(self.handle, _prec(x), 1 if transpose else 0,
+                                   _ptr(x, None, self.E, "in"), _ptr(out, x.dtype, self.E, "out"),
+                                   _stream(stream)), self.lib)
+        return out
+
+    def project_volume(self, y, x=None, lo: float = 0.0, hi: float = 1.0, vmax: float = None,
+                       lam: Optional[torch.Tensor] = None, stream=None):
+        if x is None:
+            x = torch.empty_like(y)
+        check(self.lib.fbto_project_volume(self.handle, _prec(y), _ptr(y, None, self.E, "y"),
+                                           _ptr(x, y.dtype, self.E, "x"), float(lo), float(hi),
+                                           float(vmax), _ptr(lam, torch.float64, None, "lambda"),
+                                           _stream(stream)), self.lib)
+        return x
+
+    def outer_step(self, x, u, f, k: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
+                   mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None):
+        nr = self._nrhs(u)
+        check(self.lib.fbto_outer_step(self.handle, _prec(x), _ptr(x, None, self.E, "x"),
+                                       _ptr(u, x.dtype, None, "u"), _ptr(f, x.dtype, u.numel(), "f"),
+                                       nr, int(k), float(alpha0), int(inner_steps),
+                                       1 if mean_project else 0, float(lo), float(vmax),
+                                       _ptr(info, torch.float64, None, "info"), _stream(stream)),
+              self.lib)
+        return x
+
+
+__all__ = ["Grid", "FbtoError"]

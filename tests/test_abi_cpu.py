@@ -1,0 +1,72 @@
+"""CPU-side checks of the C ABI: the library loads without a GPU, exports
+every function include/fbto.h declares, and rejects invalid arguments on
+the host before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fbto.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fbto_[A-Za-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2204_06204_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2204_06204_amd.build import build
+        build()
+    return _lib.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("fbto_setup_grid", "fbto_apply_K", "fbto_inner_solve", "fbto_sensitivity",
+              "fbto_filter", "fbto_project_volume", "fbto_outer_step", "fbto_solve_refined",
+              "fbto_destroy_grid", "fbto_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2204_06204_amd import _lib
+    names = declared_functions()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(_lib.EXPORTED)
+
+
+def test_host_side_argument_errors(lib):
+    from paper_2204_06204_amd import _lib
+    h = C.c_void_p()
+    bad = [
+        _lib.GridDesc(0, 4, 4, 1, 1.0, 0.3, 3.0, 1e-3, 1.5),      # empty axis
+        _lib.GridDesc(4, 4, 4, 5, 1.0, 0.3, 3.0, 1e-3, 1.5),      # max_rhs
+        _lib.GridDesc(4, 4, 4, 1, -1.0, 0.3, 3.0, 1e-3, 1.5),     # young
+        _lib.GridDesc(4, 4, 4, 1, 1.0, 0.5, 3.0, 1e-3, 1.5),      # poisson
+        _lib.GridDesc(4, 4, 4, 1, 1.0, 0.3, 0.5, 1e-3, 1.5),      # penal
+        _lib.GridDesc(4, 4, 4, 1, 1.0, 0.3, 3.0, 1.0, 1.5),       # rho_min
+        _lib.GridDesc(4, 4, 4, 1, 1.0, 0.3, 3.0, 1e-3, -2.0),     # radius
+    ]
+    for d in bad:
+        assert lib.fbto_setup_grid(C.byref(d), None, 0, None, None, C.byref(h)) == _lib.FBTO_ERR_ARG
+        assert lib.fbto_last_error().decode() != ""
+        assert not h.value
+    d = _lib.GridDesc(4, 4, 4, 1, 1.0, 0.3, 3.0, 1e-3, 1.5)
+    assert lib.fbto_setup_grid(C.byref(d), None, 2, None, None, C.byref(h)) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_setup_grid(None, None, 0, None, None, C.byref(h)) == _lib.FBTO_ERR_ARG
+    # spring DOF out of range
+    dof = (C.c_int64 * 1)(10 ** 9)
+    kk = (C.c_double * 1)(0.1)
+    assert lib.fbto_setup_grid(C.byref(d), None, 1, dof, kk, C.byref(h)) == _lib.FBTO_ERR_ARG
+    # calls on a NULL handle
+    assert lib.fbto_apply_K(None, 0, None, None, None, 1, None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_outer_step(None, 0, None, None, None, 1, 1, 0.1, 1, 1, 0.0, 1.0, None, None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume(None, 0, None, None, 0.0, 1.0, 1.0, None, None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_version().decode().startswith("fbto")

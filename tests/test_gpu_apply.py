@@ -1,0 +1,145 @@
+"""GPU parity of fbto_apply_K against the CPU oracle.
+
+Small grids (several tiles in x and y, ragged tails) are compared element
+by element; the workload grids (128x64x64, 256x128x128, 384x192x192) on
+sampled nodes, each row recomputed by the oracle from its incident
+elements.  Tolerance: |y - y_ref|_i <= c eps_T (|K| |u|)_i, the rounding
+bound of a sum of products (c = 256 covers the sum/difference transforms
+and the FP32 storage of s_e), plus the norm-wise bound of the acceptance
+criterion: ||y - y_ref||_inf <= 1e-13 (FP64) / 1e-6 (FP32) ||y_ref||_inf.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle.grid import Grid as OGrid
+from gpu_util import DEV, EPS, abs_scale, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+NORM_TOL = {torch.float64: 1e-13, torch.float32: 1e-6}
+
+
+def _grid(p, max_rhs=1):
+    from paper_2204_06204_amd.grid import Grid
+    return Grid.from_problem(p, max_rhs=max_rhs)
+
+
+def _case(nx, ny, nz, seed, mask_frac=0.05, springs=True):
+    p = synth.cantilever(nx, ny, nz, volfrac=0.3, filter_radius=1.5, outer_iters=1,
+                         inner_steps=1, seed=seed)
+    extra = synth.random_mask(p.ndof, mask_frac, seed=seed + 100)
+    p.fixed_mask = np.maximum(p.fixed_mask, extra).astype(np.uint8)
+    if springs:
+        free = np.flatnonzero(p.fixed_mask == 0)
+        rng = np.random.default_rng(seed)
+        p.springs = tuple((int(d), float(k)) for d, k in
+                          zip(rng.choice(free, 3, replace=False), (0.1, 0.5, 2.0)))
+    return p
+
+
+SMALL = [(24, 13, 11, 5), (37, 9, 6, 6), (3, 2, 2, 7), (1, 1, 1, 8), (16, 31, 4, 9), (66, 4, 3, 10)]
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("nx,ny,nz,seed", SMALL)
+def test_apply_small_elementwise(nx, ny, nz, seed, dtype):
+    say(f"apply small {nx}x{ny}x{nz} {dtype}")
+    p = _case(nx, ny, nz, seed)
+    og = OGrid(nx, ny, nz)
+    rho = synth.uniform_density(p.E, seed, 0.0, 1.0)
+    u = synth.normal_vector(p.ndof, seed + 1)[0]
+    rho_t = dev(rho, dtype)
+    rho_used = host(rho_t)                         # densities as the GPU sees them
+    s = oracle.simp_scale(rho_used, p.penal, p.rho_min)
+    u_t = dev(u, dtype)
+    u_used = host(u_t)
+    ref = oracle.apply_K(og, s, u_used, p.fixed_mask, p.springs)
+    scale = abs_scale(og, s, u_used, p.fixed_mask, p.springs)
+    g = _grid(p)
+    y = host(g.apply_K(rho_t, u_t))
+    err = np.abs(y - ref)
+    assert np.all(err <= 256 * EPS[dtype] * scale + 1e-300), float((err / (scale + 1e-300)).max())
+    assert err.max() <= NORM_TOL[dtype] * np.abs(ref).max()
+    fixed = np.flatnonzero(p.fixed_mask)
+    assert np.array_equal(y[fixed], u_used[fixed])     # identity rows, exactly
+
+
+@pytest.mark.parametrize("dtype,nrhs", [(torch.float32, 2), (torch.float32, 3), (torch.float32, 4),
+                                        (torch.float64, 2), (torch.float64, 4)])
+def test_apply_multi_rhs_equals_single(dtype, nrhs):
+    say(f"apply multi-rhs {dtype} nrhs={nrhs}")
+    p = _case(20, 11, 7, 21)
+    g = _grid(p, max_rhs=4)
+    rho_t = dev(synth.uniform_density(p.E, 3), dtype)
+    U = dev(synth.normal_vector(p.ndof, 4, nrhs=nrhs), dtype)
+    Y = g.apply_K(rho_t, U.reshape(-1)).reshape(nrhs, -1)
+    for r in range(nrhs):
+        yr = g.apply_K(rho_t, U[r].contiguous())
+        assert torch.equal(Y[r], yr)
+
+
+def test_apply_deterministic_and_linear():
+    p = _case(30, 17, 9, 31)
+    g = _grid(p)
+    rho_t = dev(synth.uniform_density(p.E, 5), torch.float64)
+    u = dev(synth.normal_vector(p.ndof, 6)[0])
+    y1 = g.apply_K(rho_t, u)
+    y2 = g.apply_K(rho_t, u)
+    assert torch.equal(y1, y2)
+    # symmetry <K u, w> = <u, K w>
+    w = dev(synth.normal_vector(p.ndof, 7)[0])
+    a = float(torch.dot(y1, w))
+    b = float(torch.dot(u, g.apply_K(rho_t, w)))
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def _sample_nodes(nx, ny, nz, count, seed):
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (nx, ny, nz), (nx, 0, 0), (0, ny, nz), (nx // 2, ny // 2, nz // 2),
+           (nx, ny // 2, 0), (1, ny - 1, nz), (nx - 1, 1, 1)]
+    pts += [tuple(int(v) for v in (rng.integers(0, nx + 1), rng.integers(0, ny + 1), rng.integers(0, nz + 1)))
+            for _ in range(count)]
+    return [synth.node_id(i, j, k, nx, ny) for i, j, k in pts]
+
+
+@pytest.mark.parametrize("name,dtype", [("cfg3", torch.float32), ("cfg3", torch.float64),
+                                        ("cfg3_inverter", torch.float32),
+                                        ("cfg4", torch.float32), ("cfg5", torch.float32)])
+def test_apply_workload_sizes_sampled(name, dtype):
+    say(f"apply workload {name} {dtype}")
+    p = synth.config(name)
+    og = OGrid(p.nx, p.ny, p.nz)
+    g = _grid(p, max_rhs=1)
+    rho_t = dev(p.x0 if name != "cfg5" else synth.uniform_density(p.E, 0), dtype)
+    u_np = np.random.default_rng(1).standard_normal(p.ndof).astype(np.float32 if dtype == torch.float32 else np.float64)
+    u_t = torch.from_numpy(u_np).to(DEV)
+    y = g.apply_K(rho_t, u_t)
+    torch.cuda.synchronize()
+    nodes = _sample_nodes(p.nx, p.ny, p.nz, 120, 11)
+    idx = torch.tensor([3 * n + c for n in nodes for c in range(3)], device=DEV)
+    ys = y[idx].double().cpu().numpy().reshape(-1, 3)
+    rho_used = rho_t.double().cpu().numpy()
+    s = oracle.simp_scale(rho_used, p.penal, p.rho_min)
+    u_used = u_np.astype(np.float64)
+    ref = oracle.apply_K_rows(og, s, u_used, nodes, p.fixed_mask, p.springs)
+    KEa = np.abs(oracle.element_stiffness())
+    scale = oracle.apply_K_rows(og, s, np.abs(u_used), nodes, p.fixed_mask,
+                                tuple((d, abs(k)) for d, k in p.springs), KE=KEa)
+    err = np.abs(ys - ref)
+    assert np.all(err <= 256 * EPS[dtype] * scale + 1e-300), float((err / (scale + 1e-300)).max())
+
+
+def test_apply_argument_errors():
+    from paper_2204_06204_amd import FbtoError
+    p = _case(4, 3, 2, 41)
+    g = _grid(p, max_rhs=1)
+    rho_t = dev(synth.uniform_density(p.E, 1), torch.float32)
+    u = dev(np.zeros(2 * p.ndof), torch.float32)
+    with pytest.raises(FbtoError):
+        g.apply_K(rho_t, u)                       # nrhs 2 > max_rhs 1
+    with pytest.raises(TypeError):
+        g.apply_K(rho_t, u[: p.ndof].double())    # dtype mismatch (binding check)

@@ -1,0 +1,165 @@
+"""GPU parity of the design-side kernels: sensitivity (compliance and
+adjoint), density filter and its transpose, projection onto the volume box
+(against Alg. 4), and whole outer iterations against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle.grid import Grid as OGrid
+from oracle.outer import OuterContext, outer_step_ref, run_outer_ref
+from gpu_util import DEV, EPS, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _grid(p, max_rhs=1):
+    from paper_2204_06204_amd.grid import Grid
+    return Grid.from_problem(p, max_rhs=max_rhs)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("nrhs,adjoint", [(1, False), (1, True), (3, False), (2, True)])
+def test_sensitivity(dtype, nrhs, adjoint):
+    say(f"sensitivity {dtype} nrhs={nrhs} adjoint={adjoint}")
+    p = synth.cantilever(13, 7, 5, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=1, seed=4)
+    p.fixed_mask = np.maximum(p.fixed_mask, synth.random_mask(p.ndof, 0.05, 9)).astype(np.uint8)
+    og = OGrid(p.nx, p.ny, p.nz)
+    g = _grid(p, max_rhs=4)
+    rho_t = dev(synth.uniform_density(p.E, 2, 0.05, 1.0), dtype)
+    U_t = dev(synth.normal_vector(p.ndof, 3, nrhs).ravel(), dtype)
+    L_t = dev(synth.normal_vector(p.ndof, 5, nrhs).ravel(), dtype) if adjoint else None
+    F_t = dev(synth.normal_vector(p.ndof, 6, nrhs).ravel(), dtype)
+    obj = torch.zeros(1, dtype=torch.float64, device=DEV)
+    d = host(g.sensitivity(rho_t, U_t, lam=L_t, f=F_t, obj=obj))
+    rho, U, F = host(rho_t), host(U_t).reshape(nrhs, -1), host(F_t).reshape(nrhs, -1)
+    if adjoint:
+        ref = oracle.adjoint_gradient(og, rho, U, host(L_t).reshape(nrhs, -1), p.fixed_mask, p.penal, p.rho_min)
+    else:
+        ref = oracle.compliance_gradient(og, rho, U, p.fixed_mask, p.penal, p.rho_min)
+    tol = 1e-12 if dtype == torch.float64 else 2e-5
+    # error scale: ds_e * sum |KE| |u_e| |lam_e|
+    assert np.abs(d - ref).max() <= tol * np.abs(ref).max()
+    assert abs(float(obj[0]) - float((F * U).sum())) <= 1e-12 * np.abs(F * U).sum()
+
+
+@pytest.mark.parametrize("r", [1.0, 1.5, 2.0, 3.0])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_filter(r, dtype):
+    say(f"filter r={r} {dtype}")
+    og = OGrid(19, 8, 7)
+    p = synth.cantilever(19, 8, 7, volfrac=0.3, filter_radius=r, outer_iters=1, inner_steps=1, seed=1)
+    g = _grid(p)
+    H, Hs = oracle.cone_filter_matrix(og, r) if r > 1.0 else (None, None)
+    x_t = dev(synth.uniform_density(p.E, 7, 0.0, 1.0), dtype)
+    x = host(x_t)
+    fw = host(g.filter(x_t))
+    tr = host(g.filter(x_t, transpose=True))
+    if r <= 1.0:
+        assert np.array_equal(fw, x) and np.array_equal(tr, x)
+        return
+    tol = 1e-14 if dtype == torch.float64 else 1e-6
+    assert np.abs(fw - oracle.filter_forward(H, Hs, x)).max() <= tol
+    assert np.abs(tr - oracle.filter_transpose(H, Hs, x)).max() <= tol * 2
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("E_shape,vf,seed", [((17, 9, 5), 0.3, 1), ((128, 64, 64), 0.25, 2),
+                                             ((6, 1, 1), 0.5, 3), ((40, 20, 10), 0.01, 4)])
+def test_projection_against_alg4(dtype, E_shape, vf, seed):
+    say(f"projection {E_shape} {dtype}")
+    nx, ny, nz = E_shape
+    p = synth.cantilever(nx, ny, nz, volfrac=vf, filter_radius=1.0, outer_iters=1, inner_steps=1)
+    g = _grid(p)
+    rng = np.random.default_rng(seed)
+    y = rng.uniform(-0.4, 1.4, p.E)
+    if seed == 3:
+        y[:3] = 0.7                                  # ties
+    y_t = dev(y, dtype)
+    yd = host(y_t)
+    lam = torch.zeros(1, dtype=torch.float64, device=DEV)
+    for lo in (0.0, 0.1):
+        if p.vmax < lo * p.E:
+            continue
+        x = host(g.project_volume(y_t, lo=lo, hi=1.0, vmax=p.vmax, lam=lam))
+        xr, lr = oracle.project_alg4(yd, lo, 1.0, p.vmax, return_lambda=True)
+        xtol = 1e-12 if dtype == torch.float64 else 2 * EPS[torch.float32]
+        assert np.abs(x - xr).max() <= xtol, (lo, np.abs(x - xr).max())
+        assert abs(float(lam[0]) - lr) <= 1e-10 * max(1.0, abs(lr))
+        if lr > 0:
+            assert abs(x.sum() - p.vmax) <= 1e-9 * p.vmax + p.E * xtol
+
+
+def test_projection_inactive_and_infeasible():
+    from paper_2204_06204_amd import FbtoError
+    p = synth.cantilever(8, 4, 4, volfrac=0.9, filter_radius=1.0, outer_iters=1, inner_steps=1)
+    g = _grid(p)
+    y = dev(np.random.default_rng(0).uniform(0, 1.2, p.E))
+    lam = torch.full((1,), -1.0, dtype=torch.float64, device=DEV)
+    x = host(g.project_volume(y, lo=0.0, hi=1.0, vmax=0.9 * p.E, lam=lam))
+    assert np.array_equal(x, np.clip(host(y), 0.0, 1.0)) and float(lam[0]) == 0.0
+    with pytest.raises(FbtoError):
+        g.project_volume(y, lo=0.5, hi=1.0, vmax=0.1 * p.E)
+
+
+def _run_gpu(p, iters, alpha0, dtype, g=None):
+    g = g or _grid(p)
+    x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
+    u = torch.zeros(p.nrhs * p.ndof, dtype=dtype, device=DEV)
+    f = dev(p.loads.ravel(), dtype)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    recs, xs = [], []
+    for k in range(1, iters + 1):
+        g.outer_step(x, u, f, k, alpha0, p.inner_steps, 0.0, p.vmax, info=info)
+        recs.append(host(info).copy())
+        xs.append(host(x).copy())
+    return recs, xs, host(u)
+
+
+def test_outer_trajectory_cfg1_fp64():
+    """16x8x8 cantilever, 50 outer iterations x 5 PCG steps in FP64 against
+    the oracle: compliance and design agree to 1e-9 relative."""
+    say("outer cfg1 fp64")
+    p = synth.config("cfg1")
+    alpha0 = 0.0016874513029055756
+    recs, xs, _ = _run_gpu(p, 50, alpha0, torch.float64)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 50, alpha0, p.inner_steps, 0.0, 1.0, p.vmax)
+    for k in range(50):
+        c, cr = recs[k][0], rrecs[k].compliance
+        assert abs(c - cr) <= 1e-9 * abs(cr), (k, c, cr)
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= 1e-9, (k, np.abs(xs[k] - rxs[k + 1]).max())
+        assert abs(recs[k][4] - rrecs[k].volume) <= 1e-9 * p.vmax
+        assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-7 * max(1e-12, rrecs[k].r_inf) + 1e-14
+        assert recs[k][4] <= p.vmax * (1 + 1e-12)
+
+
+def test_outer_fp32_tracks_fp64_small():
+    """FP32 storage with FP64 reductions against the FP64 oracle: reported
+    deviation over 20 iterations on a 32x16x16 cantilever (gate 1e-3)."""
+    p = synth.cantilever(32, 16, 16, volfrac=0.25, filter_radius=2.0, outer_iters=20, inner_steps=8, seed=0)
+    alpha0 = 0.0017
+    recs, xs, _ = _run_gpu(p, 20, alpha0, torch.float32)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 20, alpha0, p.inner_steps, 0.0, 1.0, p.vmax)
+    dc = max(abs(recs[k][0] - rrecs[k].compliance) / rrecs[k].compliance for k in range(20))
+    dx = max(np.abs(xs[k] - rxs[k + 1]).max() for k in range(20))
+    say(f"fp32 vs fp64 oracle over 20 its: max rel dc={dc:.3e} max dx={dx:.3e}")
+    assert dc <= 1e-3 and dx <= 1e-3
+
+
+def test_outer_multiload_and_springs():
+    """Multi-load (summed compliance) and a spring-loaded inverter grid: one
+    FP64 outer iteration against the oracle."""
+    for p in (synth.multiload_cantilever(12, 6, 6, seed=2),
+              synth.inverter(24, 8, 8, seed=1)):
+        say(f"outer one step {p.name}")
+        g = _grid(p, max_rhs=p.nrhs)
+        recs, xs, u = _run_gpu(p, 2, 1e-3, torch.float64, g)
+        ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+        xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 2, 1e-3, p.inner_steps, 0.0, 1.0, p.vmax)
+        for k in range(2):
+            assert abs(recs[k][0] - rrecs[k].compliance) <= 1e-9 * abs(rrecs[k].compliance)
+            assert np.abs(xs[k] - rxs[k + 1]).max() <= 1e-9
+        assert np.abs(u.reshape(p.nrhs, -1) - ur).max() <= 1e-9 * np.abs(ur).max()
