@@ -1,0 +1,274 @@
+"""Benchmark of the matrix-free SIMP hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one outer iteration of the first-order bilevel method on the
+128x64x64 hex8 cantilever (524,288 elements, 1,635,075 DOFs): density
+filter, SIMP scaling and Jacobi diagonal, 8 warm-started Jacobi-PCG steps
+(each one K(rho) p product), sensitivity u_e^T KE u_e, filter transpose,
+mean-projected gradient step and FP64 projection onto the volume box.
+Inputs are seeded synthetic data resident in HBM before timing starts.
+Prints ONE JSON line (rank 0).  The value is outer iterations per second
+of the FP32 path (FP32 storage and arithmetic, FP64 reductions); the same
+line carries the FP64 path, the K(rho)u rate in GDOF/s with its roofline
+fraction, the time to a fixed residual (FP32 + FP64 refinement vs FP64),
+and the CPU oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "K(ρ)u GDOF/s + TO outer iters/s, 128x64x64 hex, mixed vs FP64 at fixed err"
+HBM_PEAK_GBS = 8000.0
+ALPHA0_CFG3 = 0.0016591384929631413      # tests/golden/alpha0.json (oracle-generated)
+KERNEL_SOURCES = ("paper_2204_06204_amd/csrc/kernels.hip", "paper_2204_06204_amd/csrc/device.h")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, s), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per apply launch from the committed rocprofv3 PMC summary,
+    if it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "apply_K_pmc.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return d.get(workload_key, {}).get("hbm_bytes_per_launch")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--apply-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fixed-err", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--profile-only", choices=["apply", "outer"], default=None,
+                    help="run only a short loop of one kind (for rocprofv3)")
+    return ap.parse_args()
+
+
+def outer_loop(g, p, dtype, steps, warmup, torch):
+    """Times `steps` outer iterations after `warmup` untimed ones."""
+    dev = torch.device("cuda:0")
+    x = g.project_volume(torch.tensor(p.x0, dtype=dtype, device=dev), lo=0.0, hi=1.0, vmax=p.vmax)
+    u = torch.zeros(p.ndof, dtype=dtype, device=dev)
+    f = torch.tensor(p.loads[0], dtype=dtype, device=dev)
+    info = torch.zeros(8, dtype=torch.float64, device=dev)
+    k = 1
+    for _ in range(warmup):
+        g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+        k += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+        k += 1
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    inf = info.cpu().tolist()
+    return dt, {"compliance": inf[0], "dx_inf": inf[1], "r_inf": inf[2], "lambda": inf[3],
+                "volume": inf[4], "status": inf[6], "k_last": k - 1}
+
+
+def apply_timing(g, p, dtype, reps, torch, cold=False):
+    """Average duration of one fbto_apply_K launch, from HIP events recorded
+    on the stream the kernel runs on (the current torch stream)."""
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(p.x0, dtype=dtype, device=dev)
+    u = torch.randn(p.ndof, dtype=dtype, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    y = torch.empty_like(u)
+    st = torch.cuda.current_stream()
+    for _ in range(10):
+        g.apply_K(rho, u, y)
+    if not cold:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            g.apply_K(rho, u, y)
+        e1.record(st)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+    # cold: overwrite a 1 GiB buffer (4x the 256 MB Infinity Cache) between launches
+    scratch = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    tot = 0.0
+    n = max(10, reps // 10)
+    for _ in range(n):
+        scratch.fill_(1.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        g.apply_K(rho, u, y)
+        e1.record(st)
+        torch.cuda.synchronize()
+        tot += e0.elapsed_time(e1) * 1e-3
+    return tot / n
+
+
+def fixed_error(g, p, torch, rtol=1e-8):
+    """Time to ||f - K u|| <= rtol ||f|| from u = 0 at the seeded density:
+    FP64 Jacobi-PCG vs FP32 Jacobi-PCG with FP64 iterative refinement."""
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(p.x0, dtype=torch.float64, device=dev)
+    f = torch.tensor(p.loads[0], dtype=torch.float64, device=dev)
+    out = {}
+    info = torch.zeros(8, dtype=torch.float64, device=dev)
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.inner_solve(rho, f, u, 200000, rtol=rtol, info=info)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    i64 = info.cpu().tolist()
+    c64 = float(torch.dot(f, u))
+    u2 = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nref = g.solve_refined(rho, f, u2, rtol, 1000, 400, inner_dtype=torch.float32, info=info)
+    torch.cuda.synchronize()
+    tmix = time.perf_counter() - t0
+    imix = info.cpu().tolist()
+    cmix = float(torch.dot(f, u2))
+    out["rtol"] = rtol
+    out["fp64_pcg"] = {"seconds": t64, "pcg_steps": i64[3], "rel_residual": i64[0] / i64[2]}
+    out["fp32_pcg_fp64_refine"] = {"seconds": tmix, "inner_steps": imix[3], "refinements": nref,
+                                   "rel_residual": imix[0] / imix[2],
+                                   "compliance_rel_diff_vs_fp64": abs(cmix - c64) / abs(c64)}
+    out["speedup_mixed_vs_fp64"] = t64 / tmix if tmix > 0 else None
+    return out
+
+
+def cpu_baseline(p, seconds):
+    """The CPU FP64 oracle (as it stands) running outer iterations of the same
+    workload on the host cores for about `seconds`."""
+    import numpy as np
+    import threadpoolctl
+    import oracle
+    from oracle.outer import OuterContext, outer_step_ref
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs, use_csr=False)
+    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    u = np.zeros_like(p.loads)
+    n, k = 0, 1
+    t0 = time.perf_counter()
+    while True:
+        x, u, rec, _ = outer_step_ref(ctx, x, u, p.loads, k, ALPHA0_CFG3, p.inner_steps, 0.0, 1.0, p.vmax)
+        n += 1
+        k += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    blas = max((d.get("num_threads", 1) for d in threadpoolctl.threadpool_info()), default=1)
+    return {"value": n / dt, "unit": "outer_iter/s", "cores": int(blas), "kind": "oracle",
+            "sample": f"{n} outer iteration(s) of the 128x64x64 workload from the projected seeded "
+                      f"density (NumPy/SciPy FP64 element-loop K u, 8 PCG steps each), {dt:.1f} s; "
+                      f"host has {os.cpu_count()} logical CPUs, BLAS threads {blas}"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus_requested": args.gpus}))
+        sys.exit(2)
+    import torch
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    p = synth.config("cfg3")
+    g = Grid.from_problem(p)
+
+    if args.profile_only == "apply":
+        for dtype in (torch.float32, torch.float64):
+            apply_timing(g, p, dtype, args.apply_reps, torch)
+        torch.cuda.synchronize()
+        print("profile-only apply done", flush=True)
+        return
+    if args.profile_only == "outer":
+        outer_loop(g, p, torch.float32, args.steps, args.warmup, torch)
+        print("profile-only outer done", flush=True)
+        return
+
+    dt32, st32 = outer_loop(g, p, torch.float32, args.steps, args.warmup, torch)
+    steps64 = max(10, args.steps // 2)
+    dt64, st64 = outer_loop(g, p, torch.float64, steps64, args.warmup // 2, torch)
+    t_apply32 = apply_timing(g, p, torch.float32, args.apply_reps, torch)
+    t_apply64 = apply_timing(g, p, torch.float64, args.apply_reps, torch)
+    t_apply32_cold = apply_timing(g, p, torch.float32, args.apply_reps, torch, cold=True)
+    t_apply64_cold = apply_timing(g, p, torch.float64, args.apply_reps, torch, cold=True)
+
+    ndof, E = p.ndof, p.E
+    bytes32 = 2 * ndof * 4 + E * 4          # read u, write y, read one density per element
+    bytes64 = 2 * ndof * 8 + E * 8
+    achieved = bytes32 / t_apply32 / 1e9
+    traffic = measured_traffic("cfg3_fp32")
+
+    fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(p, args.cpu_seconds)
+
+    value = args.steps / dt32
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "outer_iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt32 / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded U[0.2,0.4] densities, unit tip load), no dataset",
+        "config": {"workload": "hex8 cantilever 128x64x64 (524,288 elements, 1,635,075 DOFs), "
+                               "one outer iteration = filter r=2 + 8 Jacobi-PCG steps + sensitivity "
+                               "+ filter^T + mean-projected step + FP64 volume projection",
+                   "elements": E, "dofs": ndof, "inner_steps": p.inner_steps, "volfrac": p.volfrac,
+                   "filter_radius": p.filter_radius, "alpha0": ALPHA0_CFG3,
+                   "precision": "fp32 storage and arithmetic, fp64 dot products / norms / projection"},
+        "apply_K": {
+            "fp32_us": t_apply32 * 1e6, "fp32_gdof_s": ndof / t_apply32 / 1e9,
+            "fp64_us": t_apply64 * 1e6, "fp64_gdof_s": ndof / t_apply64 / 1e9,
+            "fp32_cold_us": t_apply32_cold * 1e6, "fp32_cold_gdof_s": ndof / t_apply32_cold / 1e9,
+            "fp64_cold_us": t_apply64_cold * 1e6, "fp64_cold_gdof_s": ndof / t_apply64_cold / 1e9,
+            "fp64_hbm_frac": bytes64 / t_apply64 / 1e9 / HBM_PEAK_GBS,
+            "fp32_cold_hbm_frac": bytes32 / t_apply32_cold / 1e9 / HBM_PEAK_GBS,
+            "fp64_cold_hbm_frac": bytes64 / t_apply64_cold / 1e9 / HBM_PEAK_GBS,
+        },
+        "fp64_path": {"outer_iter_s": steps64 / dt64, "ms_per_step": dt64 / steps64 * 1e3},
+        "final_state": {"fp32": st32, "fp64": st64},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_apply<float> (fbto_apply_K), algorithmic bytes 2*3N*4 + E*4 = "
+                               f"{bytes32} per launch"},
+        "fixed_error": fixed,
+        "cpu_baseline": cpu,
+        "kernel_hash": kernel_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -108,6 +108,7 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
   const int64_t nd = g->geo.ndof * g->desc.max_rhs, E = g->geo.E;
   HIP_TRY(hipMalloc(&V.r, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.p, nd * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.p2, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.q, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.invD, g->geo.ndof * sizeof(T)));
   HIP_TRY(hipMalloc(&V.rho, E * sizeof(T)));
@@ -122,7 +123,7 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
 }
 
 void free_vecs(Vecs& V) {
-  void* ps[] = {V.r, V.p, V.q, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
+  void* ps[] = {V.r, V.p, V.p2, V.q, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   V = Vecs{};
@@ -165,24 +166,40 @@ void drop_extra(fbto_grid_s* g) {
   }
 }
 
+// Counts of the per-block partials currently held in the CG slots.
+struct CgCounts {
+  int rz[2], rn[2], fn;
+};
+
 // PCG on K(rho) u = f from the warm start u (steps iterations; rtol > 0 stops
-// early, checked on the host every 32 steps).
+// early, checked on the host every 32 steps).  Per step: q = K p with the
+// partials of p.q, the update of u and r, and the next direction.  The CG
+// scalars live in per-block partials ping-ponging between two slots (cur).
+// f_dot: also leave the f.u partials (slot DOT) from the last update.
 template <typename T>
 fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps,
-                      double rtol, hipStream_t st) {
+                      double rtol, hipStream_t st, bool f_dot, int* cur_out, CgCounts* cn_out) {
   Vecs& V = vecs<T>(g);
   T* r = (T*)V.r;
   T* p = (T*)V.p;
   T* q = (T*)V.q;
   T* invD = (T*)V.invD;
+  CgCounts cn{};
+  int nb_a = 0, nb_u = 0;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
-  HIP_TRY(launch_pcg_init<T>(g, r, p, invD, nrhs, f, rtol, st));
+  HIP_TRY(launch_resid<T>(g, rho, u, f, r, invD, nrhs, st, &nb_a));
+  cn.rz[0] = cn.rn[0] = cn.fn = nb_a;
+  if (steps > 0) HIP_TRY(launch_pcg_first<T>(g, r, p, invD, nrhs, st));
+  int cur = 0;
   for (int s = 0; s < steps; ++s) {
-    HIP_TRY(launch_apply<T>(g, rho, p, q, nullptr, nrhs, 2, st));
-    HIP_TRY(launch_pcg_update<T>(g, u, r, p, q, invD, nrhs, st));
-    if (s + 1 < steps) HIP_TRY(launch_pcg_pupdate<T>(g, r, p, invD, nrhs, st));
-    if (rtol > 0.0 && ((s + 1) % 32 == 0)) {
+    HIP_TRY(launch_apply_pcg<T>(g, rho, p, q, nrhs, st, &nb_a));
+    const bool last = s + 1 == steps;
+    HIP_TRY(launch_pcg_update<T>(g, u, r, p, q, invD, (f_dot && last) ? f : nullptr, nrhs, cur, cn.rz[cur], nb_a,
+                                 cn.rn[cur], cn.fn, rtol, st, &nb_u));
+    cn.rz[cur ^ 1] = cn.rn[cur ^ 1] = nb_u;
+    cur ^= 1;
+    if (!last) HIP_TRY(launch_pcg_pupdate<T>(g, r, p, invD, nrhs, cur, cn.rz[cur], cn.rz[cur ^ 1], st));
+    if (rtol > 0.0 && ((s + 1) % 32 == 0) && !last) {
       Scalars host;
       HIP_TRY(hipMemcpyAsync(&host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -191,11 +208,31 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, 
       if (all) break;
     }
   }
+  if (f_dot && steps == 0) HIP_TRY(launch_dot<T>(g, f, u, nrhs, st));
+  *cur_out = cur;
+  *cn_out = cn;
   return FBTO_OK;
 }
 
-__global__ void k_set_steps(Scalars* sc, int nrhs, double steps) {
-  for (int R = 0; R < nrhs; ++R) sc->steps[R] = steps;
+template <typename T>
+fbto_status_t pcg_solve(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps, double rtol,
+                        hipStream_t st) {
+  int cur = 0;
+  CgCounts cn{};
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, steps, rtol, st, false, &cur, &cn);
+  if (s) return s;
+  HIP_TRY(launch_pcg_finish(g, nrhs, cur, cn.rz[cur], cn.rn[cur], cn.fn, nullptr, 0, 0, 0, st));
+  return FBTO_OK;
+}
+
+// r = f - K u with its norms (into the scalars)
+template <typename T>
+fbto_status_t residual_norms(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD, int nrhs,
+                             hipStream_t st) {
+  int nb = 0;
+  HIP_TRY(launch_resid<T>(g, rho, u, f, r, invD, nrhs, st, &nb));
+  HIP_TRY(launch_pcg_finish(g, nrhs, 0, nb, nb, nb, nullptr, 0, 0, 0, st));
+  return FBTO_OK;
 }
 
 template <typename T>
@@ -206,14 +243,10 @@ fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs
   T* invD = (T*)V.invD;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
   for (int s = 0; s < steps; ++s) {
-    HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
+    HIP_TRY(launch_resid<T>(g, rho, u, f, r, (const T*)nullptr, nrhs, st, nullptr));
     HIP_TRY(launch_relax_update<T>(g, u, r, invD, nrhs, omega, use_diag, st));
   }
-  HIP_TRY(launch_apply<T>(g, rho, u, r, f, nrhs, 1, st));
-  HIP_TRY(launch_pcg_init<T>(g, r, (T*)V.p, invD, nrhs, f, 0.0, st));
-  hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, g->sc, nrhs, (double)steps);
-  HIP_TRY(hipGetLastError());
-  return FBTO_OK;
+  return residual_norms<T>(g, rho, u, f, r, invD, nrhs, st);
 }
 
 template <typename T>
@@ -223,16 +256,19 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   Vecs& V = vecs<T>(g);
   T* rho = (T*)V.rho;
   HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
-  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st);
+  int cur = 0;
+  CgCounts cn{};
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cur, &cn);
   if (s != FBTO_OK) return s;
-  HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, st));
-  HIP_TRY(launch_dot<T>(g, f, u, g->geo.ndof, nrhs, &g->sc->dot[0], st));
-  HIP_TRY(launch_filter<T>(g, 1, (const T*)V.ge, (T*)V.gx, 1, st));
+  // element gradient already divided by Hs, so the filter transpose is a plain sum
+  HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
+  HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 1, st));
   const double alpha_k = alpha0 * std::pow((double)k, -0.75);
-  HIP_TRY(launch_step_v<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, vmax,
-                           st));
-  HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, info, st));
-  if (info) HIP_TRY(launch_outer_info(g, info, nrhs, st));
+  HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
+  HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, st));
+  const int nbE = vec_blocks(g->geo.E);
+  const int nbD = inner_steps > 0 ? vec_blocks(g->geo.ndof) : vec_blocks(g->geo.ndof);
+  HIP_TRY(launch_pcg_finish(g, nrhs, cur, cn.rz[cur], cn.rn[cur], cn.fn, info, nbD, nbE, nbE, st));
   return FBTO_OK;
 }
 
@@ -254,8 +290,9 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   if (d->nx > 65534 || d->ny > 65534 || d->nz > 65534)
     return fail(FBTO_ERR_ARG, "grid axis longer than 65534 elements");
   const int64_t N = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1);
-  if (N > ((int64_t)1 << 31))
-    return fail(FBTO_ERR_ARG, "grid has %lld nodes (limit 2^31)", (long long)N);
+  if (N >= ((int64_t)1 << 29))
+    return fail(FBTO_ERR_ARG, "grid has %lld nodes (limit 2^29, so that DOF indices fit 32 bits)",
+                (long long)N);
   if (d->max_rhs < 1 || d->max_rhs > 4) return fail(FBTO_ERR_ARG, "max_rhs = %d outside [1, 4]", d->max_rhs);
   if (!(d->young > 0.0) || !std::isfinite(d->young)) return fail(FBTO_ERR_ARG, "young must be > 0");
   if (!(d->poisson > -1.0 && d->poisson < 0.5)) return fail(FBTO_ERR_ARG, "poisson must be in (-1, 0.5)");
@@ -286,6 +323,10 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   G.N = N;
   G.E = (int64_t)d->nx * d->ny * d->nz;
   G.ndof = 3 * N;
+  G.rnx = 1.0 / G.nx;
+  G.rny = 1.0 / G.ny;
+  G.rnxn = 1.0 / G.nxn;
+  G.rnyn = 1.0 / G.nyn;
   modal_coefficients(d->young, d->poisson, g->km64, g->ke_diag);
   for (int i = 0; i < 3; ++i)
     for (int q = 0; q < 8; ++q) g->km32.dg[i][q] = (float)g->km64.dg[i][q];
@@ -360,10 +401,9 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   SETUP_TRY(hipMemcpy(g->stencil_w32, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice));
   SETUP_TRY(hipMalloc(&g->sc, sizeof(Scalars)));
   SETUP_TRY(hipMemset(g->sc, 0, sizeof(Scalars)));
-  SETUP_TRY(hipMalloc(&g->counters, CNT_COUNT * sizeof(unsigned)));
-  SETUP_TRY(hipMemset(g->counters, 0, CNT_COUNT * sizeof(unsigned)));
-  g->max_partials = std::max(apply_max_blocks(G, g->n_cu), g->n_cu * 8);
-  SETUP_TRY(hipMalloc(&g->partials, (size_t)g->max_partials * 16 * sizeof(double)));
+  g->max_partials = std::max(apply_max_blocks(G, g->n_cu), kMaxVecBlocks);
+  SETUP_TRY(hipMalloc(&g->partials, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
+  SETUP_TRY(hipMemset(g->partials, 0, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
   SETUP_TRY(hipDeviceSynchronize());
 #undef SETUP_TRY
   *out = g;
@@ -374,7 +414,7 @@ fbto_status_t fbto_destroy_grid(fbto_grid_t g) {
   if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
   (void)hipDeviceSynchronize();
   void* ps[] = {g->mask, g->spring_dof, g->spring_k64, g->spring_k32, g->stencil_off,
-                g->stencil_w64, g->stencil_w32, g->sc, g->counters, g->partials};
+                g->stencil_w64, g->stencil_w32, g->sc, g->partials};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   free_vecs(g->v64);
@@ -399,9 +439,9 @@ fbto_status_t fbto_apply_K(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys
   if (u == y) return fail(FBTO_ERR_ARG, "u and y must not overlap");
   hipStream_t st = (hipStream_t)stream;
   if (prec == FBTO_F64)
-    HIP_TRY(launch_apply<double>(g, (const double*)rho_phys, (const double*)u, (double*)y, nullptr, nrhs, 0, st));
+    HIP_TRY(launch_apply<double>(g, (const double*)rho_phys, (const double*)u, (double*)y, nrhs, st));
   else
-    HIP_TRY(launch_apply<float>(g, (const float*)rho_phys, (const float*)u, (float*)y, nullptr, nrhs, 0, st));
+    HIP_TRY(launch_apply<float>(g, (const float*)rho_phys, (const float*)u, (float*)y, nrhs, st));
   return ok();
 }
 
@@ -423,18 +463,18 @@ fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_
   if (prec == FBTO_F64) {
     if ((s = ensure_vecs<double>(g))) return s;
     s = method == FBTO_PCG_JACOBI
-            ? pcg_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, rtol, st)
+            ? pcg_solve<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, rtol, st)
             : relax_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, omega,
                                 method == FBTO_DAMPED_JACOBI, st);
   } else {
     if ((s = ensure_vecs<float>(g))) return s;
     s = method == FBTO_PCG_JACOBI
-            ? pcg_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, rtol, st)
+            ? pcg_solve<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, rtol, st)
             : relax_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, omega,
                                method == FBTO_DAMPED_JACOBI, st);
   }
   if (s) return s;
-  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, st));
+  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, method == FBTO_PCG_JACOBI ? -1.0 : (double)steps, st));
   return ok();
 }
 
@@ -460,13 +500,13 @@ fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const do
   const int64_t n = g->geo.ndof * nrhs;
   float* rho32 = (float*)g->v32.rho;
   if (inner_prec == FBTO_F32) HIP_TRY(launch_convert<float>(rho_phys, rho32, g->geo.E, 0, st));
+  HIP_TRY(launch_diag<double>(g, rho_phys, (double*)g->v64.invD, st));
   int it = 0;
   double total_inner = 0.0;
   std::vector<double> fn(nrhs, 0.0);
   for (;;) {
     // FP64 residual r = f - K64 u and its norms
-    HIP_TRY(launch_apply<double>(g, rho_phys, u, B.r64, f, nrhs, 1, st));
-    HIP_TRY(launch_pcg_init<double>(g, B.r64, (double*)g->v64.p, (double*)g->v64.invD, nrhs, f, 0.0, st));
+    if ((s = residual_norms<double>(g, rho_phys, u, f, B.r64, (const double*)g->v64.invD, nrhs, st))) return s;
     Scalars h;
     HIP_TRY(hipMemcpyAsync(&h, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -481,20 +521,18 @@ fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const do
     if (inner_prec == FBTO_F32) {
       HIP_TRY(launch_ir_scale(g, B.r64, (float*)B.f, nrhs, st));
       HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(float), st));
-      if ((s = pcg_run<float>(g, rho32, (const float*)B.f, (float*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      if ((s = pcg_solve<float>(g, rho32, (const float*)B.f, (float*)B.d, nrhs, inner_steps, 0.0, st))) return s;
       HIP_TRY(launch_ir_accum(g, u, (const float*)B.d, nrhs, st));
     } else {
       HIP_TRY(hipMemcpyAsync(B.f, B.r64, n * sizeof(double), hipMemcpyDeviceToDevice, st));
       HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(double), st));
-      if ((s = pcg_run<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      if ((s = pcg_solve<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, 0.0, st))) return s;
       HIP_TRY(launch_axpy64(u, (const double*)B.d, n, st));
     }
     total_inner += inner_steps;
   }
   // final norms are in the scalars (from the last FP64 residual)
-  hipLaunchKernelGGL(k_set_steps, dim3(1), dim3(1), 0, st, g->sc, nrhs, total_inner);
-  HIP_TRY(hipGetLastError());
-  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, st));
+  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, total_inner, st));
   if (refinements) *refinements = it;
   return ok();
 }
@@ -507,12 +545,18 @@ fbto_status_t fbto_sensitivity(fbto_grid_t g, fbto_prec_t prec, const void* rho_
   hipStream_t st = (hipStream_t)stream;
   if (prec == FBTO_F64) {
     HIP_TRY(launch_sens<double>(g, (const double*)rho_phys, (const double*)u, (const double*)lam, nrhs,
-                                (double*)dobj, st));
-    if (f && obj) HIP_TRY(launch_dot<double>(g, (const double*)f, (const double*)u, g->geo.ndof, nrhs, obj, st));
+                                (double*)dobj, (const double*)nullptr, st));
+    if (f && obj) {
+      HIP_TRY(launch_dot<double>(g, (const double*)f, (const double*)u, nrhs, st));
+      HIP_TRY(launch_dot_store(g, obj, st));
+    }
   } else {
     HIP_TRY(launch_sens<float>(g, (const float*)rho_phys, (const float*)u, (const float*)lam, nrhs,
-                               (float*)dobj, st));
-    if (f && obj) HIP_TRY(launch_dot<float>(g, (const float*)f, (const float*)u, g->geo.ndof, nrhs, obj, st));
+                               (float*)dobj, (const float*)nullptr, st));
+    if (f && obj) {
+      HIP_TRY(launch_dot<float>(g, (const float*)f, (const float*)u, nrhs, st));
+      HIP_TRY(launch_dot_store(g, obj, st));
+    }
   }
   return ok();
 }
@@ -545,9 +589,9 @@ fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y
                 lo * (double)g->geo.E);
   hipStream_t st = (hipStream_t)stream;
   if (prec == FBTO_F64)
-    HIP_TRY(launch_project<double>(g, (const double*)y, (double*)x, lo, hi, vmax, 0, nullptr, lambda, nullptr, st));
+    HIP_TRY(launch_project<double>(g, (const double*)y, (double*)x, lo, hi, vmax, 0, nullptr, lambda, st));
   else
-    HIP_TRY(launch_project<float>(g, (const float*)y, (float*)x, lo, hi, vmax, 0, nullptr, lambda, nullptr, st));
+    HIP_TRY(launch_project<float>(g, (const float*)y, (float*)x, lo, hi, vmax, 0, nullptr, lambda, st));
   return ok();
 }
 

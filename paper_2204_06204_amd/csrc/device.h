@@ -12,22 +12,42 @@ namespace fbto {
 // --------------------------------------------------------------------------
 // FP64 reductions with a fixed summation order (deterministic run to run).
 // --------------------------------------------------------------------------
+// Wave-wide sum / max of a double with DPP lane moves (no LDS traffic):
+// xor-1 and xor-2 within quads, mirrors within 8 and 16 lanes, then the
+// row broadcasts fold the four 16-lane rows into lane 63, which is read
+// back as a wave-uniform value.  The order of operations is fixed.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int rlo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, false);
+  const int rhi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, false);
+  return __hiloint2double(rhi, rlo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<0xB1, 0xf>(v);    // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E, 0xf>(v);    // quad_perm [2,3,0,1]
+  v += dpp_move<0x141, 0xf>(v);   // row_half_mirror
+  v += dpp_move<0x140, 0xf>(v);   // row_mirror: every lane holds its row's sum
+  v += dpp_move<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_move<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-__device__ __forceinline__ double ld_agent(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v = fmax(v, dpp_move<0xB1, 0xf>(v));
+  v = fmax(v, dpp_move<0x4E, 0xf>(v));
+  v = fmax(v, dpp_move<0x141, 0xf>(v));
+  v = fmax(v, dpp_move<0x140, 0xf>(v));
+  // rows not written by a broadcast receive 0 from dpp_move; max with a
+  // non-negative or -inf identity needs the real value, so fold explicitly
+  const double b15 = dpp_move<0x142, 0xa>(v);
+  v = ((__lane_id() >> 4) & 1) ? fmax(v, b15) : v;
+  const double b31 = dpp_move<0x143, 0xc>(v);
+  v = (__lane_id() >= 32) ? fmax(v, b31) : v;
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
 }
 
 // Reduce NV values over the block: entry i is a sum, or a max when bit i of
@@ -53,42 +73,45 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV]) {
   __syncthreads();
 }
 
-// Grid-wide reduction through per-block partials and a "last block
-// finishes" counter.  Every block calls it exactly once with its threads'
-// values; the function returns true in all threads of the block that
-// arrived last, with tot[] = reduction over all blocks in block order
-// (independent of arrival order).  `nblocks` is the number of blocks that
-// call it; the counter is reset for the next launch.
+// Reduce NV arrays of per-block partials (entry i: n[i] values at src[i];
+// sum, or max where bit i of MAXMASK is set).  Every block computes the same
+// result in the same order; the producing kernel has finished, so plain
+// loads see its stores.
 template <int NV, unsigned MAXMASK>
-__device__ __forceinline__ bool grid_reduce(double (&v)[NV], int block, int nblocks,
-                                            double* partials, unsigned* counter) {
-  __shared__ int am_last;
+__device__ __forceinline__ void reduce_parts(double (&v)[NV], const double* const (&src)[NV],
+                                             const int (&n)[NV]) {
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   const int nthr = blockDim.x * blockDim.y * blockDim.z;
-  block_reduce<NV, MAXMASK>(v);
-  if (tid == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) st_agent(&partials[(int64_t)block * NV + i], v[i]);
-    __threadfence();
-    const unsigned prev = atomicAdd(counter, 1u);
-    am_last = (prev == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (!am_last) return false;
-  __threadfence();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const bool is_max = (MAXMASK >> i) & 1u;
     double acc = is_max ? -INFINITY : 0.0;
-    for (int b = tid; b < nblocks; b += nthr) {
-      const double x = ld_agent(&partials[(int64_t)b * NV + i]);
-      acc = is_max ? fmax(acc, x) : acc + x;
-    }
+    for (int k = tid; k < n[i]; k += nthr) acc = is_max ? fmax(acc, src[i][k]) : acc + src[i][k];
     v[i] = acc;
   }
   block_reduce<NV, MAXMASK>(v);
-  if (tid == 0) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return true;
+}
+
+// Block-reduce NV values and let thread 0 store them as this block's
+// partials: entry i goes to dst[i][block].
+template <int NV, unsigned MAXMASK>
+__device__ __forceinline__ void write_parts(double (&v)[NV], double* const (&dst)[NV], int block) {
+  block_reduce<NV, MAXMASK>(v);
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  if (tid == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) dst[i][block] = v[i];
+  }
+}
+
+// q = n / d for 0 <= n < 2^31 with rd = 1.0 / d: the FP64 product is within
+// 2^-21 of n / d, so one correction step makes the quotient exact.
+__device__ __forceinline__ int fdiv(int n, int d, double rd) {
+  int q = (int)((double)n * rd);
+  const int r = n - q * d;
+  q += (r >= d) ? 1 : 0;
+  q -= (r < 0) ? 1 : 0;
+  return q;
 }
 
 // --------------------------------------------------------------------------

@@ -15,6 +15,7 @@ struct Geo {
   int nxn, nyn, nzn;   // nodes per axis (n + 1)
   int64_t N, E;        // nodes, elements
   int64_t ndof;        // 3N
+  double rnx, rny, rnxn, rnyn;  // reciprocals for 32-bit index division
 };
 
 // Element stiffness in the sum/difference ("modal") basis.  Per axis the
@@ -54,11 +55,12 @@ struct Scalars {
   double done[4];      // 1 once converged
   double status[4];    // fbto_status_t of the RHS
   double dot[4];       // scratch dot results
-  // projection
-  double lam;          // current multiplier / iterate
-  double lam_prev;     // last solution (warm start)
-  double br_a, br_b;   // bracket: f(a) > vmax >= f(b)
-  double proj_done;
+  // projection search state, double-buffered across passes: pass t reads
+  // ps[t & 1] and writes ps[(t + 1) & 1] = {lambda, a, b, done}, where the
+  // bracket satisfies f(a) > vmax >= f(b)
+  double ps[2][4];
+  double lam;          // multiplier of the last projection
+  double lam_prev;     // warm start of the next projection
   double proj_status;
   double sum0;         // sum clamp(y)
   double ymax, ymin;
@@ -67,22 +69,37 @@ struct Scalars {
   double work[8];
 };
 
-enum CounterSlot {
-  CNT_APPLY = 0, CNT_INIT, CNT_UPDATE, CNT_DOT, CNT_PROJ, CNT_PROJF, CNT_FILT,
-  CNT_STEP, CNT_MISC, CNT_COUNT
+// Per-block FP64 partial results.  A producing kernel writes one value per
+// block (and per RHS); the consuming kernel reduces them in a fixed order in
+// every block (no atomics, no inter-block fences, bitwise reproducible).
+enum PartSlot {
+  P_PQ = 0,            // p . K p            (apply, PCG mode)
+  P_RZ0, P_RZ1,        // r . z              (ping-pong between CG steps)
+  P_RN0, P_RN1,        // ||r||_2^2
+  P_RI0, P_RI1,        // ||r||_inf
+  P_FN,                // ||f||_2^2
+  P_DOT,               // sum_r f_r . u_r
+  P_GSUM,              // sum of the filtered gradient
+  P_S0, P_YMAX, P_NACT,  // projection seed: sum clamp(y), max y, #interior
+  P_E0,                // projection pass: 11 consecutive slots P_E0 .. P_E0+10
+  P_VOL = P_E0 + 11,   // sum x_new
+  P_DX,                // max |x_new - x_old|
+  P_COUNT
 };
+constexpr int kMaxVecBlocks = 1024;
 
 // Workspace vectors of one precision.
 struct Vecs {
   void* r = nullptr;      // [max_rhs][3N]
-  void* p = nullptr;
+  void* p = nullptr;      // search direction
+  void* p2 = nullptr;     // spare vector
   void* q = nullptr;
   void* invD = nullptr;   // [3N]
   void* rho = nullptr;    // [E]  filtered density
   void* ge = nullptr;     // [E]  element gradient
   void* gx = nullptr;     // [E]  design gradient
   void* y = nullptr;      // [E]  step / projection input
-  void* Hs = nullptr;     // [E]  filter normalisation
+  void* Hs = nullptr;     // [E]  inverse filter normalisation 1 / Hs
   bool ready = false;
 };
 
@@ -110,8 +127,7 @@ struct fbto_grid_s {
   double* stencil_w64 = nullptr;
   float* stencil_w32 = nullptr;
   fbto::Scalars* sc = nullptr;     // device
-  unsigned* counters = nullptr;    // device [CNT_COUNT]
-  double* partials = nullptr;      // device [max_partials * 8]
+  double* partials = nullptr;      // device [P_COUNT][4][max_partials]
   int max_partials = 0;
   fbto::Vecs v64, v32;
   int device = 0;
@@ -121,45 +137,53 @@ struct fbto_grid_s {
 namespace fbto {
 
 // ---- launchers (kernels.hip) ----------------------------------------------
-// All return hipSuccess or the launch error; none synchronises.
+// All return hipSuccess or the launch error; none synchronises.  Kernels that
+// leave per-block partials report how many blocks wrote them (nb_out), which
+// the consumer is told.
+int vec_blocks(int64_t n);
+int apply_max_blocks(const Geo& G, int n_cu);
 template <typename T>
-hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, const T* f,
-                        int nrhs, int mode, hipStream_t st);
+hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs, hipStream_t st);
+template <typename T>
+hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD,
+                        int nrhs, hipStream_t st, int* nb_out);
+template <typename T>
+hipError_t launch_apply_pcg(fbto_grid_s* g, const T* rho, const T* p, T* q, int nrhs, hipStream_t st,
+                            int* nb_out);
+template <typename T>
+hipError_t launch_pcg_pupdate(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, int cur,
+                              int n_new, int n_old, hipStream_t st);
+template <typename T>
+hipError_t launch_pcg_first(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, hipStream_t st);
 template <typename T>
 hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
 template <typename T>
-hipError_t launch_pcg_init(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs,
-                           const T* f, double rtol, hipStream_t st);
-template <typename T>
-hipError_t launch_pcg_update(fbto_grid_s* g, T* u, T* r, const T* p, const T* q,
-                             const T* invD, int nrhs, hipStream_t st);
-template <typename T>
-hipError_t launch_pcg_pupdate(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs,
-                              hipStream_t st);
+hipError_t launch_pcg_update(fbto_grid_s* g, T* u, T* r, const T* p, const T* q, const T* invD,
+                             const T* f, int nrhs, int cur, int n_rz, int n_pq, int n_rn, int n_fn,
+                             double rtol, hipStream_t st, int* nb_out);
+hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int cur, int n_rz, int n_rn, int n_fn,
+                             double* info, int n_dot, int n_e, int n_gsum, hipStream_t st);
 template <typename T>
 hipError_t launch_relax_update(fbto_grid_s* g, T* u, const T* r, const T* invD, int nrhs,
                                double omega, int use_diag, hipStream_t st);
 template <typename T>
-hipError_t launch_norms(fbto_grid_s* g, const T* r, int nrhs, hipStream_t st);
-template <typename T>
 hipError_t launch_sens(fbto_grid_s* g, const T* rho, const T* u, const T* lam, int nrhs,
-                       T* dobj, hipStream_t st);
+                       T* dobj, const T* Hsi, hipStream_t st);
 template <typename T>
-hipError_t launch_dot(fbto_grid_s* g, const T* a, const T* b, int64_t n, int nrhs,
-                      double* out, hipStream_t st);
+hipError_t launch_dot(fbto_grid_s* g, const T* a, const T* b, int nrhs, hipStream_t st);
+hipError_t launch_dot_store(fbto_grid_s* g, double* out, hipStream_t st);
 template <typename T>
-hipError_t launch_filter(fbto_grid_s* g, int transpose, const T* in, T* out, int want_sum,
+hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want_sum,
                          hipStream_t st);
 template <typename T>
-hipError_t launch_step_v(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
-                         int mean_project, double lo, double hi, double vmax, hipStream_t st);
+hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
+                       int mean_project, double lo, double hi, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(fbto_grid_s* g, T* Hs, hipStream_t st);
-int apply_max_blocks(const Geo& G, int n_cu);
 template <typename T>
 hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi,
-                          double vmax, int have_sum, const T* x_old, double* lam_out,
-                          double* info, hipStream_t st);
+                          double vmax, int seeded, const T* x_old, double* lam_out,
+                          hipStream_t st);
 template <typename T>
 hipError_t launch_convert(const void* in, void* out, int64_t n, int to_double, hipStream_t st);
 hipError_t launch_axpy64(double* u, const double* d, int64_t n, hipStream_t st);
@@ -167,8 +191,7 @@ hipError_t launch_ir_scale(fbto_grid_s* g, const double* r64, float* r32, int nr
                            hipStream_t st);
 hipError_t launch_ir_accum(fbto_grid_s* g, double* u64, const float* d32, int nrhs,
                            hipStream_t st);
-hipError_t launch_outer_info(fbto_grid_s* g, double* info, int nrhs, hipStream_t st);
-hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, hipStream_t st);
-hipError_t launch_scalar_reset(fbto_grid_s* g, int nrhs, hipStream_t st);
+hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double steps_override,
+                             hipStream_t st);
 
 }  // namespace fbto

@@ -130,3 +130,25 @@ def test_iterative_refinement_cfg3_residual():
     c = f @ uh
     c_corr = c + uh @ r
     assert abs(c - c_corr) <= 1e-6 * abs(c_corr)
+
+
+def test_solver_state_is_reset_between_calls():
+    """A converged tolerance solve must not leak its convergence flag or
+    step count into later solves on the same grid handle."""
+    p = synth.cantilever(16, 8, 8, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=2)
+    og, g, rho_t, s, K, D = _setup(p, torch.float64, 2)
+    f = p.loads[0]
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    u = torch.zeros(p.ndof, dtype=torch.float64, device=DEV)
+    g.inner_solve(rho_t, dev(f), u, 20000, rtol=1e-10, info=info)
+    assert host(info)[4] == 0
+    # fixed-step solve from zero on the same handle: exactly the oracle iterate
+    u2 = torch.zeros(p.ndof, dtype=torch.float64, device=DEV)
+    g.inner_solve(rho_t, dev(f), u2, 6, info=info)
+    ur, _ = oracle.pcg_ref(lambda v: K @ v, D, f, np.zeros(p.ndof), 6)
+    assert np.abs(host(u2) - ur).max() <= 1e-10 * np.abs(ur).max()
+    assert host(info)[3] == 6
+    # refinement after a converged solve on the same handle still converges
+    u3 = torch.zeros(p.ndof, dtype=torch.float64, device=DEV)
+    g.solve_refined(rho_t, dev(f), u3, 1e-10, 200, 60, inner_dtype=torch.float32)
+    assert np.linalg.norm(f - K @ host(u3)) <= 1e-10 * np.linalg.norm(f)
