@@ -117,16 +117,24 @@ __device__ __forceinline__ int fdiv(int n, int d, double rd) {
 // --------------------------------------------------------------------------
 // SIMP scaling s = rho_min + (1 - rho_min) rho^p and ds/drho.
 // --------------------------------------------------------------------------
+// General exponents go through pow() in a separate function so that the
+// cubic case (the common SIMP exponent) keeps the hot loops free of it.
+__device__ __noinline__ double simp_pow(double rho, double e) { return pow(rho, e); }
+
 template <typename T>
 __device__ __forceinline__ T simp_s(T rho, const Simp& sp) {
   const T rm = (T)sp.rho_min;
-  const T pw = sp.cubic ? rho * rho * rho : (T)pow((double)rho, sp.penal);
+  T pw;
+  if (sp.cubic) pw = rho * rho * rho;
+  else pw = (T)simp_pow((double)rho, sp.penal);
   return rm + ((T)1 - rm) * pw;
 }
 template <typename T>
 __device__ __forceinline__ T simp_ds(T rho, const Simp& sp) {
   const T rm = (T)sp.rho_min;
-  const T pw = sp.cubic ? rho * rho : (T)pow((double)rho, sp.penal - 1.0);
+  T pw;
+  if (sp.cubic) pw = rho * rho;
+  else pw = (T)simp_pow((double)rho, sp.penal - 1.0);
   return (T)sp.penal * ((T)1 - rm) * pw;
 }
 
