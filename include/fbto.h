@@ -140,10 +140,13 @@ fbto_status_t fbto_apply_K(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys
 
 /* Low-level refinement of u towards K(rho_phys) u = f (Alg. 1 / 3 low-level
  * line), `steps` steps of `method` from the warm start in u, per RHS.
+ * PCG_JACOBI runs the textbook preconditioned CG recurrence rearranged as in
+ * Chronopoulos and Gear (one reduction phase per step; same iterates in
+ * exact arithmetic).
  *   omega   step of RICHARDSON (beta) or DAMPED_JACOBI (omega); unused by PCG.
  *   rtol    0: run exactly `steps` steps, asynchronously.  rtol > 0 (PCG
  *           only): stop once ||r||_2 <= rtol ||f||_2 or after `steps`
- *           steps; this mode synchronises the stream every 32 steps.
+ *           steps; this mode synchronises the stream every 64 steps.
  *   info    device, FP64 [nrhs][FBTO_SOLVE_INFO], may be NULL.
  * Device-detected breakdown/non-finite values go to FBTO_SI_STATUS. */
 fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys,
@@ -153,7 +156,9 @@ fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_
 
 /* Mixed-precision solve with FP64 iterative refinement:
  *   repeat: r = f - K64 u (FP64 operator);  stop if ||r||_2 <= rtol ||f||_2;
- *           d = `inner_steps` steps of PCG in `inner_prec` on K d = r;  u += d
+ *           d = PCG in `inner_prec` on K d = r from d = 0, at most
+ *               `inner_steps` steps, stopping once its own residual has
+ *               dropped by inner_rtol (0: always inner_steps steps);  u += d
  * rho_phys, f, u are FP64 ([E], [nrhs][3N], [nrhs][3N]).  Synchronises the
  * stream after each refinement step.  info: device FP64
  * [nrhs][FBTO_SOLVE_INFO] (STEPS counts inner steps), may be NULL.
@@ -161,7 +166,7 @@ fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_
 fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec,
                                  const double* rho_phys, const double* f, double* u,
                                  int32_t nrhs, double rtol, int32_t max_refine,
-                                 int32_t inner_steps, double* info,
+                                 int32_t inner_steps, double inner_rtol, double* info,
                                  int32_t* refinements, void* stream);
 
 /* Sensitivity of Sec. 3 / Alg. 1, summed over the nrhs load cases:

@@ -36,7 +36,7 @@ _SIGS = {
     "fbto_inner_solve": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int, C.c_int32,
                                    C.c_double, C.c_double, _VP, _VP]),
     "fbto_solve_refined": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_int32,
-                                     C.c_int32, _VP, C.POINTER(C.c_int32), _VP]),
+                                     C.c_int32, C.c_double, _VP, C.POINTER(C.c_int32), _VP]),
     "fbto_sensitivity": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP]),
     "fbto_filter": (C.c_int, [_VP, C.c_int, C.c_int32, _VP, _VP, _VP]),
     "fbto_project_volume": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_double, C.c_double,

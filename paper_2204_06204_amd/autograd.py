@@ -22,8 +22,8 @@ from .grid import Grid
 def _solve(grid: Grid, rho: torch.Tensor, rhs: torch.Tensor, rtol: float, max_steps: int) -> torch.Tensor:
     u = torch.zeros_like(rhs)
     if rhs.dtype == torch.float64:
-        grid.solve_refined(rho, rhs.contiguous(), u, rtol, max_refine=max(1, max_steps // 200),
-                           inner_steps=200, inner_dtype=torch.float32)
+        grid.solve_refined(rho, rhs.contiguous(), u, rtol, max_refine=100, inner_steps=max_steps,
+                           inner_dtype=torch.float32, inner_rtol=1e-3)
     else:
         grid.inner_solve(rho, rhs.contiguous(), u, max_steps, rtol=rtol)
     return u

@@ -109,6 +109,7 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
   HIP_TRY(hipMalloc(&V.r, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.p, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.p2, nd * sizeof(T)));
+  HIP_TRY(hipMalloc(&V.s, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.q, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.invD, g->geo.ndof * sizeof(T)));
   HIP_TRY(hipMalloc(&V.rho, E * sizeof(T)));
@@ -123,7 +124,7 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
 }
 
 void free_vecs(Vecs& V) {
-  void* ps[] = {V.r, V.p, V.p2, V.q, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
+  void* ps[] = {V.r, V.p, V.p2, V.q, V.s, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   V = Vecs{};
@@ -166,40 +167,36 @@ void drop_extra(fbto_grid_s* g) {
   }
 }
 
-// Counts of the per-block partials currently held in the CG slots.
+// Jacobi-PCG on K(rho) x = f from the warm start x, `steps` steps in the
+// Chronopoulos-Gear arrangement (one apply and one vector kernel per step,
+// one reduction phase).  rtol > 0 stops early (checked on the host every 32
+// steps).  f_dot: also leave the f.x partials (slot DOT) after the last
+// step.  Returns the partial counts the finish kernel needs.
 struct CgCounts {
-  int rz[2], rn[2], fn;
+  int r, fn;
 };
 
-// PCG on K(rho) u = f from the warm start u (steps iterations; rtol > 0 stops
-// early, checked on the host every 32 steps).  Per step: q = K p with the
-// partials of p.q, the update of u and r, and the next direction.  The CG
-// scalars live in per-block partials ping-ponging between two slots (cur).
-// f_dot: also leave the f.u partials (slot DOT) from the last update.
 template <typename T>
-fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps,
-                      double rtol, hipStream_t st, bool f_dot, int* cur_out, CgCounts* cn_out) {
+fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, int steps,
+                      double rtol, hipStream_t st, bool f_dot, CgCounts* cn_out) {
   Vecs& V = vecs<T>(g);
   T* r = (T*)V.r;
+  T* z = (T*)V.q;
+  T* w = (T*)V.p2;
   T* p = (T*)V.p;
-  T* q = (T*)V.q;
+  T* s = (T*)V.s;
   T* invD = (T*)V.invD;
-  CgCounts cn{};
-  int nb_a = 0, nb_u = 0;
+  int nb_a = 0, nb_v = 0;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  HIP_TRY(launch_resid<T>(g, rho, u, f, r, invD, nrhs, st, &nb_a));
-  cn.rz[0] = cn.rn[0] = cn.fn = nb_a;
-  if (steps > 0) HIP_TRY(launch_pcg_first<T>(g, r, p, invD, nrhs, st));
-  int cur = 0;
-  for (int s = 0; s < steps; ++s) {
-    HIP_TRY(launch_apply_pcg<T>(g, rho, p, q, nrhs, st, &nb_a));
-    const bool last = s + 1 == steps;
-    HIP_TRY(launch_pcg_update<T>(g, u, r, p, q, invD, (f_dot && last) ? f : nullptr, nrhs, cur, cn.rz[cur], nb_a,
-                                 cn.rn[cur], cn.fn, rtol, st, &nb_u));
-    cn.rz[cur ^ 1] = cn.rn[cur ^ 1] = nb_u;
-    cur ^= 1;
-    if (!last) HIP_TRY(launch_pcg_pupdate<T>(g, r, p, invD, nrhs, cur, cn.rz[cur], cn.rz[cur ^ 1], st));
-    if (rtol > 0.0 && ((s + 1) % 32 == 0) && !last) {
+  HIP_TRY(launch_resid<T>(g, rho, x, f, r, invD, z, nrhs, st, &nb_a));
+  CgCounts cn{nb_a, nb_a};
+  for (int k = 0; k < steps; ++k) {
+    HIP_TRY(launch_apply_cg<T>(g, rho, z, r, w, nrhs, st, &nb_a));
+    const bool last = k + 1 == steps;
+    HIP_TRY(launch_cg_step<T>(g, x, r, z, w, p, s, invD, (f_dot && last) ? f : nullptr, nrhs, nb_a, cn.fn, k, rtol,
+                              st, &nb_v));
+    cn.r = nb_v;
+    if (rtol > 0.0 && ((k + 1) % 64 == 0) && !last) {
       Scalars host;
       HIP_TRY(hipMemcpyAsync(&host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -208,8 +205,7 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, 
       if (all) break;
     }
   }
-  if (f_dot && steps == 0) HIP_TRY(launch_dot<T>(g, f, u, nrhs, st));
-  *cur_out = cur;
+  if (f_dot && steps == 0) HIP_TRY(launch_dot<T>(g, f, x, nrhs, st));
   *cn_out = cn;
   return FBTO_OK;
 }
@@ -217,11 +213,10 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, 
 template <typename T>
 fbto_status_t pcg_solve(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps, double rtol,
                         hipStream_t st) {
-  int cur = 0;
   CgCounts cn{};
-  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, steps, rtol, st, false, &cur, &cn);
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, steps, rtol, st, false, &cn);
   if (s) return s;
-  HIP_TRY(launch_pcg_finish(g, nrhs, cur, cn.rz[cur], cn.rn[cur], cn.fn, nullptr, 0, 0, 0, st));
+  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, nullptr, 0, 0, 0, st));
   return FBTO_OK;
 }
 
@@ -230,8 +225,8 @@ template <typename T>
 fbto_status_t residual_norms(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD, int nrhs,
                              hipStream_t st) {
   int nb = 0;
-  HIP_TRY(launch_resid<T>(g, rho, u, f, r, invD, nrhs, st, &nb));
-  HIP_TRY(launch_pcg_finish(g, nrhs, 0, nb, nb, nb, nullptr, 0, 0, 0, st));
+  HIP_TRY(launch_resid<T>(g, rho, u, f, r, invD, (T*)vecs<T>(g).q, nrhs, st, &nb));
+  HIP_TRY(launch_pcg_finish(g, nrhs, nb, nb, nullptr, 0, 0, 0, st));
   return FBTO_OK;
 }
 
@@ -243,7 +238,7 @@ fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs
   T* invD = (T*)V.invD;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
   for (int s = 0; s < steps; ++s) {
-    HIP_TRY(launch_resid<T>(g, rho, u, f, r, (const T*)nullptr, nrhs, st, nullptr));
+    HIP_TRY(launch_resid<T>(g, rho, u, f, r, (const T*)nullptr, (T*)nullptr, nrhs, st, nullptr));
     HIP_TRY(launch_relax_update<T>(g, u, r, invD, nrhs, omega, use_diag, st));
   }
   return residual_norms<T>(g, rho, u, f, r, invD, nrhs, st);
@@ -256,9 +251,8 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   Vecs& V = vecs<T>(g);
   T* rho = (T*)V.rho;
   HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
-  int cur = 0;
   CgCounts cn{};
-  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cur, &cn);
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn);
   if (s != FBTO_OK) return s;
   // element gradient already divided by Hs, so the filter transpose is a plain sum
   HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
@@ -267,8 +261,8 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
   HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
-  const int nbD = inner_steps > 0 ? vec_blocks(g->geo.ndof) : vec_blocks(g->geo.ndof);
-  HIP_TRY(launch_pcg_finish(g, nrhs, cur, cn.rz[cur], cn.rn[cur], cn.fn, info, nbD, nbE, nbE, st));
+  const int nbD = vec_blocks(g->geo.ndof);
+  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, nbD, nbE, nbE, st));
   return FBTO_OK;
 }
 
@@ -480,12 +474,13 @@ fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_
 
 fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const double* rho_phys,
                                  const double* f, double* u, int32_t nrhs, double rtol,
-                                 int32_t max_refine, int32_t inner_steps, double* info,
-                                 int32_t* refinements, void* stream) {
+                                 int32_t max_refine, int32_t inner_steps, double inner_rtol,
+                                 double* info, int32_t* refinements, void* stream) {
   if (check_grid(g) || check_prec(inner_prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
   if (!rho_phys || !f || !u) return fail(FBTO_ERR_ARG, "rho_phys, f and u must be non-NULL");
   if (!(rtol > 0.0)) return fail(FBTO_ERR_ARG, "rtol must be > 0");
   if (max_refine < 1 || inner_steps < 1) return fail(FBTO_ERR_ARG, "max_refine and inner_steps must be >= 1");
+  if (!(inner_rtol >= 0.0 && inner_rtol < 1.0)) return fail(FBTO_ERR_ARG, "inner_rtol must be in [0, 1)");
   hipStream_t st = (hipStream_t)stream;
   fbto_status_t s;
   if ((s = ensure_vecs<double>(g))) return s;
@@ -521,12 +516,12 @@ fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const do
     if (inner_prec == FBTO_F32) {
       HIP_TRY(launch_ir_scale(g, B.r64, (float*)B.f, nrhs, st));
       HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(float), st));
-      if ((s = pcg_solve<float>(g, rho32, (const float*)B.f, (float*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      if ((s = pcg_solve<float>(g, rho32, (const float*)B.f, (float*)B.d, nrhs, inner_steps, inner_rtol, st))) return s;
       HIP_TRY(launch_ir_accum(g, u, (const float*)B.d, nrhs, st));
     } else {
       HIP_TRY(hipMemcpyAsync(B.f, B.r64, n * sizeof(double), hipMemcpyDeviceToDevice, st));
       HIP_TRY(hipMemsetAsync(B.d, 0, n * sizeof(double), st));
-      if ((s = pcg_solve<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, 0.0, st))) return s;
+      if ((s = pcg_solve<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, inner_rtol, st))) return s;
       HIP_TRY(launch_axpy64(u, (const double*)B.d, n, st));
     }
     total_inner += inner_steps;

@@ -55,6 +55,8 @@ struct Scalars {
   double done[4];      // 1 once converged
   double status[4];    // fbto_status_t of the RHS
   double dot[4];       // scratch dot results
+  double cg_gamma[2][4];  // r.z of the previous CG step (by step parity)
+  double cg_alpha[2][4];  // alpha of the previous CG step
   // projection search state, double-buffered across passes: pass t reads
   // ps[t & 1] and writes ps[(t + 1) & 1] = {lambda, a, b, done}, where the
   // bracket satisfies f(a) > vmax >= f(b)
@@ -91,9 +93,10 @@ constexpr int kMaxVecBlocks = 1024;
 // Workspace vectors of one precision.
 struct Vecs {
   void* r = nullptr;      // [max_rhs][3N]
-  void* p = nullptr;      // search direction
-  void* p2 = nullptr;     // spare vector
-  void* q = nullptr;
+  void* p = nullptr;      // CG search direction
+  void* p2 = nullptr;     // w = K z
+  void* q = nullptr;      // z = D^-1 r
+  void* s = nullptr;      // s = K p (by recurrence)
   void* invD = nullptr;   // [3N]
   void* rho = nullptr;    // [E]  filtered density
   void* ge = nullptr;     // [E]  element gradient
@@ -146,23 +149,18 @@ template <typename T>
 hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs, hipStream_t st);
 template <typename T>
 hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD,
-                        int nrhs, hipStream_t st, int* nb_out);
+                        T* z, int nrhs, hipStream_t st, int* nb_out);
 template <typename T>
-hipError_t launch_apply_pcg(fbto_grid_s* g, const T* rho, const T* p, T* q, int nrhs, hipStream_t st,
-                            int* nb_out);
-template <typename T>
-hipError_t launch_pcg_pupdate(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, int cur,
-                              int n_new, int n_old, hipStream_t st);
-template <typename T>
-hipError_t launch_pcg_first(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, hipStream_t st);
+hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs,
+                           hipStream_t st, int* nb_out);
 template <typename T>
 hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
 template <typename T>
-hipError_t launch_pcg_update(fbto_grid_s* g, T* u, T* r, const T* p, const T* q, const T* invD,
-                             const T* f, int nrhs, int cur, int n_rz, int n_pq, int n_rn, int n_fn,
-                             double rtol, hipStream_t st, int* nb_out);
-hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int cur, int n_rz, int n_rn, int n_fn,
-                             double* info, int n_dot, int n_e, int n_gsum, hipStream_t st);
+hipError_t launch_cg_step(fbto_grid_s* g, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD,
+                          const T* f, int nrhs, int n_apply, int n_fn, int step, double rtol,
+                          hipStream_t st, int* nb_out);
+hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot,
+                             int n_e, int n_gsum, hipStream_t st);
 template <typename T>
 hipError_t launch_relax_update(fbto_grid_s* g, T* u, const T* r, const T* invD, int nrhs,
                                double omega, int use_diag, hipStream_t st);

@@ -76,11 +76,12 @@ static int flat_grid(int64_t n) {
 //
 // Modes:
 //   APPLY  y = K u
-//   RESID  y = r = f - K u; if invD is given, also the partials of the
-//          first CG step: r.(D^-1 r), f.f, r.r, max|r|
-//   PCG    y = q = K p with the per-block partials of p . q
+//   RESID  y = r = f - K u; if invD is given, also z = D^-1 r and the
+//          partials of r.r, max|r|, f.f (the start of a CG solve)
+//   CG     y = w = K z with the partials of r.z, w.z, r.r, max|r| (one
+//          reduction phase per step of the Chronopoulos-Gear recurrence)
 // ===========================================================================
-enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_PCG = 2 };
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2 };
 
 template <typename T>
 struct ApplyArgs {
@@ -89,7 +90,9 @@ struct ApplyArgs {
   const T* u;          // input vector
   T* y;
   const T* f;          // RESID
-  const T* invD;       // RESID (optional): CG-init partials
+  const T* invD;       // RESID (optional): start of a CG solve
+  T* z;                // RESID: z = D^-1 r
+  const T* r;          // CG: current residual (for r.z, r.r)
   const uint8_t* mask;
   Modal<T> km;
   Simp sp;
@@ -168,7 +171,7 @@ __global__ void __launch_bounds__(BX* BY)
     return el ? simp_s<T>(rv, A.sp) : (T)0;
   };
 
-  constexpr int NP = MODE == MODE_RESID ? 4 * NR : NR;  // partial values per block
+  constexpr int NP = MODE == MODE_APPLY ? 1 : 4 * NR;  // partial values per block
   double part[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) part[i] = 0.0;
@@ -241,15 +244,20 @@ __global__ void __launch_bounds__(BX* BY)
               const T rv = fv - acc;
               A.y[o + c] = rv;
               if (A.invD) {
-                const T zv = A.invD[3 * n + c] * rv;
-                part[4 * r + 0] += (double)rv * (double)zv;
-                part[4 * r + 1] += (double)fv * (double)fv;
-                part[4 * r + 2] += (double)rv * (double)rv;
-                part[4 * r + 3] = fmax(part[4 * r + 3], fabs((double)rv));
+                A.z[o + c] = A.invD[3 * n + c] * rv;
+                part[4 * r + 0] += (double)rv * (double)rv;
+                part[4 * r + 1] = fmax(part[4 * r + 1], fabs((double)rv));
+                part[4 * r + 2] += (double)fv * (double)fv;
               }
             } else {
               A.y[o + c] = acc;
-              if constexpr (MODE == MODE_PCG) part[r] += (double)pv * (double)acc;
+              if constexpr (MODE == MODE_CG) {
+                const T rv = A.r[o + c];
+                part[4 * r + 0] += (double)rv * (double)pv;     // r.z
+                part[4 * r + 1] += (double)acc * (double)pv;    // w.z
+                part[4 * r + 2] += (double)rv * (double)rv;     // r.r
+                part[4 * r + 3] = fmax(part[4 * r + 3], fabs((double)rv));
+              }
             }
           }
         }
@@ -264,11 +272,16 @@ __global__ void __launch_bounds__(BX* BY)
         for (int c = 0; c < 3; ++c) ul[r][a][c] = uu[r][a][c];
   }
 
-  if constexpr (MODE == MODE_PCG) {
-    double* dst[NR];
+  if constexpr (MODE == MODE_CG) {
+    double* dst[4 * NR];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) dst[r] = A.P + ((int64_t)P_PQ * 4 + rhs0 + r) * A.maxp;
-    write_parts<NR, 0u>(part, dst, lb);
+    for (int r = 0; r < NR; ++r) {
+      dst[4 * r + 0] = A.P + ((int64_t)P_RZ0 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 1] = A.P + ((int64_t)P_PQ * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 2] = A.P + ((int64_t)P_RN0 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 3] = A.P + ((int64_t)P_RI0 * 4 + rhs0 + r) * A.maxp;
+    }
+    write_parts<4 * NR, 0x8888u>(part, dst, lb);
   }
   if constexpr (MODE == MODE_RESID) {
     if (A.invD == nullptr) return;
@@ -283,12 +296,12 @@ __global__ void __launch_bounds__(BX* BY)
     double* dst[4 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      dst[4 * r + 0] = A.P + ((int64_t)P_RZ0 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 1] = A.P + ((int64_t)P_FN * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 2] = A.P + ((int64_t)P_RN0 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 3] = A.P + ((int64_t)P_RI0 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 0] = A.P + ((int64_t)P_RN1 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 1] = A.P + ((int64_t)P_RI1 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 2] = A.P + ((int64_t)P_FN * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 3] = A.P + ((int64_t)P_RZ1 * 4 + rhs0 + r) * A.maxp;
     }
-    write_parts<4 * NR, 0x8888u>(part, dst, lb);
+    write_parts<4 * NR, 0x2222u>(part, dst, lb);
   }
 }
 
@@ -404,7 +417,7 @@ hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs
 }
 
 template <typename T>
-hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD,
+hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD, T* z,
                         int nrhs, hipStream_t st, int* nb_out) {
   ApplyArgs<T> A{};
   A.rho = rho;
@@ -412,17 +425,19 @@ hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T*
   A.y = r;
   A.f = f;
   A.invD = invD;
+  A.z = z;
   return launch_apply_mode<T, MODE_RESID>(g, A, nrhs, st, nb_out);
 }
 
 template <typename T>
-hipError_t launch_apply_pcg(fbto_grid_s* g, const T* rho, const T* p, T* q, int nrhs, hipStream_t st,
-                            int* nb_out) {
+hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, hipStream_t st,
+                           int* nb_out) {
   ApplyArgs<T> A{};
   A.rho = rho;
-  A.u = p;
-  A.y = q;
-  return launch_apply_mode<T, MODE_PCG>(g, A, nrhs, st, nb_out);
+  A.u = z;
+  A.r = r;
+  A.y = w;
+  return launch_apply_mode<T, MODE_CG>(g, A, nrhs, st, nb_out);
 }
 
 // ===========================================================================
@@ -471,251 +486,199 @@ hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st) {
 }
 
 // ===========================================================================
-// CG update.  Scalars are not stored by the producing kernels: the
-// prologue reduces their per-block partials, identically in every block.
-// alpha = (r.z) / (p.Kp); convergence / breakdown is decided the same way in
-// every block (block 0 records it; the decision is monotone, so a block that
-// reads the recorded flag or recomputes it gets the same alpha).  Then
-// u += alpha p, r -= alpha q, with partials of the new r.z, r.r, max|r| into
-// the other ping-pong slots, and optionally of f.u (slot DOT).
-// Loads of four strided entries per thread are issued together (ILP).
+// Jacobi-PCG in the Chronopoulos-Gear arrangement: one reduction phase per
+// step.  With z = D^-1 r and w = K z (from the CG-mode apply, which also
+// leaves the partials of gamma = r.z, delta = w.z, r.r, max|r|):
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+//   p = z + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,  z = D^-1 r
+// (beta = 0, alpha = gamma / delta on the first step).  In exact arithmetic
+// the iterates are those of the textbook recurrence.  The scalars are
+// reduced from the partials in every block's prologue; gamma and alpha of
+// the previous step are kept in the scalars, double-buffered by step parity
+// (block 0 writes the slot no block of this kernel reads).  Convergence and
+// breakdown are decided identically in every block.
 // ===========================================================================
 constexpr int kU = 4;
 
-struct UpdCounts {
-  int rz, pq, rn, fn;
+struct CgCnt {
+  int apply;   // partials of the last apply (gamma, delta, r.r, max|r|)
+  int fn;      // partials of f.f (the residual apply)
 };
 
 template <typename T, int NR>
 __global__ void __launch_bounds__(kVecBlock)
-    k_pcg_update(int64_t ndof, T* u, T* r, const T* p, const T* q, const T* invD, const T* f, double* P,
-                 int maxp, int cur, UpdCounts cn, double rtol, Scalars* sc) {
-  const int s_rz = cur ? P_RZ1 : P_RZ0, s_rn = cur ? P_RN1 : P_RN0;
-  const int n_rz = cur ? P_RZ0 : P_RZ1, n_rn = cur ? P_RN0 : P_RN1, n_ri = cur ? P_RI0 : P_RI1;
+    k_cg_step(int64_t ndof, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD, const T* f, double* P,
+              int maxp, CgCnt cn, int step, double rtol, Scalars* sc) {
+  // first chunk of this thread's vector entries is loaded before the prologue
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t i_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool first = step == 0;
+  T zv[kU][NR], wv[kU][NR], pv[kU][NR], sv[kU][NR], xv[kU][NR], rv[kU][NR], dv[kU];
+  bool ok[kU];
+  auto load_chunk = [&](int64_t i0) {
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int64_t i = i0 + k * stride;
+      ok[k] = i < ndof;
+      const int64_t ii = ok[k] ? i : 0;
+      dv[k] = invD[ii];
+#pragma unroll
+      for (int R = 0; R < NR; ++R) {
+        const int64_t o = R * ndof + ii;
+        zv[k][R] = z[o];
+        wv[k][R] = w[o];
+        xv[k][R] = x[o];
+        rv[k][R] = r[o];
+        pv[k][R] = first ? (T)0 : p[o];
+        sv[k][R] = first ? (T)0 : s[o];
+      }
+    }
+  };
+  if (i_first < ndof) load_chunk(i_first);
+
   double pre[4 * NR];
   {
     const double* src[4 * NR];
     int cnt[4 * NR];
 #pragma unroll
     for (int R = 0; R < NR; ++R) {
-      src[4 * R + 0] = pslot(P, s_rz, R, maxp);
+      src[4 * R + 0] = pslot(P, P_RZ0, R, maxp);
       src[4 * R + 1] = pslot(P, P_PQ, R, maxp);
-      src[4 * R + 2] = pslot(P, s_rn, R, maxp);
+      src[4 * R + 2] = pslot(P, P_RN0, R, maxp);
       src[4 * R + 3] = pslot(P, P_FN, R, maxp);
-      cnt[4 * R + 0] = cn.rz;
-      cnt[4 * R + 1] = cn.pq;
-      cnt[4 * R + 2] = cn.rn;
+      cnt[4 * R + 0] = cn.apply;
+      cnt[4 * R + 1] = cn.apply;
+      cnt[4 * R + 2] = cn.apply;
       cnt[4 * R + 3] = cn.fn;
     }
     reduce_parts<4 * NR, 0u>(pre, src, cnt);
   }
-  T al[NR];
+  T al[NR], be[NR];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  const int rd = (step + 1) & 1, wr = step & 1;
 #pragma unroll
   for (int R = 0; R < NR; ++R) {
-    const double rz = pre[4 * R], pq = pre[4 * R + 1], rn = sqrt(pre[4 * R + 2]), fn = sqrt(pre[4 * R + 3]);
+    const double gam = pre[4 * R], del = pre[4 * R + 1], rn = sqrt(pre[4 * R + 2]), fn = sqrt(pre[4 * R + 3]);
     bool done = sc->done[R] != 0.0 || (rtol > 0.0 && rn <= rtol * fn);
-    double alpha = 0.0, status = 0.0;
+    double alpha = 0.0, beta = 0.0, status = 0.0;
     if (!done) {
-      if (pq > 0.0 && isfinite(pq) && isfinite(rz)) {
-        alpha = rz / pq;
-      } else if (rz == 0.0) {
+      double denom = del;
+      if (!first) {
+        beta = gam / sc->cg_gamma[rd][R];
+        denom = del - beta * gam / sc->cg_alpha[rd][R];
+      }
+      if (denom > 0.0 && isfinite(denom) && isfinite(gam)) {
+        alpha = gam / denom;
+      } else if (gam == 0.0) {
         done = true;
+        beta = 0.0;
       } else {
-        status = isfinite(pq) && isfinite(rz) ? (double)FBTO_ERR_BREAKDOWN : (double)FBTO_ERR_NONFINITE;
+        status = isfinite(denom) && isfinite(gam) ? (double)FBTO_ERR_BREAKDOWN : (double)FBTO_ERR_NONFINITE;
         done = true;
+        beta = 0.0;
       }
     }
     al[R] = (T)alpha;
+    be[R] = (T)beta;
     if (lead) {
+      sc->cg_gamma[wr][R] = gam;
+      sc->cg_alpha[wr][R] = alpha;
       if (done) sc->done[R] = 1.0;
       if (status != 0.0) sc->status[R] = status;
       if (alpha != 0.0) sc->steps[R] += 1.0;
       sc->alpha[R] = alpha;
-      sc->pq[R] = pq;
+      sc->beta[R] = beta;
     }
   }
-  double v[3 * NR + 1];
+
+  double v[2 * NR + 1];
 #pragma unroll
-  for (int i = 0; i < 3 * NR + 1; ++i) v[i] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < ndof; i0 += kU * stride) {
-    T dv[kU], uv[kU][NR], pv[kU][NR], qv[kU][NR], rv[kU][NR];
-    bool ok[kU];
-#pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      const int64_t i = i0 + k * stride;
-      ok[k] = i < ndof;
-      const int64_t ii = ok[k] ? i : 0;
-      dv[k] = invD[ii];
-#pragma unroll
-      for (int R = 0; R < NR; ++R) {
-        uv[k][R] = u[R * ndof + ii];
-        pv[k][R] = p[R * ndof + ii];
-        qv[k][R] = q[R * ndof + ii];
-        rv[k][R] = r[R * ndof + ii];
-      }
-    }
+  for (int i = 0; i < 2 * NR + 1; ++i) v[i] = 0.0;
+  for (int64_t i0 = i_first; i0 < ndof; i0 += kU * stride) {
+    if (i0 != i_first) load_chunk(i0);
 #pragma unroll
     for (int k = 0; k < kU; ++k) {
       if (!ok[k]) continue;
       const int64_t i = i0 + k * stride;
 #pragma unroll
       for (int R = 0; R < NR; ++R) {
-        const T un = uv[k][R] + al[R] * pv[k][R];
-        const T rn = rv[k][R] - al[R] * qv[k][R];
-        u[R * ndof + i] = un;
-        r[R * ndof + i] = rn;
-        const T zn = dv[k] * rn;
-        v[3 * R + 0] += (double)rn * (double)zn;
-        v[3 * R + 1] += (double)rn * (double)rn;
-        v[3 * R + 2] = fmax(v[3 * R + 2], fabs((double)rn));
-        if (f) v[3 * NR] += (double)f[R * ndof + i] * (double)un;
+        const int64_t o = R * ndof + i;
+        const T pn = zv[k][R] + be[R] * pv[k][R];
+        const T sn = wv[k][R] + be[R] * sv[k][R];
+        const T xn = xv[k][R] + al[R] * pn;
+        const T rn = rv[k][R] - al[R] * sn;
+        p[o] = pn;
+        s[o] = sn;
+        x[o] = xn;
+        r[o] = rn;
+        z[o] = dv[k] * rn;
+        v[2 * R] += (double)rn * (double)rn;
+        v[2 * R + 1] = fmax(v[2 * R + 1], fabs((double)rn));
+        if (f) v[2 * NR] += (double)f[o] * (double)xn;
       }
     }
   }
-  if (f) {
-    double* dst[3 * NR + 1];
-#pragma unroll
-    for (int R = 0; R < NR; ++R) {
-      dst[3 * R + 0] = pslot(P, n_rz, R, maxp);
-      dst[3 * R + 1] = pslot(P, n_rn, R, maxp);
-      dst[3 * R + 2] = pslot(P, n_ri, R, maxp);
-    }
-    dst[3 * NR] = pslot(P, P_DOT, 0, maxp);
-    write_parts<3 * NR + 1, 0x924u>(v, dst, blockIdx.x);
-  } else {
-    double w[3 * NR];
-    double* dst[3 * NR];
-#pragma unroll
-    for (int R = 0; R < NR; ++R) {
-      w[3 * R] = v[3 * R];
-      w[3 * R + 1] = v[3 * R + 1];
-      w[3 * R + 2] = v[3 * R + 2];
-      dst[3 * R + 0] = pslot(P, n_rz, R, maxp);
-      dst[3 * R + 1] = pslot(P, n_rn, R, maxp);
-      dst[3 * R + 2] = pslot(P, n_ri, R, maxp);
-    }
-    write_parts<3 * NR, 0x924u>(w, dst, blockIdx.x);
-  }
-}
-
-// Prologue: beta = (r.z)_new / (r.z)_old (zero once the RHS has converged).
-// Then p = D^-1 r + beta p.
-template <typename T, int NR>
-__global__ void __launch_bounds__(kVecBlock)
-    k_pcg_pupdate(int64_t ndof, const T* r, T* p, const T* invD, const double* P, int maxp, int cur, int n_new,
-                  int n_old, const Scalars* sc) {
-  const int s_old = cur ? P_RZ0 : P_RZ1, s_new = cur ? P_RZ1 : P_RZ0;
-  double pre[2 * NR];
-  {
-    const double* src[2 * NR];
-    int cnt[2 * NR];
-#pragma unroll
-    for (int R = 0; R < NR; ++R) {
-      src[2 * R] = pslot(P, s_old, R, maxp);
-      src[2 * R + 1] = pslot(P, s_new, R, maxp);
-      cnt[2 * R] = n_old;
-      cnt[2 * R + 1] = n_new;
-    }
-    reduce_parts<2 * NR, 0u>(pre, src, cnt);
-  }
-  T be[NR];
-#pragma unroll
-  for (int R = 0; R < NR; ++R)
-    be[R] = (sc->done[R] == 0.0 && pre[2 * R] != 0.0) ? (T)(pre[2 * R + 1] / pre[2 * R]) : (T)0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < ndof; i0 += kU * stride) {
-    T dv[kU], rv[kU][NR], pv[kU][NR];
-    bool ok[kU];
-#pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      const int64_t i = i0 + k * stride;
-      ok[k] = i < ndof;
-      const int64_t ii = ok[k] ? i : 0;
-      dv[k] = invD[ii];
-#pragma unroll
-      for (int R = 0; R < NR; ++R) {
-        rv[k][R] = r[R * ndof + ii];
-        pv[k][R] = p[R * ndof + ii];
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < kU; ++k) {
-      if (!ok[k]) continue;
-      const int64_t i = i0 + k * stride;
-#pragma unroll
-      for (int R = 0; R < NR; ++R) p[R * ndof + i] = dv[k] * rv[k][R] + be[R] * pv[k][R];
-    }
-  }
-}
-
-// z = D^-1 r, p = z (the first CG direction)
-template <typename T, int NR>
-__global__ void __launch_bounds__(kVecBlock)
-    k_pcg_first(int64_t ndof, const T* r, T* p, const T* invD) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ndof;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const T di = invD[i];
-#pragma unroll
-    for (int R = 0; R < NR; ++R) p[R * ndof + i] = di * r[R * ndof + i];
-  }
-}
-
-// Reduce the final CG partials into the scalars; optionally also write the
-// outer-iteration record (compliance, projection results, gradient mean).
-template <int NR>
-__global__ void __launch_bounds__(kVecBlock)
-    k_pcg_finish(const double* P, int maxp, int cur, int n_rz, int n_rn, int n_fn, Scalars* sc,
-                 double* info, int n_dot, int n_e, int n_gsum, int64_t E) {
-  const int s_rz = cur ? P_RZ1 : P_RZ0, s_rn = cur ? P_RN1 : P_RN0, s_ri = cur ? P_RI1 : P_RI0;
-  double v[4 * NR + 4];
-  const double* src[4 * NR + 4];
-  int cnt[4 * NR + 4];
+  double* dst[2 * NR + 1];
 #pragma unroll
   for (int R = 0; R < NR; ++R) {
-    src[4 * R + 0] = pslot(P, s_rz, R, maxp);
-    src[4 * R + 1] = pslot(P, s_rn, R, maxp);
-    src[4 * R + 2] = pslot(P, s_ri, R, maxp);
-    src[4 * R + 3] = pslot(P, P_FN, R, maxp);
-    cnt[4 * R + 0] = n_rz;
-    cnt[4 * R + 1] = n_rn;
-    cnt[4 * R + 2] = n_rn;
-    cnt[4 * R + 3] = n_fn;
+    dst[2 * R] = pslot(P, P_RN1, R, maxp);
+    dst[2 * R + 1] = pslot(P, P_RI1, R, maxp);
   }
-  src[4 * NR + 0] = pslot(P, P_DOT, 0, maxp);
-  src[4 * NR + 1] = pslot(P, P_VOL, 0, maxp);
-  src[4 * NR + 2] = pslot(P, P_DX, 0, maxp);
-  src[4 * NR + 3] = pslot(P, P_GSUM, 0, maxp);
-  cnt[4 * NR + 0] = info ? n_dot : 0;
-  cnt[4 * NR + 1] = info ? n_e : 0;
-  cnt[4 * NR + 2] = info ? n_e : 0;
-  cnt[4 * NR + 3] = info ? n_gsum : 0;
-  constexpr unsigned MM = 0x4444u | (1u << (4 * NR + 2));
-  reduce_parts<4 * NR + 4, MM>(v, src, cnt);
+  dst[2 * NR] = pslot(P, P_DOT, 0, maxp);
+  write_parts<2 * NR + 1, 0xAAAu>(v, dst, blockIdx.x);
+}
+
+// Reduce the final residual norms into the scalars (slots RN1, RI1 with n_r
+// partials, f.f from FN); with `info`, also write the outer-iteration record
+// (compliance from DOT, projection results, gradient mean).
+template <int NR>
+__global__ void __launch_bounds__(kVecBlock)
+    k_pcg_finish(const double* P, int maxp, int n_r, int n_fn, Scalars* sc, double* info, int n_dot, int n_e,
+                 int n_gsum, int64_t E) {
+  double v[3 * NR + 4];
+  const double* src[3 * NR + 4];
+  int cnt[3 * NR + 4];
+#pragma unroll
+  for (int R = 0; R < NR; ++R) {
+    src[3 * R + 0] = pslot(P, P_RN1, R, maxp);
+    src[3 * R + 1] = pslot(P, P_RI1, R, maxp);
+    src[3 * R + 2] = pslot(P, P_FN, R, maxp);
+    cnt[3 * R + 0] = n_r;
+    cnt[3 * R + 1] = n_r;
+    cnt[3 * R + 2] = n_fn;
+  }
+  src[3 * NR + 0] = pslot(P, P_DOT, 0, maxp);
+  src[3 * NR + 1] = pslot(P, P_VOL, 0, maxp);
+  src[3 * NR + 2] = pslot(P, P_DX, 0, maxp);
+  src[3 * NR + 3] = pslot(P, P_GSUM, 0, maxp);
+  cnt[3 * NR + 0] = info ? n_dot : 0;
+  cnt[3 * NR + 1] = info ? n_e : 0;
+  cnt[3 * NR + 2] = info ? n_e : 0;
+  cnt[3 * NR + 3] = info ? n_gsum : 0;
+  constexpr unsigned MM = 0x492u | (1u << (3 * NR + 2));
+  reduce_parts<3 * NR + 4, MM>(v, src, cnt);
   if (threadIdx.x == 0) {
     double rinf = 0.0, rrel = 0.0, status = 0.0;
     for (int R = 0; R < NR; ++R) {
-      sc->rz[R] = v[4 * R];
-      sc->rnorm2[R] = sqrt(v[4 * R + 1]);
-      sc->rinf[R] = v[4 * R + 2];
-      sc->fnorm2[R] = sqrt(v[4 * R + 3]);
-      if (!isfinite(v[4 * R + 1]) && sc->status[R] == 0.0) sc->status[R] = (double)FBTO_ERR_NONFINITE;
+      sc->rnorm2[R] = sqrt(v[3 * R]);
+      sc->rinf[R] = v[3 * R + 1];
+      sc->fnorm2[R] = sqrt(v[3 * R + 2]);
+      if (!isfinite(v[3 * R]) && sc->status[R] == 0.0) sc->status[R] = (double)FBTO_ERR_NONFINITE;
       rinf = fmax(rinf, sc->rinf[R]);
       rrel = fmax(rrel, sc->fnorm2[R] > 0.0 ? sc->rnorm2[R] / sc->fnorm2[R] : sc->rnorm2[R]);
       if (sc->status[R] != 0.0) status = sc->status[R];
     }
     if (info) {
       if (sc->proj_status > 0.0) status = sc->proj_status;
-      sc->dot[0] = v[4 * NR];
-      info[FBTO_OI_COMPLIANCE] = v[4 * NR];
-      info[FBTO_OI_DX_INF] = v[4 * NR + 2];
+      sc->dot[0] = v[3 * NR];
+      info[FBTO_OI_COMPLIANCE] = v[3 * NR];
+      info[FBTO_OI_DX_INF] = v[3 * NR + 2];
       info[FBTO_OI_R_INF] = rinf;
       info[FBTO_OI_LAMBDA] = sc->lam;
-      info[FBTO_OI_VOLUME] = v[4 * NR + 1];
+      info[FBTO_OI_VOLUME] = v[3 * NR + 1];
       info[FBTO_OI_RREL] = rrel;
       info[FBTO_OI_STATUS] = status;
-      info[FBTO_OI_GRAD_MEAN] = v[4 * NR + 3] / (double)E;
+      info[FBTO_OI_GRAD_MEAN] = v[3 * NR + 3] / (double)E;
     }
   }
 }
@@ -739,38 +702,21 @@ __global__ void __launch_bounds__(kVecBlock)
   }
 
 template <typename T>
-hipError_t launch_pcg_update(fbto_grid_s* g, T* u, T* r, const T* p, const T* q, const T* invD, const T* f,
-                             int nrhs, int cur, int n_rz, int n_pq, int n_rn, int n_fn, double rtol,
-                             hipStream_t st, int* nb_out) {
+hipError_t launch_cg_step(fbto_grid_s* g, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD, const T* f,
+                          int nrhs, int n_apply, int n_fn, int step, double rtol, hipStream_t st, int* nb_out) {
   const int nb = vec_blocks(g->geo.ndof);
   if (nb_out) *nb_out = nb;
-  const UpdCounts cn{n_rz, n_pq, n_rn, n_fn};
-  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_update<T, NR>), dim3(nb), dim3(kVecBlock), 0, st,
-                                            g->geo.ndof, u, r, p, q, invD, f, g->partials, g->max_partials,
-                                            cur, cn, rtol, g->sc));
+  const CgCnt cn{n_apply, n_fn};
+  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_cg_step<T, NR>), dim3(nb), dim3(kVecBlock), 0, st, g->geo.ndof,
+                                            x, r, z, w, p, s, invD, f, g->partials, g->max_partials, cn, step,
+                                            rtol, g->sc));
   return hipGetLastError();
 }
-template <typename T>
-hipError_t launch_pcg_pupdate(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, int cur, int n_new,
-                              int n_old, hipStream_t st) {
-  const int nb = vec_blocks(g->geo.ndof);
-  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_pupdate<T, NR>), dim3(nb), dim3(kVecBlock), 0, st,
-                                            g->geo.ndof, r, p, invD, (const double*)g->partials,
-                                            g->max_partials, cur, n_new, n_old, (const Scalars*)g->sc));
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_pcg_first(fbto_grid_s* g, const T* r, T* p, const T* invD, int nrhs, hipStream_t st) {
-  const int nb = vec_blocks(g->geo.ndof);
-  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_first<T, NR>), dim3(nb), dim3(kVecBlock), 0, st,
-                                            g->geo.ndof, r, p, invD));
-  return hipGetLastError();
-}
-hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int cur, int n_rz, int n_rn, int n_fn, double* info,
-                             int n_dot, int n_e, int n_gsum, hipStream_t st) {
+hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot, int n_e,
+                             int n_gsum, hipStream_t st) {
   FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_finish<NR>), dim3(1), dim3(kVecBlock), 0, st,
-                                            (const double*)g->partials, g->max_partials, cur, n_rz, n_rn, n_fn,
-                                            g->sc, info, n_dot, n_e, n_gsum, g->geo.E));
+                                            (const double*)g->partials, g->max_partials, n_r, n_fn, g->sc, info,
+                                            n_dot, n_e, n_gsum, g->geo.E));
   return hipGetLastError();
 }
 template <typename T>
@@ -1341,16 +1287,13 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
 // ---- explicit instantiations ----------------------------------------------
 #define FBTO_INST(T)                                                                                   \
   template hipError_t launch_apply<T>(fbto_grid_s*, const T*, const T*, T*, int, hipStream_t);         \
-  template hipError_t launch_resid<T>(fbto_grid_s*, const T*, const T*, const T*, T*, const T*, int,   \
+  template hipError_t launch_resid<T>(fbto_grid_s*, const T*, const T*, const T*, T*, const T*, T*, int, \
                                       hipStream_t, int*);                                              \
-  template hipError_t launch_apply_pcg<T>(fbto_grid_s*, const T*, const T*, T*, int, hipStream_t, int*); \
-  template hipError_t launch_pcg_pupdate<T>(fbto_grid_s*, const T*, T*, const T*, int, int, int, int,    \
-                                            hipStream_t);                                               \
-  template hipError_t launch_pcg_first<T>(fbto_grid_s*, const T*, T*, const T*, int, hipStream_t);       \
+  template hipError_t launch_apply_cg<T>(fbto_grid_s*, const T*, const T*, const T*, T*, int, hipStream_t, \
+                                         int*);                                                        \
+  template hipError_t launch_cg_step<T>(fbto_grid_s*, T*, T*, T*, const T*, T*, T*, const T*, const T*,  \
+                                        int, int, int, int, double, hipStream_t, int*);                \
   template hipError_t launch_diag<T>(fbto_grid_s*, const T*, T*, hipStream_t);                         \
-  template hipError_t launch_pcg_update<T>(fbto_grid_s*, T*, T*, const T*, const T*, const T*,         \
-                                           const T*, int, int, int, int, int, int, double,             \
-                                           hipStream_t, int*);                                         \
   template hipError_t launch_relax_update<T>(fbto_grid_s*, T*, const T*, const T*, int, double, int,    \
                                              hipStream_t);                                             \
   template hipError_t launch_sens<T>(fbto_grid_s*, const T*, const T*, const T*, int, T*, const T*,    \

@@ -130,14 +130,15 @@ class Grid:
         return u
 
     def solve_refined(self, rho64, f64, u64, rtol: float, max_refine: int, inner_steps: int,
-                      inner_dtype=torch.float32, info: Optional[torch.Tensor] = None, stream=None):
+                      inner_dtype=torch.float32, inner_rtol: float = 0.0,
+                      info: Optional[torch.Tensor] = None, stream=None):
         prec = _lib.FBTO_F32 if inner_dtype == torch.float32 else _lib.FBTO_F64
         nr = self._nrhs(u64)
         nref = C.c_int32(0)
         check(self.lib.fbto_solve_refined(self.handle, prec, _ptr(rho64, torch.float64, self.E, "rho"),
                                           _ptr(f64, torch.float64, u64.numel(), "f"),
                                           _ptr(u64, torch.float64, None, "u"), nr, float(rtol),
-                                          int(max_refine), int(inner_steps),
+                                          int(max_refine), int(inner_steps), float(inner_rtol),
                                           _ptr(info, torch.float64, None, "info"), C.byref(nref),
                                           _stream(stream)), self.lib)
         return nref.value

@@ -62,7 +62,9 @@ def test_autograd_matches_oracle_mid_grid(which, dtype):
     L.backward()
     g_gpu = host(x_t.grad)
     val, g_ref = _oracle_objective_and_grad(p, p.x0, which)
-    vt, gt = (1e-9, 1e-8) if dtype == torch.float64 else (1e-5, 1e-4)
+    # float32 designs run FP32 Jacobi-PCG to 1e-6 (its true residual stalls near
+    # 1e-5 at this conditioning); float64 designs use the FP64-refined solve
+    vt, gt = (1e-9, 1e-8) if dtype == torch.float64 else (5e-5, 5e-4)
     assert abs(float(L.detach()) - val) <= vt * abs(val)
     assert np.linalg.norm(g_gpu - g_ref) <= gt * np.linalg.norm(g_ref)
 
