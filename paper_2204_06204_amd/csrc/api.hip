@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -106,10 +107,13 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
   Vecs& V = vecs<T>(g);
   if (V.ready) return FBTO_OK;
   const int64_t nd = g->geo.ndof * g->desc.max_rhs, E = g->geo.E;
-  HIP_TRY(hipMalloc(&V.r, nd * sizeof(T)));
-  HIP_TRY(hipMalloc(&V.p, nd * sizeof(T)));
-  HIP_TRY(hipMalloc(&V.p2, nd * sizeof(T)));
-  HIP_TRY(hipMalloc(&V.s, nd * sizeof(T)));
+  for (int b = 0; b < 2; ++b) {
+    HIP_TRY(hipMalloc(&V.r[b], nd * sizeof(T)));
+    HIP_TRY(hipMalloc(&V.p[b], nd * sizeof(T)));
+    HIP_TRY(hipMalloc(&V.s[b], nd * sizeof(T)));
+    HIP_TRY(hipMalloc(&V.w[b], nd * sizeof(T)));
+  }
+  HIP_TRY(hipMalloc(&V.x1, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.q, nd * sizeof(T)));
   HIP_TRY(hipMalloc(&V.invD, g->geo.ndof * sizeof(T)));
   HIP_TRY(hipMalloc(&V.rho, E * sizeof(T)));
@@ -124,7 +128,8 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
 }
 
 void free_vecs(Vecs& V) {
-  void* ps[] = {V.r, V.p, V.p2, V.q, V.s, V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
+  void* ps[] = {V.r[0], V.r[1], V.p[0], V.p[1], V.s[0], V.s[1], V.w[0], V.w[1], V.x1, V.q,
+                V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   V = Vecs{};
@@ -176,36 +181,94 @@ struct CgCounts {
   int r, fn;
 };
 
+// Diagnostics: FBTO_CG_TRACE=1 prints the reduced partial set of parity
+// `par` (r.z, w.z, r.r over n blocks) and the step coefficients after each
+// CG kernel (synchronises the stream).
+static void cg_trace(fbto_grid_s* g, hipStream_t st, const char* what, int k, int par, int n) {
+  static const bool on = getenv("FBTO_CG_TRACE") != nullptr;
+  if (!on) return;
+  (void)hipStreamSynchronize(st);
+  std::vector<double> h((size_t)P_COUNT * 4 * g->max_partials);
+  (void)hipMemcpy(h.data(), g->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+  Scalars sc;
+  (void)hipMemcpy(&sc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost);
+  auto sum = [&](int slot) {
+    double a = 0.0;
+    for (int i = 0; i < n; ++i) a += h[((size_t)slot * 4) * g->max_partials + i];
+    return a;
+  };
+  fprintf(stderr, "cg %s k=%d set %d (n=%d): rz %.17g wz %.17g rr %.17g | alpha %.17g beta %.17g done %g st %g\n",
+          what, k, par, n, sum(P_RZ0 + par), sum(P_PQ0 + par), sum(P_RN0 + par), sc.alpha[0], sc.beta[0],
+          sc.done[0], sc.status[0]);
+}
+
 template <typename T>
 fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, int steps,
                       double rtol, hipStream_t st, bool f_dot, CgCounts* cn_out) {
   Vecs& V = vecs<T>(g);
-  T* r = (T*)V.r;
-  T* z = (T*)V.q;
-  T* w = (T*)V.p2;
-  T* p = (T*)V.p;
-  T* s = (T*)V.s;
   T* invD = (T*)V.invD;
+  T* z = (T*)V.q;
+  CgSet<T> set[2] = {{x, (T*)V.r[0], (T*)V.p[0], (T*)V.s[0], (T*)V.w[0]},
+                     {(T*)V.x1, (T*)V.r[1], (T*)V.p[1], (T*)V.s[1], (T*)V.w[1]}};
   int nb_a = 0, nb_v = 0;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  HIP_TRY(launch_resid<T>(g, rho, x, f, r, invD, z, nrhs, st, &nb_a));
+  HIP_TRY(launch_resid<T>(g, rho, x, f, set[0].r, invD, z, nrhs, st, &nb_a));
   CgCounts cn{nb_a, nb_a};
-  for (int k = 0; k < steps; ++k) {
-    HIP_TRY(launch_apply_cg<T>(g, rho, z, r, w, nrhs, st, &nb_a));
-    const bool last = k + 1 == steps;
-    HIP_TRY(launch_cg_step<T>(g, x, r, z, w, p, s, invD, (f_dot && last) ? f : nullptr, nrhs, nb_a, cn.fn, k, rtol,
-                              st, &nb_v));
-    cn.r = nb_v;
-    if (rtol > 0.0 && ((k + 1) % 64 == 0) && !last) {
-      Scalars host;
-      HIP_TRY(hipMemcpyAsync(&host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      bool all = true;
-      for (int R = 0; R < nrhs; ++R) all = all && host.done[R] != 0.0;
-      if (all) break;
+  if (steps == 0) {
+    if (f_dot) HIP_TRY(launch_dot<T>(g, f, x, nrhs, st));
+    *cn_out = cn;
+    return FBTO_OK;
+  }
+  auto all_done = [&](bool& done) -> fbto_status_t {
+    Scalars host;
+    HIP_TRY(hipMemcpyAsync(&host, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    done = true;
+    for (int R = 0; R < nrhs; ++R) done = done && host.done[R] != 0.0;
+    return FBTO_OK;
+  };
+  // step 0's product w = K z from the residual's z
+  HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
+  cg_trace(g, st, "apply", 0, 0, nb_a);
+  int k = 0;
+  if constexpr (sizeof(T) == 4) {
+    // fused steps: the update of step k and the product of step k + 1 in one pass
+    for (; k + 1 < steps; ++k) {
+      HIP_TRY(launch_cg_fused<T>(g, rho, set[k & 1], set[(k + 1) & 1], invD, nrhs, k, nb_a, cn.fn, rtol, st,
+                                 &nb_a));
+      cg_trace(g, st, "fused", k, (k + 1) & 1, nb_a);
+      if (rtol > 0.0 && (k + 2) % 64 == 0 && k + 2 < steps) {
+        bool done = false;
+        if (fbto_status_t e = all_done(done)) return e;
+        if (done) {
+          ++k;
+          break;
+        }
+      }
+    }
+  } else {
+    // unfused steps: vector update, then the next product (FP64 keeps the
+    // register file for the element product)
+    for (; k + 1 < steps; ++k) {
+      HIP_TRY(launch_cg_step<T>(g, x, x, set[0].r, z, z, set[0].w, set[0].p, set[0].s, invD, nullptr, nrhs, nb_a,
+                                cn.fn, k, rtol, st, &nb_v));
+      HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, k + 1, st, &nb_a));
+      cg_trace(g, st, "step+apply", k, (k + 1) & 1, nb_a);
+      if (rtol > 0.0 && (k + 2) % 64 == 0 && k + 2 < steps) {
+        bool done = false;
+        if (fbto_status_t e = all_done(done)) return e;
+        if (done) {
+          ++k;
+          break;
+        }
+      }
     }
   }
-  if (f_dot && steps == 0) HIP_TRY(launch_dot<T>(g, f, x, nrhs, st));
+  // last vector update of step k, into the caller's x
+  const CgSet<T>& cur = set[sizeof(T) == 4 ? (k & 1) : 0];
+  HIP_TRY(launch_cg_step<T>(g, cur.x, x, cur.r, nullptr, nullptr, cur.w, cur.p, cur.s, invD, f_dot ? f : nullptr,
+                            nrhs, nb_a, cn.fn, k, rtol, st, &nb_v));
+  cn.r = nb_v;
   *cn_out = cn;
   return FBTO_OK;
 }
@@ -234,7 +297,7 @@ template <typename T>
 fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int steps,
                         double omega, int use_diag, hipStream_t st) {
   Vecs& V = vecs<T>(g);
-  T* r = (T*)V.r;
+  T* r = (T*)V.r[0];
   T* invD = (T*)V.invD;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
   for (int s = 0; s < steps; ++s) {
@@ -358,6 +421,7 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
     for (int64_t n = 0; n < N; ++n)
       nm[n] = (uint8_t)((fixed_dof_mask[3 * n] ? 1 : 0) | (fixed_dof_mask[3 * n + 1] ? 2 : 0) |
                         (fixed_dof_mask[3 * n + 2] ? 4 : 0));
+  for (int s = 0; s < n_springs; ++s) nm[spring_dof[s] / 3] |= 8;
 
   auto cleanup_fail = [&](fbto_status_t s) {
     fbto_destroy_grid(g);

@@ -16,6 +16,9 @@ namespace fbto {
 // xor-1 and xor-2 within quads, mirrors within 8 and 16 lanes, then the
 // row broadcasts fold the four 16-lane rows into lane 63, which is read
 // back as a wave-uniform value.  The order of operations is fixed.
+// DPP and readlane read all 64 lanes whatever the execution mask, so every
+// kernel that reduces this way is launched with whole waves (a partial last
+// wave would mix in the stale registers of its missing lanes).
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_move(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);

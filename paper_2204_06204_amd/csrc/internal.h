@@ -75,10 +75,13 @@ struct Scalars {
 // block (and per RHS); the consuming kernel reduces them in a fixed order in
 // every block (no atomics, no inter-block fences, bitwise reproducible).
 enum PartSlot {
-  P_PQ = 0,            // p . K p            (apply, PCG mode)
-  P_RZ0, P_RZ1,        // r . z              (ping-pong between CG steps)
-  P_RN0, P_RN1,        // ||r||_2^2
-  P_RI0, P_RI1,        // ||r||_inf
+  // CG-mode apply of step k (and the fused step that produces step k's
+  // apply) writes the set of parity k & 1: r.z, w.z, r.r, max|r|
+  P_RZ0, P_RZ1,
+  P_PQ0, P_PQ1,
+  P_RN0, P_RN1,
+  P_RI0, P_RI1,
+  P_RNF, P_RIF,        // final residual norms (residual apply, last CG vector step)
   P_FN,                // ||f||_2^2
   P_DOT,               // sum_r f_r . u_r
   P_GSUM,              // sum of the filtered gradient
@@ -90,13 +93,16 @@ enum PartSlot {
 };
 constexpr int kMaxVecBlocks = 1024;
 
-// Workspace vectors of one precision.
+// Workspace vectors of one precision.  The CG vectors come in two sets:
+// the fused CG step reads one and writes the other (x of the second set is
+// `x1`; the caller's vector is x of the first).
 struct Vecs {
-  void* r = nullptr;      // [max_rhs][3N]
-  void* p = nullptr;      // CG search direction
-  void* p2 = nullptr;     // w = K z
-  void* q = nullptr;      // z = D^-1 r
-  void* s = nullptr;      // s = K p (by recurrence)
+  void* r[2] = {nullptr, nullptr};   // [max_rhs][3N] residual
+  void* p[2] = {nullptr, nullptr};   // search direction
+  void* s[2] = {nullptr, nullptr};   // s = K p (by recurrence)
+  void* w[2] = {nullptr, nullptr};   // w = K z
+  void* x1 = nullptr;                // iterate, second set
+  void* q = nullptr;                 // z = D^-1 r (unfused steps)
   void* invD = nullptr;   // [3N]
   void* rho = nullptr;    // [E]  filtered density
   void* ge = nullptr;     // [E]  element gradient
@@ -104,6 +110,21 @@ struct Vecs {
   void* y = nullptr;      // [E]  step / projection input
   void* Hs = nullptr;     // [E]  inverse filter normalisation 1 / Hs
   bool ready = false;
+};
+
+// One set of CG vectors (pointers into Vecs or the caller's x).
+template <typename T>
+struct CgSet {
+  T* x;
+  T* r;
+  T* p;
+  T* s;
+  T* w;
+};
+
+// Tile shape and slab depth of one apply variant (chosen once per grid).
+struct TileChoice {
+  int bx, by, dz, tiles_x, tiles_y, slabs, nblocks;
 };
 
 struct StencilPt {
@@ -120,7 +141,7 @@ struct fbto_grid_s {
   fbto::Modal<float> km32;
   fbto::Simp simp;
   double ke_diag;            // every diagonal entry of KE: (lambda + 4 mu) / 9
-  uint8_t* mask = nullptr;   // [N] bit c: DOF c of the node fixed
+  uint8_t* mask = nullptr;   // [N] bit c < 3: DOF c of the node fixed; bit 3: a spring at the node
   int n_springs = 0;
   int64_t* spring_dof = nullptr;
   double* spring_k64 = nullptr;
@@ -135,6 +156,7 @@ struct fbto_grid_s {
   fbto::Vecs v64, v32;
   int device = 0;
   int n_cu = 256;
+  fbto::TileChoice tiles[2][2][4] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
 };
 
 namespace fbto {
@@ -151,14 +173,22 @@ template <typename T>
 hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD,
                         T* z, int nrhs, hipStream_t st, int* nb_out);
 template <typename T>
-hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs,
+hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, int step,
+                           hipStream_t st, int* nb_out);
+// One fused CG step k (FP32 only): vector update of step k from `in`, stored
+// into `out`, and out.w = K z of step k + 1 with its partials.
+template <typename T>
+hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, const CgSet<T>& out,
+                           const T* invD, int nrhs, int step, int n_apply, int n_fn, double rtol,
                            hipStream_t st, int* nb_out);
 template <typename T>
 hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
+// Vector update of CG step k: x = x_in + alpha p, r, p, s in place; z from
+// z_in or D^-1 r; z_out optional (the next unfused product's input).
 template <typename T>
-hipError_t launch_cg_step(fbto_grid_s* g, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD,
-                          const T* f, int nrhs, int n_apply, int n_fn, int step, double rtol,
-                          hipStream_t st, int* nb_out);
+hipError_t launch_cg_step(fbto_grid_s* g, const T* x_in, T* x, T* r, const T* z_in, T* z_out, const T* w,
+                          T* p, T* s, const T* invD, const T* f, int nrhs, int n_apply, int n_fn,
+                          int step, double rtol, hipStream_t st, int* nb_out);
 hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot,
                              int n_e, int n_gsum, hipStream_t st);
 template <typename T>

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
+#include <type_traits>
 
 #include "device.h"
 #include "internal.h"
@@ -60,19 +61,31 @@ static int flat_grid(int64_t n) {
 }
 
 // ===========================================================================
-// apply_K: z-marching tiles, one element column per thread.
+// apply_K: z-marching tiles in the sum/difference basis.
 //
-// Block = BX x BY threads; thread (tx, ty) owns element column
-// (ex, ey) = (bx (BX-1) - 1 + tx, by (BY-1) - 1 + ty) and marches the element
-// layers of one z-slab.  Per layer it uses the four nodes of the element's
-// upper face (loaded one layer ahead; the lower face is carried from the
-// previous layer), computes the full 24-entry element product in the
-// sum/difference basis, adds the lower-face half to the upper-face half
-// carried from the layer below (this completes the z-sum of every node of
-// the plane), and exchanges the four xy-corners through LDS so that each
-// interior thread sums the four element columns around its node in a fixed
-// order.  Neighbouring tiles overlap by one element column / row / layer, so
-// no atomics are needed and the result is bitwise reproducible.
+// A block owns a BX x BY tile of element columns (a runtime shape fitted to
+// the grid) and a slab of node planes.  Thread (tx, ty) owns element column
+// (ex, ey) = (x0 + tx, y0 + ty), x0 = bx (BX - 1) - 1, y0 = by (BY - 1) - 1,
+// and writes node (ex, ey) of every plane of the slab when tx, ty >= 1:
+// column and row 0 are the halo shared with the neighbouring tiles.
+//
+// Per element layer ez:
+//   - every node of plane ez + 2 is read from HBM once per tile (the own
+//     node, plus the far column and row of the tile by the first BX + BY + 1
+//     threads), masked and staged in LDS one layer ahead of its use;
+//   - the thread turns the upper face of its element into face modes
+//     (x, then y butterflies); the lower face's modes are the upper face's
+//     of the layer below, kept in registers;
+//   - z butterflies give 8 modes x 3 components; the modal KE (45 entries)
+//     times s_e; inverse z butterflies split the result into a lower-face
+//     and an upper-face part.  The upper part is carried to the next layer in
+//     modal form and added to that layer's lower part before the inverse x/y
+//     butterflies, so each face is transformed once in each direction;
+//   - the four corner values of plane ez are summed over the four element
+//     columns around each node through LDS, in a fixed order.
+// Node and corner buffers are double-buffered: one barrier per layer.
+// Tiles overlap by one element column / row and slabs by one element layer,
+// so there are no atomics and the result is bitwise reproducible.
 //
 // Modes:
 //   APPLY  y = K u
@@ -80,8 +93,18 @@ static int flat_grid(int64_t n) {
 //          partials of r.r, max|r|, f.f (the start of a CG solve)
 //   CG     y = w = K z with the partials of r.z, w.z, r.r, max|r| (one
 //          reduction phase per step of the Chronopoulos-Gear recurrence)
+//   CGF    one fused Chronopoulos-Gear step: the vector update of step k is
+//          done where each node is staged (z = D^-1 r, p = z + beta p,
+//          s = w + beta s, x += alpha p, r -= alpha s, z' = D^-1 r'), the
+//          owner of the node stores x', r', p', s' into the output set, and
+//          the product is w' = K z' (step k + 1's apply) with its partials.
+//          Input and output sets are distinct buffers: halo nodes of a tile
+//          are read by its neighbours while their owner writes the update.
 // ===========================================================================
-enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2 };
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3 };
+constexpr int kApplyMaxThreads = 512;
+constexpr size_t kApplyMaxLds = 64 * 1024;
+constexpr int kApplyMaxBlocks = 8192;
 
 template <typename T>
 struct ApplyArgs {
@@ -93,199 +116,476 @@ struct ApplyArgs {
   const T* invD;       // RESID (optional): start of a CG solve
   T* z;                // RESID: z = D^-1 r
   const T* r;          // CG: current residual (for r.z, r.r)
-  const uint8_t* mask;
+  const uint8_t* mask; // bits 0-2: fixed DOFs of the node; bit 3: the node has a spring
   Modal<T> km;
   Simp sp;
   int nspring;
   const int64_t* sdof;
   const T* sk;
+  int bx, by;          // tile shape (threads = bx * by)
   int tiles_x, tiles_y, slabs, dz, nblocks, per_xcd;
   double* P;           // partial slots
   int maxp;
   const Scalars* sc;
+  int step;            // CG, CGF: step k; CG writes, CGF reads the partial set of parity k & 1
+  // CGF only
+  const T *xi, *ri, *pi, *si, *wi;   // step k's x, r, p, s, w (p, s unread on the first step)
+  T *xo, *ro, *po, *so;              // step k + 1's x, r, p, s (w goes to y)
+  int n_apply, n_fn;                 // partial counts of step k's product and of f.f
+  double rtol;
 };
 
-template <typename T, int BX, int BY, int NR, int MODE>
-__global__ void __launch_bounds__(BX* BY)
+// Step coefficients of the Chronopoulos-Gear recurrence for one RHS from
+// gamma = r.z, delta = w.z, r.r and f.f of step k (identical in every
+// block):  beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma /
+// alpha_prev); beta = 0, alpha = gamma / delta on the first step.  A solved,
+// converged or broken-down RHS gets alpha = beta = 0.  The lead thread
+// records gamma and alpha in the step-parity slot k & 1 (this kernel reads
+// the other one), the flags and the step count.
+__device__ __forceinline__ void cg_coefficients(double gam, double del, double rr, double ff, int R,
+                                                int step, double rtol, Scalars* sc, bool lead,
+                                                double& alpha, double& beta) {
+  const bool first = step == 0;
+  const int rd = (step + 1) & 1, wr = step & 1;
+  const double rn = sqrt(rr), fn = sqrt(ff);
+  bool done = sc->done[R] != 0.0 || (rtol > 0.0 && rn <= rtol * fn);
+  double status = 0.0;
+  alpha = 0.0;
+  beta = 0.0;
+  if (!done) {
+    double denom = del;
+    if (!first) {
+      beta = gam / sc->cg_gamma[rd][R];
+      denom = del - beta * gam / sc->cg_alpha[rd][R];
+    }
+    if (denom > 0.0 && isfinite(denom) && isfinite(gam)) {
+      alpha = gam / denom;
+    } else if (gam == 0.0) {
+      done = true;
+      beta = 0.0;
+    } else {
+      status = isfinite(denom) && isfinite(gam) ? (double)FBTO_ERR_BREAKDOWN : (double)FBTO_ERR_NONFINITE;
+      done = true;
+      beta = 0.0;
+    }
+  }
+  if (lead) {
+    sc->cg_gamma[wr][R] = gam;
+    sc->cg_alpha[wr][R] = alpha;
+    if (done) sc->done[R] = 1.0;
+    if (status != 0.0) sc->status[R] = status;
+    if (alpha != 0.0) sc->steps[R] += 1.0;
+    sc->alpha[R] = alpha;
+    sc->beta[R] = beta;
+  }
+}
+
+// Face modes of one face: u[a][c] at local node a = ax + 2 ay -> F[q][c],
+// bit 0 / 1 of q set for the difference mode along x / y.
+template <typename T>
+__device__ __forceinline__ void face_modes(const T (&u)[4][3], T (&F)[4][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T s0 = u[0][c] + u[1][c], d0 = u[1][c] - u[0][c];
+    const T s1 = u[2][c] + u[3][c], d1 = u[3][c] - u[2][c];
+    F[0][c] = s0 + s1;
+    F[1][c] = d0 + d1;
+    F[2][c] = s1 - s0;
+    F[3][c] = d1 - d0;
+  }
+}
+// Transpose of face_modes.
+template <typename T>
+__device__ __forceinline__ void face_values(const T (&F)[4][3], T (&u)[4][3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const T v0 = F[0][c] - F[1][c], v1 = F[0][c] + F[1][c];
+    const T v2 = F[2][c] - F[3][c], v3 = F[2][c] + F[3][c];
+    u[0][c] = v0 - v2;
+    u[2][c] = v0 + v2;
+    u[1][c] = v1 - v3;
+    u[3][c] = v1 + v3;
+  }
+}
+
+// One element (one RHS): face modes of its lower and upper face, scale s.
+// `carry` holds the modal upper-face result of the element below on entry
+// and this element's on exit; `out` receives the values at the 4 nodes of
+// the lower face (both elements' contributions).
+template <typename T>
+__device__ __forceinline__ void layer_product(const T (&Flo)[4][3], const T (&Fup)[4][3], T s,
+                                              const Modal<T>& km, T (&carry)[4][3],
+                                              T (&out)[4][3]) {
+  T c[3][8], z[3][8];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    c[i][0] = (T)0;  // the all-sum mode (translation) carries no energy
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q) c[i][q] = s * (Flo[q][i] + Fup[q][i]);
+      c[i][q + 4] = s * (Fup[q][i] - Flo[q][i]);
+    }
+  }
+  modal_ke(c, km, z);
+  T lo[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lo[q][i] = (z[i][q] - z[i][q + 4]) + carry[q][i];
+      carry[q][i] = z[i][q] + z[i][q + 4];
+    }
+  face_values(lo, out);
+}
+
+template <typename T, int NR>
+struct ApplyStage {
+  T v[2][NR][3];
+  unsigned m[2];
+};
+
+// Loads of one node plane for the fused CG step (one RHS).
+template <typename T>
+struct FusedStage {
+  T x[3], r[2][3], p[2][3], s[2][3], w[2][3], d[2][3];
+  unsigned m[2];
+};
+
+template <typename T, int NR, int MODE>
+__global__ void __launch_bounds__(kApplyMaxThreads)
     k_apply(ApplyArgs<T> A, int rhs0) {
-  __shared__ T lds[NR][3][3][BY][BX];  // [rhs][corner 0..2][comp][ty][tx]
-  const int tx = threadIdx.x, ty = threadIdx.y;
+  extern __shared__ __align__(16) unsigned char apply_smem[];
   const int b = blockIdx.x;
   const int lb = (b & 7) * A.per_xcd + (b >> 3);  // XCD-aware: neighbours share an L2
-  if (lb >= A.nblocks) return;
+  if (lb >= A.nblocks) return;                    // whole block
   const Geo G = A.g;
+  const int BX = A.bx, BY = A.by;
+  const int NW = BX + 1;          // LDS node row
+  const int NS = NW * (BY + 1);   // LDS nodes per plane
+  const int TS = BX * BY;
+  T* nodes = reinterpret_cast<T*>(apply_smem);   // [2][NR][3][NS]
+  T* corners = nodes + 2 * NR * 3 * NS;          // [2][NR][9][TS]
 
-  const int bx = lb % A.tiles_x;
+  // The block is padded to whole waves (the DPP reductions read every lane
+  // of a wave); padding threads mirror thread 0 and store nothing.
+  const int tid = threadIdx.x;
+  const bool live = tid < TS;
+  const int tl = live ? tid : 0;
+  const int ty = tl / BX, tx = tl - ty * BX;
+  const int bxi = lb % A.tiles_x;
   const int t2 = lb / A.tiles_x;
-  const int by = t2 % A.tiles_y;
+  const int byi = t2 % A.tiles_y;
   const int bz = t2 / A.tiles_y;
-  const int ex = bx * (BX - 1) - 1 + tx;
-  const int ey = by * (BY - 1) - 1 + ty;
+  const int x0 = bxi * (BX - 1) - 1, y0 = byi * (BY - 1) - 1;
+  const int ex = x0 + tx, ey = y0 + ty;
   const int k0 = bz * A.dz;
-  const int kend = min(k0 + A.dz, G.nz + 1);
-  const bool xy_elem = ex >= 0 && ex < G.nx && ey >= 0 && ey < G.ny;
-  const bool out_xy = tx < BX - 1 && ty < BY - 1 && ex + 1 <= G.nx && ey + 1 <= G.ny;
+  const int kend = min(k0 + A.dz, G.nz + 1);  // emitted planes [k0, kend)
+  const int ez0 = k0 == 0 ? 0 : k0 - 1;        // first element layer (a halo layer if k0 > 0)
   const int plane = G.nxn * G.nyn;
+  const bool col_elem = ex >= 0 && ex < G.nx && ey >= 0 && ey < G.ny;
+  const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
 
-  bool vxy[4];
-  int nb0[4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int i = ex + (a & 1), j = ey + (a >> 1);
-    vxy[a] = i >= 0 && i <= G.nx && j >= 0 && j <= G.ny;
-    nb0[a] = vxy[a] ? i + G.nxn * j : 0;
+  // node columns staged by this thread: slot 0 its own (ex, ey), slot 1 one
+  // node of the tile's far column / row (threads 0 .. BX + BY)
+  const bool has_extra = tid <= BX + BY;
+  int li[2], gcol[2];
+  li[0] = tx + NW * ty;
+  gcol[0] = (ex >= 0 && ex <= G.nx && ey >= 0 && ey <= G.ny) ? ex + G.nxn * ey : -1;
+  {
+    const int lx = tid <= BY ? BX : tid - BY - 1;
+    const int ly = tid <= BY ? tid : BY;
+    const int i1 = x0 + lx, j1 = y0 + ly;
+    li[1] = has_extra ? lx + NW * ly : 0;
+    gcol[1] = (has_extra && i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1;
   }
-  const T* ub[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) ub[r] = A.u + (int64_t)(rhs0 + r) * G.ndof;
 
-  // raw loads of a face, issued one layer ahead of their use
-  T raw[NR][4][3];
-  unsigned rmask[4];
-  auto issue_face = [&](int k) {
+  auto issue = [&](int k, ApplyStage<T, NR>& S) {
     const bool kv = k >= 0 && k <= G.nz;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const bool ok = vxy[a] && kv;
-      const int n = ok ? nb0[a] + k * plane : 0;
-      rmask[a] = ok ? (unsigned)A.mask[n] : 7u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int r = 0; r < NR; ++r) raw[r][a][c] = ub[r][3 * n + c];
-    }
-  };
-  auto take_face = [&](T(&dst)[NR][4][3]) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+      const bool ok = kv && gcol[sl] >= 0;
+      const int n = ok ? gcol[sl] + k * plane : 0;
+      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          dst[r][a][c] = ((rmask[a] >> c) & 1u) ? (T)0 : raw[r][a][c];
-        }
+        for (int c = 0; c < 3; ++c) S.v[sl][r][c] = A.u[(int64_t)(rhs0 + r) * G.ndof + 3 * n + c];
+    }
   };
-  auto load_rho = [&](int ez) -> T {
-    const bool el = xy_elem && ez >= 0 && ez < G.nz;
+  auto stage = [&](const ApplyStage<T, NR>& S, int buf) {
+    T* nb = nodes + buf * (NR * 3 * NS);
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          nb[(r * 3 + c) * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : S.v[sl][r][c];
+    }
+  };
+  auto read_face = [&](int buf, T (&F)[NR][4][3], T (&own)[NR][3]) {
+    const T* nb = nodes + buf * (NR * 3 * NS);
+    const int o4[4] = {0, 1, NW, NW + 1};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T u4[4][3];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) u4[a][c] = nb[(r * 3 + c) * NS + li[0] + o4[a]];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) own[r][c] = u4[0][c];
+      face_modes(u4, F[r]);
+    }
+  };
+  auto load_s = [&](int ez) -> T {
+    const bool el = col_elem && ez >= 0 && ez < G.nz;
     const T rv = A.rho[el ? ex + G.nx * (ey + G.ny * ez) : 0];
     return el ? simp_s<T>(rv, A.sp) : (T)0;
   };
 
+  static_assert(MODE != MODE_CGF || NR == 1, "the fused CG step handles one RHS per launch");
   constexpr int NP = MODE == MODE_APPLY ? 1 : 4 * NR;  // partial values per block
   double part[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) part[i] = 0.0;
 
-  T ul[NR][4][3], uu[NR][4][3], carry[NR][4][3];
+  // fused CG step: coefficients of step k from its partials (every block)
+  T al = (T)0, be = (T)0;
+  const bool first = A.step == 0;
+  if constexpr (MODE == MODE_CGF) {
+    const int par = A.step & 1;
+    double pre[4];
+    const double* src[4] = {pslot(A.P, P_RZ0 + par, rhs0, A.maxp), pslot(A.P, P_PQ0 + par, rhs0, A.maxp),
+                            pslot(A.P, P_RN0 + par, rhs0, A.maxp), pslot(A.P, P_FN, rhs0, A.maxp)};
+    const int cnt[4] = {A.n_apply, A.n_apply, A.n_apply, A.n_fn};
+    reduce_parts<4, 0u>(pre, src, cnt);
+    double alpha, beta;
+    cg_coefficients(pre[0], pre[1], pre[2], pre[3], rhs0, A.step, A.rtol, const_cast<Scalars*>(A.sc),
+                    lb == 0 && tid == 0, alpha, beta);
+    al = (T)alpha;
+    be = (T)beta;
+  }
+  // fused CG step: loads of one plane, and the update at staging time
+  auto issue_f = [&](int k, FusedStage<T>& S) {
+    const bool kv = k >= 0 && k <= G.nz;
+    const bool own_plane = k >= k0 && k < kend;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+      const bool ok = kv && gcol[sl] >= 0;
+      const int n = ok ? gcol[sl] + k * plane : 0;
+      const int64_t o = (int64_t)rhs0 * G.ndof + 3 * n;
+      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        S.r[sl][c] = A.ri[o + c];
+        S.w[sl][c] = A.wi[o + c];
+        S.d[sl][c] = A.invD[3 * n + c];
+        S.p[sl][c] = first ? (T)0 : A.pi[o + c];
+        S.s[sl][c] = first ? (T)0 : A.si[o + c];
+      }
+      if (sl == 0 && writer && own_plane) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S.x[c] = A.xi[o + c];
+      }
+    }
+  };
+  auto stage_f = [&](const FusedStage<T>& S, int buf, int k) {
+    T* nb = nodes + buf * (3 * NS);
+    const bool own_plane = k >= k0 && k < kend;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+      const bool owner = sl == 0 && writer && own_plane;  // the owner's node index is valid
+      const int64_t o = (int64_t)rhs0 * G.ndof + 3 * (owner ? gcol[0] + k * plane : 0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T z = S.d[sl][c] * S.r[sl][c];
+        const T pn = z + be * S.p[sl][c];
+        const T sn = S.w[sl][c] + be * S.s[sl][c];
+        const T rn = S.r[sl][c] - al * sn;
+        const T zn = S.d[sl][c] * rn;
+        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : zn;
+        if (owner) {
+          A.xo[o + c] = S.x[c] + al * pn;
+          A.ro[o + c] = rn;
+          A.po[o + c] = pn;
+          A.so[o + c] = sn;
+          part[0] += (double)rn * (double)zn;  // r.z
+          part[2] += (double)rn * (double)rn;  // r.r
+          part[3] = fmax(part[3], fabs((double)rn));
+        }
+      }
+    }
+  };
+
+  ApplyStage<T, NR> S[2];
+  FusedStage<T> SF;
+  T F[2][NR][4][3];
+  T own[2][NR][3];
+  T carry[NR][4][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) carry[r][a][c] = (T)0;
+      for (int c = 0; c < 3; ++c) carry[r][q][c] = (T)0;
 
-  issue_face(k0 - 1);
-  take_face(ul);
-  issue_face(k0);
-  T s_next = load_rho(k0 - 1);
-  for (int ez = k0 - 1; ez < kend; ++ez) {
-    take_face(uu);
-    const T s = s_next;
-    if (ez + 1 < kend) {  // prefetch the next layer (uniform over the block)
-      issue_face(ez + 2);
-      s_next = load_rho(ez + 1);
+  // prologue: planes ez0, ez0 + 1 staged (and, unfused, plane ez0 + 2 in flight)
+  unsigned mq;  // masks of the own node, plane ez in byte 0, ez + 1 in byte 1, ..
+  if constexpr (MODE == MODE_CGF) {
+    issue_f(ez0, SF);
+    stage_f(SF, ez0 & 1, ez0);
+    mq = SF.m[0] & 0xffu;
+    issue_f(ez0 + 1, SF);
+    stage_f(SF, (ez0 + 1) & 1, ez0 + 1);
+    mq |= (SF.m[0] & 0xffu) << 8;
+  } else {
+    issue(ez0, S[0]);
+    issue(ez0 + 1, S[1]);
+    stage(S[0], ez0 & 1);
+    stage(S[1], (ez0 + 1) & 1);
+    mq = (S[0].m[0] & 0xffu) | ((S[1].m[0] & 0xffu) << 8);
+    issue(ez0 + 2, S[0]);
+  }
+  T s_cur = load_s(ez0);
+  __syncthreads();
+  read_face(ez0 & 1, F[0], own[0]);
+  __syncthreads();  // the first layer restages the buffer of plane ez0
+
+  auto layer = [&](auto parity, int ez) {
+    constexpr int P = decltype(parity)::value;
+    if constexpr (MODE == MODE_CGF) {
+      if (ez + 2 <= kend) issue_f(ez + 2, SF);
+    } else {
+      if (ez + 3 <= kend) issue(ez + 3, S[P ^ 1]);
     }
+    const T s = s_cur;
+    if (ez + 1 < kend) s_cur = load_s(ez + 1);
+    read_face((ez + 1) & 1, F[P ^ 1], own[P ^ 1]);
     const bool emit = ez >= k0;  // uniform over the block
-    T own[NR][3];
+    T out[NR][4][3];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      T ue[8][3], ye[8][3];
+    for (int r = 0; r < NR; ++r) layer_product(F[P][r], F[P ^ 1][r], s, A.km, carry[r], out[r]);
+    const int cb = ez & 1;
+    if (emit && live) {
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+      for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          ue[a][c] = ul[r][a][c];
-          ue[a + 4][c] = uu[r][a][c];
-        }
-      elem_apply<T>(ue, s, A.km, ye);
-      if (emit) {
+        for (int a = 1; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) lds[r][a][c][ty][tx] = carry[r][a][c] + ye[a][c];
-          own[r][c] = carry[r][3][c] + ye[3][c];
-        }
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) carry[r][a][c] = ye[a + 4][c];
+          for (int c = 0; c < 3; ++c)
+            corners[((cb * NR + r) * 9 + (a - 1) * 3 + c) * TS + tid] = out[r][a][c];
     }
-    if (emit) {
-      __syncthreads();
-      if (out_xy) {
-        const int n = (ex + 1) + G.nxn * (ey + 1) + ez * plane;
-        const unsigned m = A.mask[n];
+    if (ez + 2 <= kend) {
+      if constexpr (MODE == MODE_CGF) {
+        stage_f(SF, ez & 1, ez + 2);
+        mq |= (SF.m[0] & 0xffu) << 16;
+      } else {
+        stage(S[P], ez & 1);
+        mq |= (S[P].m[0] & 0xffu) << 16;
+      }
+    }
+    __syncthreads();
+    if (emit && writer) {
+      const int n = gcol[0] + ez * plane;
+      const unsigned m = mq & 0xffu;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const int64_t o = (int64_t)(rhs0 + r) * G.ndof + 3 * n;
+      for (int r = 0; r < NR; ++r) {
+        const T* cr = corners + (cb * NR + r) * 9 * TS;
+        const int64_t o = (int64_t)(rhs0 + r) * G.ndof + 3 * n;
+        T acc[3], pv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          acc[c] = ((out[r][0][c] + cr[(0 + c) * TS + tid - 1]) + cr[(3 + c) * TS + tid - BX]) +
+                   cr[(6 + c) * TS + tid - BX - 1];
+          pv[c] = own[P][r][c];  // masked input value at this node
+        }
+        if (m) {  // springs, then identity rows of fixed DOFs (rare nodes)
+          if (m & 8u) {
+            for (int sI = 0; sI < A.nspring; ++sI) {
+              const int64_t d = A.sdof[sI] - (int64_t)3 * n;
+#pragma unroll
+              for (int c = 0; c < 3; ++c)
+                if (d == c) acc[c] += A.sk[sI] * pv[c];
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            if ((m >> c) & 1u) {
+              if constexpr (MODE == MODE_CGF) {  // unmasked z' of this DOF, as staged
+                const T sn = A.wi[o + c] + be * (first ? (T)0 : A.si[o + c]);
+                pv[c] = A.invD[3 * n + c] * (A.ri[o + c] - al * sn);
+              } else {
+                pv[c] = A.u[o + c];
+              }
+              acc[c] = pv[c];
+            }
+        }
+        if constexpr (MODE == MODE_RESID) {
+          T fv[3], rv[3];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            T acc = ((own[r][c] + lds[r][2][c][ty][tx + 1]) + lds[r][1][c][ty + 1][tx]) +
-                    lds[r][0][c][ty + 1][tx + 1];
-            T pv = ul[r][3][c];  // masked input value at this node
-            for (int sI = 0; sI < A.nspring; ++sI)
-              if (A.sdof[sI] == (int64_t)(3 * n + c)) acc += A.sk[sI] * pv;
-            const bool fixed = (m >> c) & 1u;
-            if (fixed) pv = A.u[o + c];
-            if (fixed) acc = pv;
-            if constexpr (MODE == MODE_RESID) {
-              const T fv = A.f[o + c];
-              const T rv = fv - acc;
-              A.y[o + c] = rv;
-              if (A.invD) {
-                A.z[o + c] = A.invD[3 * n + c] * rv;
-                part[4 * r + 0] += (double)rv * (double)rv;
-                part[4 * r + 1] = fmax(part[4 * r + 1], fabs((double)rv));
-                part[4 * r + 2] += (double)fv * (double)fv;
-              }
-            } else {
-              A.y[o + c] = acc;
-              if constexpr (MODE == MODE_CG) {
-                const T rv = A.r[o + c];
-                part[4 * r + 0] += (double)rv * (double)pv;     // r.z
-                part[4 * r + 1] += (double)acc * (double)pv;    // w.z
-                part[4 * r + 2] += (double)rv * (double)rv;     // r.r
-                part[4 * r + 3] = fmax(part[4 * r + 3], fabs((double)rv));
-              }
+            fv[c] = A.f[o + c];
+            rv[c] = fv[c] - acc[c];
+            A.y[o + c] = rv[c];
+          }
+          if (A.invD) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              A.z[o + c] = A.invD[3 * n + c] * rv[c];
+              part[4 * r + 0] += (double)rv[c] * (double)rv[c];
+              part[4 * r + 1] = fmax(part[4 * r + 1], fabs((double)rv[c]));
+              part[4 * r + 2] += (double)fv[c] * (double)fv[c];
             }
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) A.y[o + c] = acc[c];
+          if constexpr (MODE == MODE_CG) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              const T rv = A.r[o + c];
+              part[4 * r + 0] += (double)rv * (double)pv[c];      // r.z
+              part[4 * r + 1] += (double)acc[c] * (double)pv[c];  // w.z
+              part[4 * r + 2] += (double)rv * (double)rv;         // r.r
+              part[4 * r + 3] = fmax(part[4 * r + 3], fabs((double)rv));
+            }
+          }
+          if constexpr (MODE == MODE_CGF) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) part[1] += (double)acc[c] * (double)pv[c];  // w'.z'
           }
         }
       }
-      __syncthreads();
     }
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ul[r][a][c] = uu[r][a][c];
+    mq >>= 8;
+  };
+  for (int ez = ez0; ez < kend; ez += 2) {
+    layer(std::integral_constant<int, 0>{}, ez);
+    if (ez + 1 >= kend) break;
+    layer(std::integral_constant<int, 1>{}, ez + 1);
   }
 
-  if constexpr (MODE == MODE_CG) {
+  if constexpr (MODE == MODE_CG || MODE == MODE_CGF) {
+    // CG: step k's product -> set k & 1; CGF: step k + 1's -> set (k + 1) & 1
+    const int par = (MODE == MODE_CG ? A.step : A.step + 1) & 1;
     double* dst[4 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      dst[4 * r + 0] = A.P + ((int64_t)P_RZ0 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 1] = A.P + ((int64_t)P_PQ * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 2] = A.P + ((int64_t)P_RN0 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 3] = A.P + ((int64_t)P_RI0 * 4 + rhs0 + r) * A.maxp;
+      dst[4 * r + 0] = pslot(A.P, P_RZ0 + par, rhs0 + r, A.maxp);
+      dst[4 * r + 1] = pslot(A.P, P_PQ0 + par, rhs0 + r, A.maxp);
+      dst[4 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
+      dst[4 * r + 3] = pslot(A.P, P_RI0 + par, rhs0 + r, A.maxp);
     }
     write_parts<4 * NR, 0x8888u>(part, dst, lb);
   }
   if constexpr (MODE == MODE_RESID) {
     if (A.invD == nullptr) return;
-    if (lb == 0 && tx == 0 && ty == 0) {   // a new solve starts from this residual
+    if (lb == 0 && tid == 0) {   // a new solve starts from this residual
       Scalars* sc = const_cast<Scalars*>(A.sc);
       for (int r = 0; r < NR; ++r) {
         sc->done[rhs0 + r] = 0.0;
@@ -293,73 +593,90 @@ __global__ void __launch_bounds__(BX* BY)
         sc->steps[rhs0 + r] = 0.0;
       }
     }
-    double* dst[4 * NR];
+    double v[3 * NR];
+    double* dst[3 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      dst[4 * r + 0] = A.P + ((int64_t)P_RN1 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 1] = A.P + ((int64_t)P_RI1 * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 2] = A.P + ((int64_t)P_FN * 4 + rhs0 + r) * A.maxp;
-      dst[4 * r + 3] = A.P + ((int64_t)P_RZ1 * 4 + rhs0 + r) * A.maxp;
+      v[3 * r + 0] = part[4 * r + 0];
+      v[3 * r + 1] = part[4 * r + 1];
+      v[3 * r + 2] = part[4 * r + 2];
+      dst[3 * r + 0] = pslot(A.P, P_RNF, rhs0 + r, A.maxp);
+      dst[3 * r + 1] = pslot(A.P, P_RIF, rhs0 + r, A.maxp);
+      dst[3 * r + 2] = pslot(A.P, P_FN, rhs0 + r, A.maxp);
     }
-    write_parts<4 * NR, 0x2222u>(part, dst, lb);
+    write_parts<3 * NR, 0x92u>(v, dst, lb);
   }
 }
 
-struct TileChoice {
-  int bx, by, dz, tiles_x, tiles_y, slabs, nblocks;
-};
+template <typename T, int NR>
+static size_t apply_lds_bytes(int bx, int by) {
+  return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by);
+}
 
-static TileChoice choose_tile(const Geo& G, int n_cu, int nr, bool fp64) {
+// Tile shape and slab depth for one apply variant.  The cost is the work of
+// the busiest CU in wave-layers (each block: its waves x (layers + 1 for the
+// prologue)), with a floor of kMinWaves resident waves per round below which
+// latency, not issue, sets the time.
+template <typename T, int NR, int MODE>
+static TileChoice choose_tile(const Geo& G, int n_cu) {
   const char* env = getenv("FBTO_APPLY_TILE");
   int want_bx = 0, want_by = 0, want_dz = 0;
   if (env) sscanf(env, "%dx%dx%d", &want_bx, &want_by, &want_dz);
-  const int opts[2][2] = {{16, 16}, {32, 8}};
-  const int dzs[] = {2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 48, 64};
+  constexpr double kMinWaves = 8.0;
   TileChoice best{};
   double best_cost = 1e300;
-  for (auto& o : opts) {
-    if (want_bx && (o[0] != want_bx || o[1] != want_by)) continue;
-    for (int dz : dzs) {
-      if (want_dz && dz != want_dz) continue;
-      TileChoice t;
-      t.bx = o[0];
-      t.by = o[1];
-      t.dz = dz;
-      t.tiles_x = (G.nxn + t.bx - 2) / (t.bx - 1);
-      t.tiles_y = (G.nyn + t.by - 2) / (t.by - 1);
-      t.slabs = (G.nzn + dz - 1) / dz;
-      const int64_t nb = (int64_t)t.tiles_x * t.tiles_y * t.slabs;
-      if (nb > (1 << 30)) continue;
-      t.nblocks = (int)nb;
-      // element-steps of work, inflated when the chip is under-filled or
-      // the last wave of blocks is ragged
-      const double work = (double)nb * t.bx * t.by * (dz + 1);
-      const double slots = 2.0 * n_cu;  // resident 256-thread blocks
-      const double waves = std::ceil(nb / slots);
-      const double fill = nb / (waves * slots);
-      const double cost = work / fill;
-      if (cost < best_cost) {
-        best_cost = cost;
-        best = t;
+  for (int bx = 8; bx <= 64; ++bx) {
+    if (want_bx && bx != want_bx) continue;
+    for (int by = 4; by <= 64; ++by) {
+      if (want_by && by != want_by) continue;
+      const int ts = bx * by;
+      if (ts < 128 || ts > kApplyMaxThreads) continue;
+      const size_t lds = apply_lds_bytes<T, NR>(bx, by);
+      if (lds > kApplyMaxLds) continue;
+      const int waves = (ts + 63) / 64;
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, 64 * waves, lds) !=
+              hipSuccess ||
+          occ < 1)
+        continue;
+      const int tiles_x = (G.nxn + bx - 2) / (bx - 1);
+      const int tiles_y = (G.nyn + by - 2) / (by - 1);
+      for (int dz = 1; dz <= std::min(G.nzn, 64); ++dz) {
+        if (want_dz && dz != want_dz) continue;
+        const int slabs = (G.nzn + dz - 1) / dz;
+        const int64_t nb = (int64_t)tiles_x * tiles_y * slabs;
+        if (nb > kApplyMaxBlocks) continue;
+        const int64_t per_cu = (nb + n_cu - 1) / n_cu;
+        const int64_t full = per_cu / occ, rem = per_cu % occ;
+        const double layers = dz + 2.0;
+        const double cost = full * std::max((double)occ * waves, kMinWaves) * layers +
+                            (rem ? std::max((double)rem * waves, kMinWaves) * layers : 0.0);
+        if (cost < best_cost) {
+          best_cost = cost;
+          best = TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb};
+        }
       }
     }
   }
-  (void)nr;
-  (void)fp64;
+  if (getenv("FBTO_APPLY_VERBOSE"))
+    fprintf(stderr, "fbto apply<%s, NR=%d, mode=%d>: tile %dx%d, dz %d, %d blocks\n",
+            sizeof(T) == 8 ? "f64" : "f32", NR, MODE, best.bx, best.by, best.dz, best.nblocks);
   return best;
 }
 
-
-int apply_max_blocks(const Geo& G, int n_cu) {
-  int m = 0;
-  for (int nr : {1, 2, 4})
-    for (bool fp64 : {false, true}) m = std::max(m, choose_tile(G, n_cu, nr, fp64).nblocks);
-  return m;
-}
-
-template <typename T, int BX, int BY, int NR, int MODE>
-static hipError_t launch_apply_t(const ApplyArgs<T>& A0, const TileChoice& t, int rhs0, hipStream_t st) {
+template <typename T, int NR, int MODE>
+static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs0, hipStream_t st,
+                                 int* nb_out) {
+  TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][NR - 1][MODE];
+  if (t.nblocks == 0) {
+    t = choose_tile<T, NR, MODE>(g->geo, g->n_cu);
+    if (t.nblocks == 0) return hipErrorInvalidConfiguration;
+  }
+  if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
+  if (nb_out) *nb_out = t.nblocks;
   ApplyArgs<T> A = A0;
+  A.bx = t.bx;
+  A.by = t.by;
   A.tiles_x = t.tiles_x;
   A.tiles_y = t.tiles_y;
   A.slabs = t.slabs;
@@ -367,7 +684,9 @@ static hipError_t launch_apply_t(const ApplyArgs<T>& A0, const TileChoice& t, in
   A.nblocks = t.nblocks;
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
-  hipLaunchKernelGGL((k_apply<T, BX, BY, NR, MODE>), dim3(grid), dim3(BX, BY), 0, st, A, rhs0);
+  const size_t lds = apply_lds_bytes<T, NR>(t.bx, t.by);
+  const int threads = (t.bx * t.by + 63) / 64 * 64;  // whole waves
+  hipLaunchKernelGGL((k_apply<T, NR, MODE>), dim3(grid), dim3(threads), lds, st, A, rhs0);
   return hipGetLastError();
 }
 
@@ -383,29 +702,14 @@ static hipError_t launch_apply_mode(fbto_grid_s* g, ApplyArgs<T> A, int nrhs, hi
   A.P = g->partials;
   A.maxp = g->max_partials;
   A.sc = g->sc;
-  constexpr bool fp64 = sizeof(T) == 8;
-  const int maxnr = fp64 ? 2 : 4;
-  int r0 = 0;
+  // one RHS per launch: the per-RHS state of the z-march (two face-mode
+  // sets, the modal carry, staged loads) fills the register file at NR = 1
   hipError_t e = hipSuccess;
-  while (r0 < nrhs && e == hipSuccess) {
-    int nr = std::min(nrhs - r0, maxnr);
-    if (nr == 3) nr = 2;
-    const TileChoice t = choose_tile(g->geo, g->n_cu, nr, fp64);
-    if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
-    if (nb_out) *nb_out = t.nblocks;
-    if (nr == 1) {
-      e = t.bx == 32 ? launch_apply_t<T, 32, 8, 1, MODE>(A, t, r0, st) : launch_apply_t<T, 16, 16, 1, MODE>(A, t, r0, st);
-    } else if (nr == 2) {
-      e = t.bx == 32 ? launch_apply_t<T, 32, 8, 2, MODE>(A, t, r0, st) : launch_apply_t<T, 16, 16, 2, MODE>(A, t, r0, st);
-    } else {
-      if constexpr (!fp64) {
-        e = t.bx == 32 ? launch_apply_t<T, 32, 8, 4, MODE>(A, t, r0, st) : launch_apply_t<T, 16, 16, 4, MODE>(A, t, r0, st);
-      }
-    }
-    r0 += nr;
-  }
+  for (int r0 = 0; r0 < nrhs && e == hipSuccess; ++r0) e = launch_apply_t<T, 1, MODE>(g, A, r0, st, nb_out);
   return e;
 }
+
+int apply_max_blocks(const Geo&, int) { return kApplyMaxBlocks; }
 
 template <typename T>
 hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs, hipStream_t st) {
@@ -430,14 +734,36 @@ hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T*
 }
 
 template <typename T>
-hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, hipStream_t st,
-                           int* nb_out) {
+hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, int step,
+                           hipStream_t st, int* nb_out) {
   ApplyArgs<T> A{};
   A.rho = rho;
   A.u = z;
   A.r = r;
   A.y = w;
+  A.step = step;
   return launch_apply_mode<T, MODE_CG>(g, A, nrhs, st, nb_out);
+}
+
+template <typename T>
+hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, const CgSet<T>& out,
+                           const T* invD, int nrhs, int step, int n_apply, int n_fn, double rtol,
+                           hipStream_t st, int* nb_out) {
+  if constexpr (sizeof(T) == 8) {
+    return hipErrorNotSupported;
+  } else {
+    ApplyArgs<T> A{};
+    A.rho = rho;
+    A.y = out.w;
+    A.invD = invD;
+    A.step = step;
+    A.xi = in.x; A.ri = in.r; A.pi = in.p; A.si = in.s; A.wi = in.w;
+    A.xo = out.x; A.ro = out.r; A.po = out.p; A.so = out.s;
+    A.n_apply = n_apply;
+    A.n_fn = n_fn;
+    A.rtol = rtol;
+    return launch_apply_mode<T, MODE_CGF>(g, A, nrhs, st, nb_out);
+  }
 }
 
 // ===========================================================================
@@ -507,8 +833,8 @@ struct CgCnt {
 
 template <typename T, int NR>
 __global__ void __launch_bounds__(kVecBlock)
-    k_cg_step(int64_t ndof, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD, const T* f, double* P,
-              int maxp, CgCnt cn, int step, double rtol, Scalars* sc) {
+    k_cg_step(int64_t ndof, const T* x_in, T* x, T* r, const T* z_in, T* z_out, const T* w, T* p, T* s,
+              const T* invD, const T* f, double* P, int maxp, CgCnt cn, int step, double rtol, Scalars* sc) {
   // first chunk of this thread's vector entries is loaded before the prologue
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,10 +851,10 @@ __global__ void __launch_bounds__(kVecBlock)
 #pragma unroll
       for (int R = 0; R < NR; ++R) {
         const int64_t o = R * ndof + ii;
-        zv[k][R] = z[o];
-        wv[k][R] = w[o];
-        xv[k][R] = x[o];
         rv[k][R] = r[o];
+        zv[k][R] = z_in ? z_in[o] : dv[k] * rv[k][R];
+        wv[k][R] = w[o];
+        xv[k][R] = x_in[o];
         pv[k][R] = first ? (T)0 : p[o];
         sv[k][R] = first ? (T)0 : s[o];
       }
@@ -538,13 +864,14 @@ __global__ void __launch_bounds__(kVecBlock)
 
   double pre[4 * NR];
   {
+    const int par = step & 1;
     const double* src[4 * NR];
     int cnt[4 * NR];
 #pragma unroll
     for (int R = 0; R < NR; ++R) {
-      src[4 * R + 0] = pslot(P, P_RZ0, R, maxp);
-      src[4 * R + 1] = pslot(P, P_PQ, R, maxp);
-      src[4 * R + 2] = pslot(P, P_RN0, R, maxp);
+      src[4 * R + 0] = pslot(P, P_RZ0 + par, R, maxp);
+      src[4 * R + 1] = pslot(P, P_PQ0 + par, R, maxp);
+      src[4 * R + 2] = pslot(P, P_RN0 + par, R, maxp);
       src[4 * R + 3] = pslot(P, P_FN, R, maxp);
       cnt[4 * R + 0] = cn.apply;
       cnt[4 * R + 1] = cn.apply;
@@ -555,40 +882,13 @@ __global__ void __launch_bounds__(kVecBlock)
   }
   T al[NR], be[NR];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-  const int rd = (step + 1) & 1, wr = step & 1;
 #pragma unroll
   for (int R = 0; R < NR; ++R) {
-    const double gam = pre[4 * R], del = pre[4 * R + 1], rn = sqrt(pre[4 * R + 2]), fn = sqrt(pre[4 * R + 3]);
-    bool done = sc->done[R] != 0.0 || (rtol > 0.0 && rn <= rtol * fn);
-    double alpha = 0.0, beta = 0.0, status = 0.0;
-    if (!done) {
-      double denom = del;
-      if (!first) {
-        beta = gam / sc->cg_gamma[rd][R];
-        denom = del - beta * gam / sc->cg_alpha[rd][R];
-      }
-      if (denom > 0.0 && isfinite(denom) && isfinite(gam)) {
-        alpha = gam / denom;
-      } else if (gam == 0.0) {
-        done = true;
-        beta = 0.0;
-      } else {
-        status = isfinite(denom) && isfinite(gam) ? (double)FBTO_ERR_BREAKDOWN : (double)FBTO_ERR_NONFINITE;
-        done = true;
-        beta = 0.0;
-      }
-    }
+    double alpha, beta;
+    cg_coefficients(pre[4 * R], pre[4 * R + 1], pre[4 * R + 2], pre[4 * R + 3], R, step, rtol, sc, lead, alpha,
+                    beta);
     al[R] = (T)alpha;
     be[R] = (T)beta;
-    if (lead) {
-      sc->cg_gamma[wr][R] = gam;
-      sc->cg_alpha[wr][R] = alpha;
-      if (done) sc->done[R] = 1.0;
-      if (status != 0.0) sc->status[R] = status;
-      if (alpha != 0.0) sc->steps[R] += 1.0;
-      sc->alpha[R] = alpha;
-      sc->beta[R] = beta;
-    }
   }
 
   double v[2 * NR + 1];
@@ -611,7 +911,7 @@ __global__ void __launch_bounds__(kVecBlock)
         s[o] = sn;
         x[o] = xn;
         r[o] = rn;
-        z[o] = dv[k] * rn;
+        if (z_out) z_out[o] = dv[k] * rn;
         v[2 * R] += (double)rn * (double)rn;
         v[2 * R + 1] = fmax(v[2 * R + 1], fabs((double)rn));
         if (f) v[2 * NR] += (double)f[o] * (double)xn;
@@ -621,8 +921,8 @@ __global__ void __launch_bounds__(kVecBlock)
   double* dst[2 * NR + 1];
 #pragma unroll
   for (int R = 0; R < NR; ++R) {
-    dst[2 * R] = pslot(P, P_RN1, R, maxp);
-    dst[2 * R + 1] = pslot(P, P_RI1, R, maxp);
+    dst[2 * R] = pslot(P, P_RNF, R, maxp);
+    dst[2 * R + 1] = pslot(P, P_RIF, R, maxp);
   }
   dst[2 * NR] = pslot(P, P_DOT, 0, maxp);
   write_parts<2 * NR + 1, 0xAAAu>(v, dst, blockIdx.x);
@@ -640,8 +940,8 @@ __global__ void __launch_bounds__(kVecBlock)
   int cnt[3 * NR + 4];
 #pragma unroll
   for (int R = 0; R < NR; ++R) {
-    src[3 * R + 0] = pslot(P, P_RN1, R, maxp);
-    src[3 * R + 1] = pslot(P, P_RI1, R, maxp);
+    src[3 * R + 0] = pslot(P, P_RNF, R, maxp);
+    src[3 * R + 1] = pslot(P, P_RIF, R, maxp);
     src[3 * R + 2] = pslot(P, P_FN, R, maxp);
     cnt[3 * R + 0] = n_r;
     cnt[3 * R + 1] = n_r;
@@ -702,14 +1002,15 @@ __global__ void __launch_bounds__(kVecBlock)
   }
 
 template <typename T>
-hipError_t launch_cg_step(fbto_grid_s* g, T* x, T* r, T* z, const T* w, T* p, T* s, const T* invD, const T* f,
-                          int nrhs, int n_apply, int n_fn, int step, double rtol, hipStream_t st, int* nb_out) {
+hipError_t launch_cg_step(fbto_grid_s* g, const T* x_in, T* x, T* r, const T* z_in, T* z_out, const T* w, T* p,
+                          T* s, const T* invD, const T* f, int nrhs, int n_apply, int n_fn, int step,
+                          double rtol, hipStream_t st, int* nb_out) {
   const int nb = vec_blocks(g->geo.ndof);
   if (nb_out) *nb_out = nb;
   const CgCnt cn{n_apply, n_fn};
   FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_cg_step<T, NR>), dim3(nb), dim3(kVecBlock), 0, st, g->geo.ndof,
-                                            x, r, z, w, p, s, invD, f, g->partials, g->max_partials, cn, step,
-                                            rtol, g->sc));
+                                            x_in, x, r, z_in, z_out, w, p, s, invD, f, g->partials,
+                                            g->max_partials, cn, step, rtol, g->sc));
   return hipGetLastError();
 }
 hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot, int n_e,
@@ -1289,10 +1590,13 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   template hipError_t launch_apply<T>(fbto_grid_s*, const T*, const T*, T*, int, hipStream_t);         \
   template hipError_t launch_resid<T>(fbto_grid_s*, const T*, const T*, const T*, T*, const T*, T*, int, \
                                       hipStream_t, int*);                                              \
-  template hipError_t launch_apply_cg<T>(fbto_grid_s*, const T*, const T*, const T*, T*, int, hipStream_t, \
-                                         int*);                                                        \
-  template hipError_t launch_cg_step<T>(fbto_grid_s*, T*, T*, T*, const T*, T*, T*, const T*, const T*,  \
-                                        int, int, int, int, double, hipStream_t, int*);                \
+  template hipError_t launch_apply_cg<T>(fbto_grid_s*, const T*, const T*, const T*, T*, int, int,     \
+                                         hipStream_t, int*);                                           \
+  template hipError_t launch_cg_step<T>(fbto_grid_s*, const T*, T*, T*, const T*, T*, const T*, T*, T*, \
+                                        const T*, const T*, int, int, int, int, double, hipStream_t,   \
+                                        int*);                                                         \
+  template hipError_t launch_cg_fused<T>(fbto_grid_s*, const T*, const CgSet<T>&, const CgSet<T>&,      \
+                                         const T*, int, int, int, int, double, hipStream_t, int*);      \
   template hipError_t launch_diag<T>(fbto_grid_s*, const T*, T*, hipStream_t);                         \
   template hipError_t launch_relax_update<T>(fbto_grid_s*, T*, const T*, const T*, int, double, int,    \
                                              hipStream_t);                                             \
