@@ -247,7 +247,8 @@ struct ApplyStage {
 // Loads of one node plane for the fused CG step (one RHS).
 template <typename T>
 struct FusedStage {
-  T x[3], r[2][3], p[2][3], s[2][3], w[2][3], d[2][3];
+  T x[3], p[3];                           // owned node only
+  T r[2][3], s[2][3], w[2][3], d[2][3];
   unsigned m[2];
 };
 
@@ -384,12 +385,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         S.r[sl][c] = A.ri[o + c];
         S.w[sl][c] = A.wi[o + c];
         S.d[sl][c] = A.invD[3 * n + c];
-        S.p[sl][c] = first ? (T)0 : A.pi[o + c];
         S.s[sl][c] = first ? (T)0 : A.si[o + c];
       }
-      if (sl == 0 && writer && own_plane) {
+      if (sl == 0 && writer && own_plane) {  // p and x only where the update is stored
 #pragma unroll
-        for (int c = 0; c < 3; ++c) S.x[c] = A.xi[o + c];
+        for (int c = 0; c < 3; ++c) {
+          S.x[c] = A.xi[o + c];
+          S.p[c] = first ? (T)0 : A.pi[o + c];
+        }
       }
     }
   };
@@ -403,13 +406,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       const int64_t o = (int64_t)rhs0 * G.ndof + 3 * (owner ? gcol[0] + k * plane : 0);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T z = S.d[sl][c] * S.r[sl][c];
-        const T pn = z + be * S.p[sl][c];
         const T sn = S.w[sl][c] + be * S.s[sl][c];
         const T rn = S.r[sl][c] - al * sn;
         const T zn = S.d[sl][c] * rn;
         nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : zn;
         if (owner) {
+          const T pn = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
           A.xo[o + c] = S.x[c] + al * pn;
           A.ro[o + c] = rn;
           A.po[o + c] = pn;
@@ -619,7 +621,7 @@ static size_t apply_lds_bytes(int bx, int by) {
 // latency, not issue, sets the time.
 template <typename T, int NR, int MODE>
 static TileChoice choose_tile(const Geo& G, int n_cu) {
-  const char* env = getenv("FBTO_APPLY_TILE");
+  const char* env = getenv(MODE == MODE_CGF ? "FBTO_CGF_TILE" : "FBTO_APPLY_TILE");
   int want_bx = 0, want_by = 0, want_dz = 0;
   if (env) sscanf(env, "%dx%dx%d", &want_bx, &want_by, &want_dz);
   constexpr double kMinWaves = 8.0;
@@ -824,7 +826,7 @@ hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st) {
 // (block 0 writes the slot no block of this kernel reads).  Convergence and
 // breakdown are decided identically in every block.
 // ===========================================================================
-constexpr int kU = 4;
+constexpr int kU = 8;
 
 struct CgCnt {
   int apply;   // partials of the last apply (gamma, delta, r.r, max|r|)

@@ -1,7 +1,7 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
     python -m paper_2204_06204_amd.profiling stats <kernel_stats.csv> <steps> <title> <command>
-    python -m paper_2204_06204_amd.profiling pmc <fetch_dir> <write_dir> <copy_bytes> <title> <command>
+    python -m paper_2204_06204_amd.profiling pmc <fetch_dir> <write_dir> <copy_bytes> <title> <command> [json_out]
 
 `stats` turns a --kernel-trace --stats CSV into a table of kernels with calls,
 average duration and share.  `pmc` combines a FETCH_SIZE run and a
@@ -68,8 +68,12 @@ def pmc_summary(fetch_dir: str, write_dir: str, copy_bytes: float, title: str, c
     def pick(per, key):
         vals = [v for n, vs in per.items() if key in n for v in vs]
         return sum(vals) / len(vals) if vals else None
-    copy_f = pick(res["FETCH_SIZE"], "copy") or pick(res["FETCH_SIZE"], "elementwise")
-    copy_w = pick(res["WRITE_SIZE"], "copy") or pick(res["WRITE_SIZE"], "elementwise")
+    def calib(per):
+        # the calibration kernel: b = 2 a over copy_bytes (torch's MulFunctor)
+        vals = [sum(v) / len(v) for n, v in per.items() if "MulFunctor" in n]
+        return max(vals) if vals else None
+    copy_f = calib(res["FETCH_SIZE"])
+    copy_w = calib(res["WRITE_SIZE"])
     sf = copy_bytes / copy_f if copy_f else None
     sw = copy_bytes / copy_w if copy_w else None
     lines = [f"# {title}", "", f"Command: `{command}`", "", f"kernel_hash: {kernel_hash()}",
@@ -90,4 +94,9 @@ if __name__ == "__main__":
     if sys.argv[1] == "stats":
         print(stats_table(sys.argv[2], float(sys.argv[3]), sys.argv[4], sys.argv[5]), end="")
     elif sys.argv[1] == "pmc":
-        print(pmc_summary(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6]), end="")
+        text = pmc_summary(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6])
+        print(text, end="")
+        if len(sys.argv) > 7:
+            block = text.split("```json", 1)[1].split("```", 1)[0]
+            with open(sys.argv[7], "w") as fh:
+                fh.write(block.strip() + "\n")
