@@ -588,7 +588,14 @@ fbto_status_t fbto_solve_refined(fbto_grid_t g, fbto_prec_t inner_prec, const do
       if ((s = pcg_solve<double>(g, rho_phys, (const double*)B.f, (double*)B.d, nrhs, inner_steps, inner_rtol, st))) return s;
       HIP_TRY(launch_axpy64(u, (const double*)B.d, n, st));
     }
-    total_inner += inner_steps;
+    // inner steps taken (the largest over the RHS), read back with the
+    // refinement loop's own synchronisation budget: one copy per refinement
+    double steps_h[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(steps_h, g->sc->steps, sizeof(steps_h), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    double mx = 0.0;
+    for (int R = 0; R < nrhs; ++R) mx = std::max(mx, steps_h[R]);
+    total_inner += mx;
   }
   // final norms are in the scalars (from the last FP64 residual)
   if (info) HIP_TRY(launch_solve_info(g, info, nrhs, total_inner, st));
