@@ -211,8 +211,7 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   CgSet<T> set[2] = {{x, (T*)V.r[0], (T*)V.p[0], (T*)V.s[0], (T*)V.w[0]},
                      {(T*)V.x1, (T*)V.r[1], (T*)V.p[1], (T*)V.s[1], (T*)V.w[1]}};
   int nb_a = 0, nb_v = 0;
-  HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  HIP_TRY(launch_resid<T>(g, rho, x, f, set[0].r, invD, z, nrhs, st, &nb_a));
+  HIP_TRY(launch_resid_diag<T>(g, rho, x, f, set[0].r, invD, z, nrhs, st, &nb_a));
   CgCounts cn{nb_a, nb_a};
   if (steps == 0) {
     if (f_dot) HIP_TRY(launch_dot<T>(g, f, x, nrhs, st));

@@ -85,11 +85,22 @@ __device__ __forceinline__ void reduce_parts(double (&v)[NV], const double* cons
                                              const int (&n)[NV]) {
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  // four strided loads in flight per thread and array, folded in a fixed order
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const bool is_max = (MAXMASK >> i) & 1u;
-    double acc = is_max ? -INFINITY : 0.0;
-    for (int k = tid; k < n[i]; k += nthr) acc = is_max ? fmax(acc, src[i][k]) : acc + src[i][k];
+    const double id = is_max ? -INFINITY : 0.0;
+    double acc = id;
+    for (int k = tid; k < n[i]; k += 4 * nthr) {
+      double x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k + u * nthr;
+        x[u] = kk < n[i] ? src[i][kk] : id;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = is_max ? fmax(acc, x[u]) : acc + x[u];
+    }
     v[i] = acc;
   }
   block_reduce<NV, MAXMASK>(v);

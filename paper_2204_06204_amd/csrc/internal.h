@@ -172,6 +172,11 @@ hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs
 template <typename T>
 hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD,
                         T* z, int nrhs, hipStream_t st, int* nb_out);
+// Residual apply that also forms the Jacobi diagonal (stored to invD_out)
+// from the densities it reads, instead of a separate diagonal kernel.
+template <typename T>
+hipError_t launch_resid_diag(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, T* invD_out, T* z,
+                             int nrhs, hipStream_t st, int* nb_out);
 template <typename T>
 hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, int step,
                            hipStream_t st, int* nb_out);

@@ -114,6 +114,8 @@ struct ApplyArgs {
   T* y;
   const T* f;          // RESID
   const T* invD;       // RESID (optional): start of a CG solve
+  T* invD_out;         // RESID (optional): the Jacobi diagonal is formed here and stored
+  double ke_diag;      // diagonal entry of KE (with invD_out)
   T* z;                // RESID: z = D^-1 r
   const T* r;          // CG: current residual (for r.z, r.r)
   const uint8_t* mask; // bits 0-2: fixed DOFs of the node; bit 3: the node has a spring
@@ -266,6 +268,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int TS = BX * BY;
   T* nodes = reinterpret_cast<T*>(apply_smem);   // [2][NR][3][NS]
   T* corners = nodes + 2 * NR * 3 * NS;          // [2][NR][9][TS]
+  T* dcorn = corners + 2 * NR * 9 * TS;          // [2][TS] density sums of the diagonal
 
   // The block is padded to whole waves (the DPP reductions read every lane
   // of a wave); padding threads mirror thread 0 and store nothing.
@@ -454,6 +457,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     issue(ez0 + 2, S[0]);
   }
   T s_cur = load_s(ez0);
+  T s_below = (T)0;  // s of the element below (diagonal of the residual mode)
   __syncthreads();
   read_face(ez0 & 1, F[0], own[0]);
   __syncthreads();  // the first layer restages the buffer of plane ez0
@@ -466,6 +470,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       if (ez + 3 <= kend) issue(ez + 3, S[P ^ 1]);
     }
     const T s = s_cur;
+    const T dcol = s_below + s;  // this column's share of the lower-face nodes' diagonal
+    s_below = s;
     if (ez + 1 < kend) s_cur = load_s(ez + 1);
     read_face((ez + 1) & 1, F[P ^ 1], own[P ^ 1]);
     const bool emit = ez >= k0;  // uniform over the block
@@ -481,6 +487,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 #pragma unroll
           for (int c = 0; c < 3; ++c)
             corners[((cb * NR + r) * 9 + (a - 1) * 3 + c) * TS + tid] = out[r][a][c];
+      if constexpr (MODE == MODE_RESID) {
+        if (A.invD_out) dcorn[cb * TS + tid] = dcol;
+      }
     }
     if (ez + 2 <= kend) {
       if constexpr (MODE == MODE_CGF) {
@@ -535,10 +544,28 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
             rv[c] = fv[c] - acc[c];
             A.y[o + c] = rv[c];
           }
-          if (A.invD) {
+          if (A.invD || A.invD_out) {
+            T dv[3];
+            if (A.invD_out) {  // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements
+              const T D = ((dcol + dcorn[cb * TS + tid - 1]) + dcorn[cb * TS + tid - BX]) +
+                          dcorn[cb * TS + tid - BX - 1];
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                T d = (T)A.ke_diag * D;
+                if (m & 8u)
+                  for (int sI = 0; sI < A.nspring; ++sI)
+                    if (A.sdof[sI] == (int64_t)(3 * n + c)) d += A.sk[sI];
+                if ((m >> c) & 1u) d = (T)1;
+                dv[c] = d > (T)0 ? (T)1 / d : (T)0;
+                A.invD_out[3 * n + c] = dv[c];
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) dv[c] = A.invD[3 * n + c];
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              A.z[o + c] = A.invD[3 * n + c] * rv[c];
+              A.z[o + c] = dv[c] * rv[c];
               part[4 * r + 0] += (double)rv[c] * (double)rv[c];
               part[4 * r + 1] = fmax(part[4 * r + 1], fabs((double)rv[c]));
               part[4 * r + 2] += (double)fv[c] * (double)fv[c];
@@ -586,7 +613,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     write_parts<4 * NR, 0x8888u>(part, dst, lb);
   }
   if constexpr (MODE == MODE_RESID) {
-    if (A.invD == nullptr) return;
+    if (A.invD == nullptr && A.invD_out == nullptr) return;
     if (lb == 0 && tid == 0) {   // a new solve starts from this residual
       Scalars* sc = const_cast<Scalars*>(A.sc);
       for (int r = 0; r < NR; ++r) {
@@ -612,7 +639,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 
 template <typename T, int NR>
 static size_t apply_lds_bytes(int bx, int by) {
-  return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by);
+  return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by + 2 * bx * by);
 }
 
 // Tile shape and slab depth for one apply variant.  The cost is the work of
@@ -731,6 +758,20 @@ hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T*
   A.y = r;
   A.f = f;
   A.invD = invD;
+  A.z = z;
+  return launch_apply_mode<T, MODE_RESID>(g, A, nrhs, st, nb_out);
+}
+
+template <typename T>
+hipError_t launch_resid_diag(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, T* invD_out, T* z,
+                             int nrhs, hipStream_t st, int* nb_out) {
+  ApplyArgs<T> A{};
+  A.rho = rho;
+  A.u = u;
+  A.y = r;
+  A.f = f;
+  A.invD_out = invD_out;
+  A.ke_diag = g->ke_diag;
   A.z = z;
   return launch_apply_mode<T, MODE_RESID>(g, A, nrhs, st, nb_out);
 }
@@ -934,7 +975,7 @@ __global__ void __launch_bounds__(kVecBlock)
 // partials, f.f from FN); with `info`, also write the outer-iteration record
 // (compliance from DOT, projection results, gradient mean).
 template <int NR>
-__global__ void __launch_bounds__(kVecBlock)
+__global__ void __launch_bounds__(1024)
     k_pcg_finish(const double* P, int maxp, int n_r, int n_fn, Scalars* sc, double* info, int n_dot, int n_e,
                  int n_gsum, int64_t E) {
   double v[3 * NR + 4];
@@ -1017,7 +1058,7 @@ hipError_t launch_cg_step(fbto_grid_s* g, const T* x_in, T* x, T* r, const T* z_
 }
 hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot, int n_e,
                              int n_gsum, hipStream_t st) {
-  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_finish<NR>), dim3(1), dim3(kVecBlock), 0, st,
+  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_finish<NR>), dim3(1), dim3(1024), 0, st,
                                             (const double*)g->partials, g->max_partials, n_r, n_fn, g->sc, info,
                                             n_dot, n_e, n_gsum, g->geo.E));
   return hipGetLastError();
@@ -1592,6 +1633,8 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   template hipError_t launch_apply<T>(fbto_grid_s*, const T*, const T*, T*, int, hipStream_t);         \
   template hipError_t launch_resid<T>(fbto_grid_s*, const T*, const T*, const T*, T*, const T*, T*, int, \
                                       hipStream_t, int*);                                              \
+  template hipError_t launch_resid_diag<T>(fbto_grid_s*, const T*, const T*, const T*, T*, T*, T*, int,  \
+                                           hipStream_t, int*);                                         \
   template hipError_t launch_apply_cg<T>(fbto_grid_s*, const T*, const T*, const T*, T*, int, int,     \
                                          hipStream_t, int*);                                           \
   template hipError_t launch_cg_step<T>(fbto_grid_s*, const T*, T*, T*, const T*, T*, const T*, T*, T*, \
