@@ -324,7 +324,7 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
   const int nbD = vec_blocks(g->geo.ndof);
-  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, nbD, nbE, nbE, st));
+  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, nbD, nbE, g->n_gsum, st));
   return FBTO_OK;
 }
 

@@ -156,6 +156,7 @@ struct fbto_grid_s {
   fbto::Vecs v64, v32;
   int device = 0;
   int n_cu = 256;
+  int n_gsum = 0;                        // blocks of the last filter launch that left a sum
   fbto::TileChoice tiles[2][2][4] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
 };
 

@@ -1210,6 +1210,80 @@ __global__ void __launch_bounds__(kVecBlock)
   }
 }
 
+// Density filter for R <= 1 by z-march: a thread owns element column
+// (ex, ey) of a z-slab and keeps the 2R+1 planes of its (2R+1)^2
+// neighbourhood in registers, so a slab of dz layers reads each input
+// (2R+1)^2 (dz + 2R) / dz times instead of (2R+1)^3.  Out-of-grid
+// neighbours load as 0 (the stencil is truncated at the boundary).
+constexpr int kFiltBX = 64, kFiltBY = 4, kFiltDZ = 4;
+
+template <typename T, int R>
+__global__ void __launch_bounds__(kFiltBX * kFiltBY)
+    k_filter_z(Geo G, int kind, const T* in, T* out, const T* Hsi, StencilW<T, R> W, int want_sum,
+               double* P, int maxp, int tiles_x, int tiles_y) {
+  constexpr int D = 2 * R + 1;
+  const int tx = threadIdx.x % kFiltBX, ty = threadIdx.x / kFiltBX;
+  const int b = blockIdx.x;
+  const int bx = b % tiles_x, t2 = b / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
+  const int ex = bx * kFiltBX + tx, ey = by * kFiltBY + ty;
+  const int z0 = bz * kFiltDZ, z1 = min(z0 + kFiltDZ, G.nz);
+  const bool col = ex < G.nx && ey < G.ny;
+  const int plane = G.nx * G.ny;
+  bool okxy[D][D];
+  int offxy[D][D];
+#pragma unroll
+  for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+    for (int dx = 0; dx < D; ++dx) {
+      const int jx = ex + dx - R, jy = ey + dy - R;
+      okxy[dy][dx] = col && jx >= 0 && jx < G.nx && jy >= 0 && jy < G.ny;
+      offxy[dy][dx] = okxy[dy][dx] ? jx + G.nx * jy : 0;
+    }
+  T win[D][D][D];  // [plane][dy][dx]
+  auto load_plane = [&](int jz, T (&pl)[D][D]) {
+    const bool zok = jz >= 0 && jz < G.nz;
+#pragma unroll
+    for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < D; ++dx) {
+        const bool ok = okxy[dy][dx] && zok;
+        const int j = ok ? offxy[dy][dx] + jz * plane : 0;
+        T v = in[j];
+        if (kind == FILT_TRANS) v *= Hsi[j];
+        pl[dy][dx] = ok ? v : (T)0;
+      }
+  };
+#pragma unroll
+  for (int p = 0; p < D - 1; ++p) load_plane(z0 - R + p, win[p]);
+  double vs[1] = {0.0};
+  for (int ez = z0; ez < z1; ++ez) {
+    load_plane(ez + R, win[D - 1]);
+    T acc = (T)0;
+#pragma unroll
+    for (int dz = 0; dz < D; ++dz)
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < D; ++dx) acc += W.w[dx + D * (dy + D * dz)] * win[dz][dy][dx];
+    if (col) {
+      const int e = ex + G.nx * (ey + G.ny * ez);
+      const T res = kind == FILT_FWD ? acc * Hsi[e] : acc;
+      out[e] = res;
+      vs[0] += (double)res;
+    }
+#pragma unroll
+    for (int p = 0; p < D - 1; ++p)
+#pragma unroll
+      for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < D; ++dx) win[p][dy][dx] = win[p + 1][dy][dx];
+  }
+  if (want_sum) {
+    double* dst[1] = {pslot(P, P_GSUM, 0, maxp)};
+    write_parts<1, 0u>(vs, dst, blockIdx.x);
+  }
+}
+
 // Generic gather for wide stencils (R > 2): offsets and weights from memory.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
@@ -1277,10 +1351,21 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
   const double r = g->desc.filter_radius;
   const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
   const T* Hsi = (const T*)V.Hs;
-  if (R == 0)
-    hipLaunchKernelGGL((k_filter<T, 0>), dim3(nb), dim3(kVecBlock), 0, st, g->geo, kind, in, out, Hsi,
-                       stencil_weights<T, 0>(r), want_sum, g->partials, g->max_partials);
-  else if (R == 1)
+  const Geo& G = g->geo;
+  const int tiles_x = (G.nx + kFiltBX - 1) / kFiltBX, tiles_y = (G.ny + kFiltBY - 1) / kFiltBY;
+  const int64_t nbz = (int64_t)tiles_x * tiles_y * ((G.nz + kFiltDZ - 1) / kFiltDZ);
+  if (R <= 1 && nbz <= g->max_partials) {
+    if (want_sum) g->n_gsum = (int)nbz;
+    if (R == 0)
+      hipLaunchKernelGGL((k_filter_z<T, 0>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out, Hsi,
+                         stencil_weights<T, 0>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y);
+    else
+      hipLaunchKernelGGL((k_filter_z<T, 1>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out, Hsi,
+                         stencil_weights<T, 1>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y);
+    return hipGetLastError();
+  }
+  if (want_sum) g->n_gsum = nb;
+  if (R <= 1)
     hipLaunchKernelGGL((k_filter<T, 1>), dim3(nb), dim3(kVecBlock), 0, st, g->geo, kind, in, out, Hsi,
                        stencil_weights<T, 1>(r), want_sum, g->partials, g->max_partials);
   else if (R == 2)
@@ -1540,7 +1625,7 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
                        int mean_project, double lo, double hi, hipStream_t st) {
   const int nb = vec_blocks(g->geo.E);
   hipLaunchKernelGGL((k_step<T>), dim3(nb), dim3(kVecBlock), 0, st, g->geo.E, x, gx, y, half_alpha,
-                     mean_project, lo, hi, g->partials, g->max_partials, nb);
+                     mean_project, lo, hi, g->partials, g->max_partials, g->n_gsum);
   return hipGetLastError();
 }
 
