@@ -179,6 +179,7 @@ void drop_extra(fbto_grid_s* g) {
 // step.  Returns the partial counts the finish kernel needs.
 struct CgCounts {
   int r, fn;
+  int dot;  // partials of f . x (final vector step, or the dot kernel)
 };
 
 // Diagnostics: FBTO_CG_TRACE=1 prints the reduced partial set of parity
@@ -204,7 +205,8 @@ static void cg_trace(fbto_grid_s* g, hipStream_t st, const char* what, int k, in
 
 template <typename T>
 fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, int steps,
-                      double rtol, hipStream_t st, bool f_dot, CgCounts* cn_out) {
+                      double rtol, hipStream_t st, bool f_dot, CgCounts* cn_out, T* sens = nullptr,
+                      const T* sens_hsi = nullptr, bool* sens_done = nullptr) {
   Vecs& V = vecs<T>(g);
   T* invD = (T*)V.invD;
   T* z = (T*)V.q;
@@ -212,7 +214,7 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
                      {(T*)V.x1, (T*)V.r[1], (T*)V.p[1], (T*)V.s[1], (T*)V.w[1]}};
   int nb_a = 0, nb_v = 0;
   HIP_TRY(launch_resid_diag<T>(g, rho, x, f, set[0].r, invD, z, nrhs, st, &nb_a));
-  CgCounts cn{nb_a, nb_a};
+  CgCounts cn{nb_a, nb_a, vec_blocks(g->geo.ndof)};
   if (steps == 0) {
     if (f_dot) HIP_TRY(launch_dot<T>(g, f, x, nrhs, st));
     *cn_out = cn;
@@ -263,11 +265,22 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
       }
     }
   }
-  // last vector update of step k, into the caller's x
+  // last vector update of step k, into the caller's x; with one RHS and a
+  // sensitivity wanted, fused with it
   const CgSet<T>& cur = set[sizeof(T) == 4 ? (k & 1) : 0];
-  HIP_TRY(launch_cg_step<T>(g, cur.x, x, cur.r, nullptr, nullptr, cur.w, cur.p, cur.s, invD, f_dot ? f : nullptr,
-                            nrhs, nb_a, cn.fn, k, rtol, st, &nb_v));
+  // The fused kernel reads x at halo nodes while their owners store x', so it
+  // may only run when its input and output are different buffers: after an
+  // odd number of fused steps, when the input is the second set.
+  if (sens && nrhs == 1 && cur.x != x) {
+    HIP_TRY(launch_cg_sens<T>(g, rho, cur, x, invD, f_dot ? f : nullptr, sens, sens_hsi, k, nb_a, cn.fn, rtol, st,
+                              &nb_v));
+    if (sens_done) *sens_done = true;
+  } else {
+    HIP_TRY(launch_cg_step<T>(g, cur.x, x, cur.r, nullptr, nullptr, cur.w, cur.p, cur.s, invD,
+                              f_dot ? f : nullptr, nrhs, nb_a, cn.fn, k, rtol, st, &nb_v));
+  }
   cn.r = nb_v;
+  cn.dot = nb_v;
   *cn_out = cn;
   return FBTO_OK;
 }
@@ -314,17 +327,18 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   T* rho = (T*)V.rho;
   HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
   CgCounts cn{};
-  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn);
+  bool sens_done = false;
+  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn, (T*)V.ge, (const T*)V.Hs,
+                               &sens_done);
   if (s != FBTO_OK) return s;
   // element gradient already divided by Hs, so the filter transpose is a plain sum
-  HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
+  if (!sens_done) HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
   HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 1, st));
   const double alpha_k = alpha0 * std::pow((double)k, -0.75);
   HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
   HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
-  const int nbD = vec_blocks(g->geo.ndof);
-  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, nbD, nbE, g->n_gsum, st));
+  HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
   return FBTO_OK;
 }
 

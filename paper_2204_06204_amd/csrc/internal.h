@@ -157,7 +157,7 @@ struct fbto_grid_s {
   int device = 0;
   int n_cu = 256;
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
-  fbto::TileChoice tiles[2][2][4] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
+  fbto::TileChoice tiles[2][2][5] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
 };
 
 namespace fbto {
@@ -189,6 +189,13 @@ hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, con
                            hipStream_t st, int* nb_out);
 template <typename T>
 hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
+// The last CG step k (one RHS) fused with the sensitivity: x = x_in + alpha p
+// into `x`, final residual norms and f . x into the partial slots, and
+// dobj_e = -ds_e x_e^T KE x_e (times Hsi_e when given).
+template <typename T>
+hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x, const T* invD, const T* f,
+                          T* dobj, const T* Hsi, int step, int n_apply, int n_fn, double rtol, hipStream_t st,
+                          int* nb_out);
 // Vector update of CG step k: x = x_in + alpha p, r, p, s in place; z from
 // z_in or D^-1 r; z_out optional (the next unfused product's input).
 template <typename T>

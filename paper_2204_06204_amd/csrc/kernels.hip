@@ -101,7 +101,7 @@ static int flat_grid(int64_t n) {
 //          Input and output sets are distinct buffers: halo nodes of a tile
 //          are read by its neighbours while their owner writes the update.
 // ===========================================================================
-enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3 };
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4 };
 constexpr int kApplyMaxThreads = 512;
 constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
@@ -135,6 +135,10 @@ struct ApplyArgs {
   T *xo, *ro, *po, *so;              // step k + 1's x, r, p, s (w goes to y)
   int n_apply, n_fn;                 // partial counts of step k's product and of f.f
   double rtol;
+  // SENSF only (last CG step fused with the sensitivity)
+  T* dobj;                           // [E] -ds_e x_e^T KE x_e (times Hsi_e)
+  const T* Hsi;                      // [E] 1/Hs_e, or NULL
+  const T* fvec;                     // loads, for f . x (NULL: not formed)
 };
 
 // Step coefficients of the Chronopoulos-Gear recurrence for one RHS from
@@ -637,6 +641,196 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   }
 }
 
+// ===========================================================================
+// The last Chronopoulos-Gear step of a solve fused with the sensitivity of
+// Sec. 3 (one RHS).  On the tiling of k_apply, every staged node gets
+// x' = x + alpha (D^-1 r + beta p); the owner of the node stores x', and
+// forms r' = r - alpha (w + beta s) for the final residual norms and f . x'.
+// Each element owned by the block gets
+//   dobj_e = -ds_e x'_e^T KE x'_e  (times 1/Hs_e when given)
+// from the face modes of its two faces.  Nothing is scattered back to the
+// nodes, so there is no corner exchange; one barrier per layer guards the
+// double-buffered node planes.
+// ===========================================================================
+template <typename T>
+struct SensStage {
+  T x[2][3], r[2][3], p[2][3], d[2][3];  // every staged node
+  T w[3], s[3], f[3];                    // owned node only
+  unsigned m[2];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kApplyMaxThreads)
+    k_cg_sens(ApplyArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char apply_smem[];
+  const int b = blockIdx.x;
+  const int lb = (b & 7) * A.per_xcd + (b >> 3);
+  if (lb >= A.nblocks) return;
+  const Geo G = A.g;
+  const int BX = A.bx, BY = A.by;
+  const int NW = BX + 1;
+  const int NS = NW * (BY + 1);
+  const int TS = BX * BY;
+  T* nodes = reinterpret_cast<T*>(apply_smem);  // [2][3][NS]
+  const int tid = threadIdx.x;
+  const bool live = tid < TS;
+  const int tl = live ? tid : 0;
+  const int ty = tl / BX, tx = tl - ty * BX;
+  const int bxi = lb % A.tiles_x;
+  const int t2 = lb / A.tiles_x;
+  const int byi = t2 % A.tiles_y;
+  const int bz = t2 / A.tiles_y;
+  const int x0 = bxi * (BX - 1) - 1, y0 = byi * (BY - 1) - 1;
+  const int ex = x0 + tx, ey = y0 + ty;
+  const int k0 = bz * A.dz;
+  const int kend = min(k0 + A.dz, G.nz + 1);
+  const int ez0 = k0 == 0 ? 0 : k0 - 1;
+  const int elem_end = min(k0 + A.dz, G.nz);   // element layers [k0, elem_end) belong to this slab
+  const int plane = G.nxn * G.nyn;
+  const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
+  const bool elem_owner = writer && ex < G.nx && ey < G.ny;
+  const bool has_extra = tid <= BX + BY;
+  int li[2], gcol[2];
+  li[0] = tx + NW * ty;
+  gcol[0] = (ex >= 0 && ex <= G.nx && ey >= 0 && ey <= G.ny) ? ex + G.nxn * ey : -1;
+  {
+    const int lx = tid <= BY ? BX : tid - BY - 1;
+    const int ly = tid <= BY ? tid : BY;
+    const int i1 = x0 + lx, j1 = y0 + ly;
+    li[1] = has_extra ? lx + NW * ly : 0;
+    gcol[1] = (has_extra && i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1;
+  }
+
+  // step coefficients (every block, same order)
+  const bool first = A.step == 0;
+  T al, be;
+  {
+    const int par = A.step & 1;
+    double pre[4];
+    const double* src[4] = {pslot(A.P, P_RZ0 + par, 0, A.maxp), pslot(A.P, P_PQ0 + par, 0, A.maxp),
+                            pslot(A.P, P_RN0 + par, 0, A.maxp), pslot(A.P, P_FN, 0, A.maxp)};
+    const int cnt[4] = {A.n_apply, A.n_apply, A.n_apply, A.n_fn};
+    reduce_parts<4, 0u>(pre, src, cnt);
+    double alpha, beta;
+    cg_coefficients(pre[0], pre[1], pre[2], pre[3], 0, A.step, A.rtol, const_cast<Scalars*>(A.sc),
+                    lb == 0 && tid == 0, alpha, beta);
+    al = (T)alpha;
+    be = (T)beta;
+  }
+  double part[3] = {0.0, 0.0, 0.0};  // r'.r', max|r'|, f.x'
+
+  auto issue = [&](int k, SensStage<T>& S) {
+    const bool kv = k >= 0 && k <= G.nz;
+    const bool own = kv && writer && k >= k0 && k < kend;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+      const bool ok = kv && gcol[sl] >= 0;
+      const int n = ok ? gcol[sl] + k * plane : 0;
+      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        S.x[sl][c] = A.xi[3 * n + c];
+        S.r[sl][c] = A.ri[3 * n + c];
+        S.d[sl][c] = A.invD[3 * n + c];
+        S.p[sl][c] = first ? (T)0 : A.pi[3 * n + c];
+      }
+      if (sl == 0 && own) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          S.w[c] = A.wi[3 * n + c];
+          S.s[c] = first ? (T)0 : A.si[3 * n + c];
+          S.f[c] = A.fvec ? A.fvec[3 * n + c] : (T)0;
+        }
+      }
+    }
+  };
+  auto stage = [&](const SensStage<T>& S, int buf, int k) {
+    T* nb = nodes + buf * (3 * NS);
+    const bool own = k >= 0 && k <= G.nz && writer && k >= k0 && k < kend;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) break;
+      const int n = (sl == 0 && own) ? gcol[0] + k * plane : 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T pn = S.d[sl][c] * S.r[sl][c] + be * S.p[sl][c];
+        const T xn = S.x[sl][c] + al * pn;
+        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : xn;
+        if (sl == 0 && own) {
+          A.xo[3 * n + c] = xn;
+          const T rn = S.r[0][c] - al * (S.w[c] + be * S.s[c]);
+          part[0] += (double)rn * (double)rn;
+          part[1] = fmax(part[1], fabs((double)rn));
+          part[2] += (double)S.f[c] * (double)xn;
+        }
+      }
+    }
+  };
+  auto read_face = [&](int buf, T (&F)[4][3]) {
+    const T* nb = nodes + buf * (3 * NS);
+    const int o4[4] = {0, 1, NW, NW + 1};
+    T u4[4][3];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) u4[a][c] = nb[c * NS + li[0] + o4[a]];
+    face_modes(u4, F);
+  };
+
+  SensStage<T> S;
+  T F[2][4][3];
+  issue(ez0, S);
+  stage(S, ez0 & 1, ez0);
+  issue(ez0 + 1, S);
+  stage(S, (ez0 + 1) & 1, ez0 + 1);
+  __syncthreads();
+  read_face(ez0 & 1, F[0]);
+  __syncthreads();
+
+  auto layer = [&](auto parity, int ez) {
+    constexpr int P = decltype(parity)::value;
+    if (ez + 2 <= kend) issue(ez + 2, S);
+    read_face((ez + 1) & 1, F[P ^ 1]);
+    if (elem_owner && ez >= k0 && ez < elem_end) {
+      T c[3][8], z[3][8];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        c[i][0] = (T)0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q) c[i][q] = F[P][q][i] + F[P ^ 1][q][i];
+          c[i][q + 4] = F[P ^ 1][q][i] - F[P][q][i];
+        }
+      }
+      modal_ke(c, A.km, z);
+      double en = 0.0;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int q = 1; q < 8; ++q) en += (double)c[i][q] * (double)z[i][q];
+      const int e = ex + G.nx * (ey + G.ny * ez);
+      double val = -(double)simp_ds<T>(A.rho[e], A.sp) * en;
+      if (A.Hsi) val *= (double)A.Hsi[e];
+      A.dobj[e] = (T)val;
+    }
+    if (ez + 2 <= kend) stage(S, ez & 1, ez + 2);
+    __syncthreads();
+  };
+  for (int ez = ez0; ez < kend; ez += 2) {
+    layer(std::integral_constant<int, 0>{}, ez);
+    if (ez + 1 >= kend) break;
+    layer(std::integral_constant<int, 1>{}, ez + 1);
+  }
+  double* dst[3] = {pslot(A.P, P_RNF, 0, A.maxp), pslot(A.P, P_RIF, 0, A.maxp), pslot(A.P, P_DOT, 0, A.maxp)};
+  write_parts<3, 0x2u>(part, dst, lb);
+}
+
+template <typename T>
+static size_t sens_lds_bytes(int bx, int by) {
+  return sizeof(T) * (size_t)(2 * 3 * (bx + 1) * (by + 1));
+}
+
 template <typename T, int NR>
 static size_t apply_lds_bytes(int bx, int by) {
   return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by + 2 * bx * by);
@@ -660,14 +854,16 @@ static TileChoice choose_tile(const Geo& G, int n_cu) {
       if (want_by && by != want_by) continue;
       const int ts = bx * by;
       if (ts < 128 || ts > kApplyMaxThreads) continue;
-      const size_t lds = apply_lds_bytes<T, NR>(bx, by);
+      const size_t lds = MODE == MODE_SENSF ? sens_lds_bytes<T>(bx, by) : apply_lds_bytes<T, NR>(bx, by);
       if (lds > kApplyMaxLds) continue;
       const int waves = (ts + 63) / 64;
       int occ = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, 64 * waves, lds) !=
-              hipSuccess ||
-          occ < 1)
-        continue;
+      hipError_t oe;
+      if constexpr (MODE == MODE_SENSF)
+        oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_cg_sens<T>, 64 * waves, lds);
+      else
+        oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, 64 * waves, lds);
+      if (oe != hipSuccess || occ < 1) continue;
       const int tiles_x = (G.nxn + bx - 2) / (bx - 1);
       const int tiles_y = (G.nyn + by - 2) / (by - 1);
       for (int dz = 1; dz <= std::min(G.nzn, 64); ++dz) {
@@ -786,6 +982,51 @@ hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r,
   A.y = w;
   A.step = step;
   return launch_apply_mode<T, MODE_CG>(g, A, nrhs, st, nb_out);
+}
+
+template <typename T>
+hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x, const T* invD, const T* f,
+                          T* dobj, const T* Hsi, int step, int n_apply, int n_fn, double rtol, hipStream_t st,
+                          int* nb_out) {
+  TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][0][MODE_SENSF];
+  if (t.nblocks == 0) {
+    t = choose_tile<T, 1, MODE_SENSF>(g->geo, g->n_cu);
+    if (t.nblocks == 0) return hipErrorInvalidConfiguration;
+  }
+  if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
+  if (nb_out) *nb_out = t.nblocks;
+  ApplyArgs<T> A{};
+  A.g = g->geo;
+  A.mask = g->mask;
+  A.km = modal_of<T>(g);
+  A.sp = g->simp;
+  A.P = g->partials;
+  A.maxp = g->max_partials;
+  A.sc = g->sc;
+  A.rho = rho;
+  A.invD = invD;
+  A.xi = in.x; A.ri = in.r; A.pi = in.p; A.si = in.s; A.wi = in.w;
+  A.xo = x;
+  A.dobj = dobj;
+  A.Hsi = Hsi;
+  A.fvec = f;
+  A.step = step;
+  A.n_apply = n_apply;
+  A.n_fn = n_fn;
+  A.rtol = rtol;
+  A.bx = t.bx;
+  A.by = t.by;
+  A.tiles_x = t.tiles_x;
+  A.tiles_y = t.tiles_y;
+  A.slabs = t.slabs;
+  A.dz = t.dz;
+  A.nblocks = t.nblocks;
+  A.per_xcd = (t.nblocks + 7) / 8;
+  const int grid = A.per_xcd * 8;
+  const int threads = (t.bx * t.by + 63) / 64 * 64;
+  const size_t lds = sens_lds_bytes<T>(t.bx, t.by);
+  hipLaunchKernelGGL((k_cg_sens<T>), dim3(grid), dim3(threads), lds, st, A);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -1725,6 +1966,8 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   template hipError_t launch_cg_step<T>(fbto_grid_s*, const T*, T*, T*, const T*, T*, const T*, T*, T*, \
                                         const T*, const T*, int, int, int, int, double, hipStream_t,   \
                                         int*);                                                         \
+  template hipError_t launch_cg_sens<T>(fbto_grid_s*, const T*, const CgSet<T>&, T*, const T*, const T*, \
+                                        T*, const T*, int, int, int, double, hipStream_t, int*);       \
   template hipError_t launch_cg_fused<T>(fbto_grid_s*, const T*, const CgSet<T>&, const CgSet<T>&,      \
                                          const T*, int, int, int, int, double, hipStream_t, int*);      \
   template hipError_t launch_diag<T>(fbto_grid_s*, const T*, T*, hipStream_t);                         \

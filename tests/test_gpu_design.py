@@ -149,6 +149,23 @@ def test_outer_fp32_tracks_fp64_small():
     assert dc <= 1e-3 and dx <= 1e-3
 
 
+@pytest.mark.parametrize("inner", [7, 8])
+def test_outer_fp32_one_step_against_oracle(inner):
+    """One FP32 outer step on a grid of several tiles.  With an even number
+    of PCG steps the last step is fused with the sensitivity (8), with an odd
+    number it is not (7); both match the FP64 oracle to FP32 accuracy."""
+    say(f"outer fp32 one step, {inner} inner")
+    p = synth.cantilever(40, 20, 12, volfrac=0.25, filter_radius=2.0, outer_iters=2, inner_steps=inner, seed=3)
+    alpha0 = 0.002
+    recs, xs, u = _run_gpu(p, 2, alpha0, torch.float32)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 2, alpha0, p.inner_steps, 0.0, 1.0, p.vmax)
+    for k in range(2):
+        assert abs(recs[k][0] - rrecs[k].compliance) <= 2e-5 * abs(rrecs[k].compliance), k
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= 2e-5, (k, np.abs(xs[k] - rxs[k + 1]).max())
+    assert np.abs(u - ur[0]).max() <= 1e-4 * np.abs(ur).max()
+
+
 def test_outer_multiload_and_springs():
     """Multi-load (summed compliance) and a spring-loaded inverter grid: one
     FP64 outer iteration against the oracle."""
