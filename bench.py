@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fixed-err", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-sizes", action="store_true",
+                    help="skip the K(rho)u timings at 256x128x128 and 384x192x192")
     ap.add_argument("--profile-only", choices=["apply", "outer"], default=None,
                     help="run only a short loop of one kind (for rocprofv3)")
     return ap.parse_args()
@@ -157,11 +159,50 @@ def fixed_error(g, p, torch, rtol=1e-8):
     cmix = float(torch.dot(f, u2))
     out["rtol"] = rtol
     out["fp64_pcg"] = {"seconds": t64, "pcg_steps": i64[3], "rel_residual": i64[0] / i64[2]}
-    out["fp32_pcg_fp64_refine"] = {"seconds": tmix, "inner_steps": imix[3], "refinements": nref,
+    out["fp32_pcg_fp64_refine"] = {"seconds": tmix, "inner_steps_taken": imix[3], "refinements": nref,
                                    "inner_rtol": 1e-3,
                                    "rel_residual": imix[0] / imix[2],
                                    "compliance_rel_diff_vs_fp64": abs(cmix - c64) / abs(c64)}
     out["speedup_mixed_vs_fp64"] = t64 / tmix if tmix > 0 else None
+    return out
+
+
+def apply_sizes(torch):
+    """K(rho)u at the two larger workloads (bridge 256x128x128, cantilever
+    384x192x192 with 1 and 4 load cases): GDOF/s and HBM fraction of the
+    algorithmic bytes, warm, from HIP events on the launch stream."""
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+    out = {}
+    dev = torch.device("cuda:0")
+    for name, nrhs_list in (("cfg4", (1,)), ("cfg5", (1, 4))):
+        p = synth.config(name)
+        g = Grid.from_problem(p, max_rhs=max(nrhs_list))
+        st = torch.cuda.current_stream()
+        for dtype, b in ((torch.float32, 4), (torch.float64, 8)):
+            for nr in nrhs_list:
+                if nr > 1 and dtype == torch.float64:
+                    continue
+                rho = torch.tensor(p.x0, dtype=dtype, device=dev)
+                u = torch.randn(nr * p.ndof, dtype=dtype, device=dev,
+                                generator=torch.Generator(device=dev).manual_seed(1))
+                y = torch.empty_like(u)
+                for _ in range(3):
+                    g.apply_K(rho, u, y)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(20):
+                    g.apply_K(rho, u, y)
+                e1.record(st)
+                torch.cuda.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3 / 20
+                nbytes = 2 * nr * p.ndof * b + p.E * b
+                out[f"{name}_{'fp32' if b == 4 else 'fp64'}_rhs{nr}"] = {
+                    "us": t * 1e6, "gdof_s": nr * p.ndof / t / 1e9, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS,
+                    "grid": [p.nx, p.ny, p.nz]}
+                del rho, u, y
+        g.close()
+        torch.cuda.empty_cache()
     return out
 
 
@@ -239,6 +280,7 @@ def main():
     traffic = measured_traffic("k_apply<float, 1, 0>")
 
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
+    sizes = None if args.no_sizes else apply_sizes(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(p, args.cpu_seconds)
 
     value = args.steps / dt32
@@ -270,6 +312,7 @@ def main():
             "fp32_cold_hbm_frac": bytes32 / t_apply32_cold / 1e9 / HBM_PEAK_GBS,
             "fp64_cold_hbm_frac": bytes64 / t_apply64_cold / 1e9 / HBM_PEAK_GBS,
         },
+        "apply_K_sizes": sizes,
         "fp64_path": {"outer_iter_s": steps64 / dt64, "ms_per_step": dt64 / steps64 * 1e3},
         "final_state": {"fp32": st32, "fp64": st64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

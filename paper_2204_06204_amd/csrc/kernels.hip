@@ -1855,9 +1855,14 @@ __global__ void __launch_bounds__(kVecBlock)
   write_parts<2, 0x2u>(v, dst, blockIdx.x);
 }
 
-static int proj_passes() {
+// Pass budget of the projection.  From a cold start the search takes up to
+// six passes on the workloads here; warm-started from the previous
+// multiplier (the outer loop) it takes one or two, so four leave margin.  A
+// search that runs out of passes ends on the feasible end of its bracket and
+// says so in the status.
+static int proj_passes(bool seeded) {
   const char* env = getenv("FBTO_PROJ_PASSES");
-  int p = env ? atoi(env) : 8;
+  int p = env ? atoi(env) : (seeded ? 4 : 8);
   return p < 1 ? 1 : (p > 64 ? 64 : p);
 }
 
@@ -1879,7 +1884,7 @@ hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi
     hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, g->partials,
                        g->max_partials);
   }
-  const int passes = proj_passes();
+  const int passes = proj_passes(seeded != 0);
   for (int p = 0; p < passes; ++p) {
     hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p,
                        g->partials, g->max_partials, nb, g->sc);
