@@ -105,6 +105,8 @@ enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4
 constexpr int kApplyMaxThreads = 512;
 constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
+constexpr int kSinkStride = 16;  // sink entries per thread
+static_assert(kApplyMaxThreads * kSinkStride * sizeof(double) <= kSinkBytes, "sink too small");
 
 template <typename T>
 struct ApplyArgs {
@@ -119,6 +121,7 @@ struct ApplyArgs {
   T* z;                // RESID: z = D^-1 r
   const T* r;          // CG: current residual (for r.z, r.r)
   const uint8_t* mask; // bits 0-2: fixed DOFs of the node; bit 3: the node has a spring
+  T* sink;             // [kApplyMaxThreads * kSinkStride]: stores of threads without an owned node
   Modal<T> km;
   Simp sp;
   int nspring;
@@ -271,7 +274,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int NS = NW * (BY + 1);   // LDS nodes per plane
   const int TS = BX * BY;
   T* nodes = reinterpret_cast<T*>(apply_smem);   // [2][NR][3][NS]
-  T* corners = nodes + 2 * NR * 3 * NS;          // [2][NR][9][TS]
+  T* corners = nodes + 2 * NR * 3 * NS;         // [2][NR][9][TS]
   T* dcorn = corners + 2 * NR * 9 * TS;          // [2][TS] density sums of the diagonal
 
   // The block is padded to whole waves (the DPP reductions read every lane
@@ -294,7 +297,13 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
 
   // node columns staged by this thread: slot 0 its own (ex, ey), slot 1 one
-  // node of the tile's far column / row (threads 0 .. BX + BY)
+  // node of the tile's far column / row (threads 0 .. BX + BY).
+  // Every memory operation of the z-march is issued unconditionally (threads
+  // without a far node re-read their own node and stage it once more; planes
+  // past the slab load clamped addresses; stores without an owner go to the
+  // sink).  With no branch around them the compiler can
+  // count the loads in flight and wait only for the ones it consumes, so
+  // the planes prefetched for the next layers stay in flight.
   const bool has_extra = tid <= BX + BY;
   int li[2], gcol[2];
   li[0] = tx + NW * ty;
@@ -303,18 +312,18 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     const int lx = tid <= BY ? BX : tid - BY - 1;
     const int ly = tid <= BY ? tid : BY;
     const int i1 = x0 + lx, j1 = y0 + ly;
-    li[1] = has_extra ? lx + NW * ly : 0;
-    gcol[1] = (has_extra && i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1;
+    li[1] = has_extra ? lx + NW * ly : li[0];  // the own node again: the same value, same thread
+    gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
   }
 
   auto issue = [&](int k, ApplyStage<T, NR>& S) {
     const bool kv = k >= 0 && k <= G.nz;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
       const bool ok = kv && gcol[sl] >= 0;
       const int n = ok ? gcol[sl] + k * plane : 0;
-      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
+      const unsigned mv = A.mask[n];
+      S.m[sl] = ok ? mv : 7u;
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -325,7 +334,6 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     T* nb = nodes + buf * (NR * 3 * NS);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -348,9 +356,16 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       face_modes(u4, F[r]);
     }
   };
-  auto load_s = [&](int ez) -> T {
+  // The density of the next layer is loaded raw and turned into s_e only
+  // when it is used: consuming a load right after it was issued would make
+  // the wave wait for every load issued before it (the counter is in order),
+  // including the node planes prefetched for the next layers.
+  auto load_rho = [&](int ez) -> T {
     const bool el = col_elem && ez >= 0 && ez < G.nz;
-    const T rv = A.rho[el ? ex + G.nx * (ey + G.ny * ez) : 0];
+    return A.rho[el ? ex + G.nx * (ey + G.ny * ez) : 0];
+  };
+  auto scale_of = [&](int ez, T rv) -> T {
+    const bool el = col_elem && ez >= 0 && ez < G.nz;
     return el ? simp_s<T>(rv, A.sp) : (T)0;
   };
 
@@ -382,51 +397,68 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
       const bool ok = kv && gcol[sl] >= 0;
       const int n = ok ? gcol[sl] + k * plane : 0;
       const int64_t o = (int64_t)rhs0 * G.ndof + 3 * n;
-      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
+      const unsigned mv = A.mask[n];
+      S.m[sl] = ok ? mv : 7u;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         S.r[sl][c] = A.ri[o + c];
         S.w[sl][c] = A.wi[o + c];
         S.d[sl][c] = A.invD[3 * n + c];
-        S.s[sl][c] = first ? (T)0 : A.si[o + c];
+        const T sv = A.si[o + c];  // allocated on the first step too, its contents unused
+        S.s[sl][c] = first ? (T)0 : sv;
       }
-      if (sl == 0 && writer && own_plane) {  // p and x only where the update is stored
+      if (sl == 0) {  // p and x are used where the update is stored
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           S.x[c] = A.xi[o + c];
-          S.p[c] = first ? (T)0 : A.pi[o + c];
+          const T pv = A.pi[o + c];
+          S.p[c] = first ? (T)0 : pv;
         }
       }
     }
   };
-  auto stage_f = [&](const FusedStage<T>& S, int buf, int k) {
+  auto stage_f = [&](const FusedStage<T>& S, int buf, int k, T (&zq)[3]) {
     T* nb = nodes + buf * (3 * NS);
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
       const bool owner = sl == 0 && writer && own_plane;  // the owner's node index is valid
       const int64_t o = (int64_t)rhs0 * G.ndof + 3 * (owner ? gcol[0] + k * plane : 0);
+      T* const sink = A.sink + kSinkStride * tid;
+      T* xo = owner ? A.xo + o : sink;
+      T* ro = owner ? A.ro + o : sink + 3;
+      T* po = owner ? A.po + o : sink + 6;
+      T* so = owner ? A.so + o : sink + 9;
+      T xn[3], rn[3], pn[3], sn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T sn = S.w[sl][c] + be * S.s[sl][c];
-        const T rn = S.r[sl][c] - al * sn;
-        const T zn = S.d[sl][c] * rn;
+        sn[c] = S.w[sl][c] + be * S.s[sl][c];
+        rn[c] = S.r[sl][c] - al * sn[c];
+        const T zn = S.d[sl][c] * rn[c];
         nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : zn;
-        if (owner) {
-          const T pn = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
-          A.xo[o + c] = S.x[c] + al * pn;
-          A.ro[o + c] = rn;
-          A.po[o + c] = pn;
-          A.so[o + c] = sn;
-          part[0] += (double)rn * (double)zn;  // r.z
-          part[2] += (double)rn * (double)rn;  // r.r
-          part[3] = fmax(part[3], fabs((double)rn));
+        if (sl == 0) {
+          zq[c] = zn;  // unmasked: the output of a fixed DOF
+          pn[c] = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
+          xn[c] = S.x[c] + al * pn[c];
+          if (owner) {
+            part[0] += (double)rn[c] * (double)zn;  // r.z
+            part[2] += (double)rn[c] * (double)rn[c];  // r.r
+            part[3] = fmax(part[3], fabs((double)rn[c]));
+          }
         }
+      }
+      if (sl == 0) {  // one vector per output (the four may alias: sink)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ro[c] = rn[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) po[c] = pn[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) so[c] = sn[c];
       }
     }
   };
@@ -444,13 +476,16 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int c = 0; c < 3; ++c) carry[r][q][c] = (T)0;
 
   // prologue: planes ez0, ez0 + 1 staged (and, unfused, plane ez0 + 2 in flight)
-  unsigned mq;  // masks of the own node, plane ez in byte 0, ez + 1 in byte 1, ..
+  unsigned mq;     // masks of the own node, plane ez in byte 0, ez + 1 in byte 1, ..
+  T rq[3][NR][3];  // unmasked input value of the own node, planes ez, ez + 1, ez + 2
+  T rho_next;
   if constexpr (MODE == MODE_CGF) {
     issue_f(ez0, SF);
-    stage_f(SF, ez0 & 1, ez0);
+    stage_f(SF, ez0 & 1, ez0, rq[0][0]);
     mq = SF.m[0] & 0xffu;
+    rho_next = load_rho(ez0);  // the density before the plane, as in every layer
     issue_f(ez0 + 1, SF);
-    stage_f(SF, (ez0 + 1) & 1, ez0 + 1);
+    stage_f(SF, (ez0 + 1) & 1, ez0 + 1, rq[1][0]);
     mq |= (SF.m[0] & 0xffu) << 8;
   } else {
     issue(ez0, S[0]);
@@ -458,9 +493,18 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     stage(S[0], ez0 & 1);
     stage(S[1], (ez0 + 1) & 1);
     mq = (S[0].m[0] & 0xffu) | ((S[1].m[0] & 0xffu) << 8);
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rq[0][r][c] = S[0].v[0][r][c];
+        rq[1][r][c] = S[1].v[0][r][c];
+      }
+    // the density first, then the next plane: as in every layer, so that
+    // the wait for the density leaves the plane's loads in flight
+    rho_next = load_rho(ez0);
     issue(ez0 + 2, S[0]);
   }
-  T s_cur = load_s(ez0);
   T s_below = (T)0;  // s of the element below (diagonal of the residual mode)
   __syncthreads();
   read_face(ez0 & 1, F[0], own[0]);
@@ -468,15 +512,15 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 
   auto layer = [&](auto parity, int ez) {
     constexpr int P = decltype(parity)::value;
+    const T s = scale_of(ez, rho_next);
+    rho_next = load_rho(ez + 1);
     if constexpr (MODE == MODE_CGF) {
-      if (ez + 2 <= kend) issue_f(ez + 2, SF);
+      issue_f(ez + 2, SF);
     } else {
-      if (ez + 3 <= kend) issue(ez + 3, S[P ^ 1]);
+      issue(ez + 3, S[P ^ 1]);
     }
-    const T s = s_cur;
     const T dcol = s_below + s;  // this column's share of the lower-face nodes' diagonal
     s_below = s;
-    if (ez + 1 < kend) s_cur = load_s(ez + 1);
     read_face((ez + 1) & 1, F[P ^ 1], own[P ^ 1]);
     const bool emit = ez >= k0;  // uniform over the block
     T out[NR][4][3];
@@ -495,19 +539,26 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         if (A.invD_out) dcorn[cb * TS + tid] = dcol;
       }
     }
-    if (ez + 2 <= kend) {
-      if constexpr (MODE == MODE_CGF) {
-        stage_f(SF, ez & 1, ez + 2);
-        mq |= (SF.m[0] & 0xffu) << 16;
-      } else {
-        stage(S[P], ez & 1);
-        mq |= (S[P].m[0] & 0xffu) << 16;
-      }
+    if constexpr (MODE == MODE_CGF) {
+      stage_f(SF, ez & 1, ez + 2, rq[2][0]);
+      mq |= (SF.m[0] & 0xffu) << 16;
+    } else {
+      stage(S[P], ez & 1);
+      mq |= (S[P].m[0] & 0xffu) << 16;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) rq[2][r][c] = S[P].v[0][r][c];
     }
     __syncthreads();
-    if (emit && writer) {
-      const int n = gcol[0] + ez * plane;
-      const unsigned m = mq & 0xffu;
+    {
+      // every thread runs the output code; a thread that owns no output node
+      // reads its own LDS slots and a valid node, and stores to the sink
+      const bool wr = emit && writer;
+      const int n = wr ? gcol[0] + ez * plane : 0;
+      const unsigned m = wr ? (mq & 0xffu) : 0u;
+      const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - BX : tl, tlbb = wr ? tid - BX - 1 : tl;
+      T* const sink = A.sink + kSinkStride * tid;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const T* cr = corners + (cb * NR + r) * 9 * TS;
@@ -515,8 +566,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         T acc[3], pv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          acc[c] = ((out[r][0][c] + cr[(0 + c) * TS + tid - 1]) + cr[(3 + c) * TS + tid - BX]) +
-                   cr[(6 + c) * TS + tid - BX - 1];
+          acc[c] = ((out[r][0][c] + cr[(0 + c) * TS + tl1]) + cr[(3 + c) * TS + tlb]) + cr[(6 + c) * TS + tlbb];
           pv[c] = own[P][r][c];  // masked input value at this node
         }
         if (m) {  // springs, then identity rows of fixed DOFs (rare nodes)
@@ -530,72 +580,76 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           }
 #pragma unroll
           for (int c = 0; c < 3; ++c)
-            if ((m >> c) & 1u) {
-              if constexpr (MODE == MODE_CGF) {  // unmasked z' of this DOF, as staged
-                const T sn = A.wi[o + c] + be * (first ? (T)0 : A.si[o + c]);
-                pv[c] = A.invD[3 * n + c] * (A.ri[o + c] - al * sn);
-              } else {
-                pv[c] = A.u[o + c];
-              }
+            if ((m >> c) & 1u) {  // the unmasked input value, as staged
+              pv[c] = rq[0][r][c];
               acc[c] = pv[c];
             }
         }
+        // partial sums count owned nodes only (a select: values of a thread
+        // without an owned node may be anything, NaN included)
+        auto own_only = [wr](double v) { return wr ? v : 0.0; };
         if constexpr (MODE == MODE_RESID) {
-          T fv[3], rv[3];
+          const bool zout = A.invD || A.invD_out;
+          T* const yd = wr ? A.y + o : sink;
+          T* const zd = (wr && zout) ? A.z + o : sink + 3;
+          const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // a valid address either way
+          T fv[3], rv[3], dv[3];
+          const T D = ((dcol + dcorn[cb * TS + tl1]) + dcorn[cb * TS + tlb]) + dcorn[cb * TS + tlbb];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             fv[c] = A.f[o + c];
+            const T dl = dsrc[c];
             rv[c] = fv[c] - acc[c];
-            A.y[o + c] = rv[c];
-          }
-          if (A.invD || A.invD_out) {
-            T dv[3];
+            yd[c] = rv[c];
             if (A.invD_out) {  // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements
-              const T D = ((dcol + dcorn[cb * TS + tid - 1]) + dcorn[cb * TS + tid - BX]) +
-                          dcorn[cb * TS + tid - BX - 1];
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                T d = (T)A.ke_diag * D;
-                if (m & 8u)
-                  for (int sI = 0; sI < A.nspring; ++sI)
-                    if (A.sdof[sI] == (int64_t)(3 * n + c)) d += A.sk[sI];
-                if ((m >> c) & 1u) d = (T)1;
-                dv[c] = d > (T)0 ? (T)1 / d : (T)0;
-                A.invD_out[3 * n + c] = dv[c];
-              }
+              T d = (T)A.ke_diag * D;
+              if (m & 8u)
+                for (int sI = 0; sI < A.nspring; ++sI)
+                  if (A.sdof[sI] == (int64_t)(3 * n + c)) d += A.sk[sI];
+              if ((m >> c) & 1u) d = (T)1;
+              dv[c] = d > (T)0 ? (T)1 / d : (T)0;
             } else {
-#pragma unroll
-              for (int c = 0; c < 3; ++c) dv[c] = A.invD[3 * n + c];
+              dv[c] = dl;
             }
+          }
+          T* const dd = (wr && A.invD_out) ? A.invD_out + 3 * n : sink + 6;  // sink + 6 .. 8
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              A.z[o + c] = dv[c] * rv[c];
-              part[4 * r + 0] += (double)rv[c] * (double)rv[c];
-              part[4 * r + 1] = fmax(part[4 * r + 1], fabs((double)rv[c]));
-              part[4 * r + 2] += (double)fv[c] * (double)fv[c];
-            }
+          for (int c = 0; c < 3; ++c) {
+            if (A.invD_out) dd[c] = dv[c];
+            zd[c] = dv[c] * rv[c];
+            part[4 * r + 0] += own_only((double)rv[c] * (double)rv[c]);
+            part[4 * r + 1] = fmax(part[4 * r + 1], own_only(fabs((double)rv[c])));
+            part[4 * r + 2] += own_only((double)fv[c] * (double)fv[c]);
           }
         } else {
+          T* const yd = wr ? A.y + o : sink;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) A.y[o + c] = acc[c];
+          for (int c = 0; c < 3; ++c) yd[c] = acc[c];
           if constexpr (MODE == MODE_CG) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const T rv = A.r[o + c];
-              part[4 * r + 0] += (double)rv * (double)pv[c];      // r.z
-              part[4 * r + 1] += (double)acc[c] * (double)pv[c];  // w.z
-              part[4 * r + 2] += (double)rv * (double)rv;         // r.r
-              part[4 * r + 3] = fmax(part[4 * r + 3], fabs((double)rv));
+              part[4 * r + 0] += own_only((double)rv * (double)pv[c]);      // r.z
+              part[4 * r + 1] += own_only((double)acc[c] * (double)pv[c]);  // w.z
+              part[4 * r + 2] += own_only((double)rv * (double)rv);         // r.r
+              part[4 * r + 3] = fmax(part[4 * r + 3], own_only(fabs((double)rv)));
             }
           }
           if constexpr (MODE == MODE_CGF) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) part[1] += (double)acc[c] * (double)pv[c];  // w'.z'
+            for (int c = 0; c < 3; ++c) part[1] += own_only((double)acc[c] * (double)pv[c]);  // w'.z'
           }
         }
       }
     }
     mq >>= 8;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        rq[0][r][c] = rq[1][r][c];
+        rq[1][r][c] = rq[2][r][c];
+      }
   };
   for (int ez = ez0; ez < kend; ez += 2) {
     layer(std::integral_constant<int, 0>{}, ez);
@@ -853,7 +907,9 @@ static TileChoice choose_tile(const Geo& G, int n_cu) {
     for (int by = 4; by <= 64; ++by) {
       if (want_by && by != want_by) continue;
       const int ts = bx * by;
-      if (ts < 128 || ts > kApplyMaxThreads) continue;
+      // at most four waves: every layer ends at a block-wide barrier, and
+      // blocks of up to one wave per SIMD measured fastest
+      if (ts < 128 || ts > 256) continue;
       const size_t lds = MODE == MODE_SENSF ? sens_lds_bytes<T>(bx, by) : apply_lds_bytes<T, NR>(bx, by);
       if (lds > kApplyMaxLds) continue;
       const int waves = (ts + 63) / 64;
@@ -874,8 +930,12 @@ static TileChoice choose_tile(const Geo& G, int n_cu) {
         const int64_t per_cu = (nb + n_cu - 1) / n_cu;
         const int64_t full = per_cu / occ, rem = per_cu % occ;
         const double layers = dz + 2.0;
-        const double cost = full * std::max((double)occ * waves, kMinWaves) * layers +
-                            (rem ? std::max((double)rem * waves, kMinWaves) * layers : 0.0);
+        // a block's waves go to the CU's four SIMDs; a count that does not
+        // spread evenly (3, 5, 6, 7) leaves one SIMD with more work, as if
+        // the block had the next multiple of four
+        const double w = (waves == 1 || waves == 2 || waves == 4 || waves == 8) ? waves : (waves + 3) / 4 * 4;
+        const double cost = full * std::max((double)occ * w, kMinWaves) * layers +
+                            (rem ? std::max((double)rem * w, kMinWaves) * layers : 0.0);
         if (cost < best_cost) {
           best_cost = cost;
           best = TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb};
@@ -927,6 +987,7 @@ static hipError_t launch_apply_mode(fbto_grid_s* g, ApplyArgs<T> A, int nrhs, hi
   A.P = g->partials;
   A.maxp = g->max_partials;
   A.sc = g->sc;
+  A.sink = static_cast<T*>(g->sink);
   // one RHS per launch: the per-RHS state of the z-march (two face-mode
   // sets, the modal carry, staged loads) fills the register file at NR = 1
   hipError_t e = hipSuccess;
