@@ -80,11 +80,13 @@ def pmc_summary(fetch_dir: str, write_dir: str, copy_bytes: float, title: str, c
              f"copy scale fetch: {sf}", f"copy scale write: {sw}", ""]
     data = {"kernel_hash": kernel_hash(), "scale_fetch": sf, "scale_write": sw, "kernels": {}}
     for n in sorted(set(res["FETCH_SIZE"]) | set(res["WRITE_SIZE"])):
+        if "fbto::" not in n and "MulFunctor" not in n:
+            continue  # torch's own set-up kernels
         f = pick(res["FETCH_SIZE"], n)
         w = pick(res["WRITE_SIZE"], n)
         fb = f * sf if (f is not None and sf) else None
         wb = w * sw if (w is not None and sw) else None
-        data["kernels"][n] = {"fetch_bytes": fb, "write_bytes": wb}
+        data["kernels"][n if "fbto::" in n else n[:120]] = {"fetch_bytes": fb, "write_bytes": wb}
         lines.append(f"- `{n[:100]}`: fetch {fb} B, write {wb} B per dispatch")
     lines += ["", "```json", json.dumps(data, indent=1), "```", ""]
     return "\n".join(lines)
