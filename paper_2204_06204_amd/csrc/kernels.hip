@@ -410,11 +410,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         const T sv = A.si[o + c];  // allocated on the first step too, its contents unused
         S.s[sl][c] = first ? (T)0 : sv;
       }
-      if (sl == 0) {  // p and x are used where the update is stored
+      if (sl == 0) {  // p and x are used by the owner only: other threads all read node 0
+        const int64_t oo = (own_plane && writer && ok) ? o : (int64_t)rhs0 * G.ndof;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          S.x[c] = A.xi[o + c];
-          const T pv = A.pi[o + c];
+          S.x[c] = A.xi[oo + c];
+          const T pv = A.pi[oo + c];
           S.p[c] = first ? (T)0 : pv;
         }
       }
@@ -479,6 +480,30 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   unsigned mq;     // masks of the own node, plane ez in byte 0, ez + 1 in byte 1, ..
   T rq[3][NR][3];  // unmasked input value of the own node, planes ez, ez + 1, ez + 2
   T rho_next;
+  // residual and CG modes: values of the own node read only at its output
+  // (RESID: f and D^-1 (or f again); CG: r), loaded one layer ahead.  FP64
+  // loads them at the output instead: the queue would not fit its registers.
+  constexpr bool kOwnQ = sizeof(T) == 4 && (MODE == MODE_RESID || MODE == MODE_CG);
+  T oq[2][NR][2][3];
+  auto load_own = [&](int k, T (&q)[NR][2][3]) {
+    const bool ok = gcol[0] >= 0 && k <= G.nz;
+    const int n = ok ? gcol[0] + k * plane : 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const int64_t o = (int64_t)(rhs0 + r) * G.ndof + 3 * n;
+      if constexpr (MODE == MODE_RESID) {
+        const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // valid either way
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          q[r][0][c] = A.f[o + c];
+          q[r][1][c] = dsrc[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) q[r][0][c] = A.r[o + c];
+      }
+    }
+  };
   if constexpr (MODE == MODE_CGF) {
     issue_f(ez0, SF);
     stage_f(SF, ez0 & 1, ez0, rq[0][0]);
@@ -503,6 +528,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     // the density first, then the next plane: as in every layer, so that
     // the wait for the density leaves the plane's loads in flight
     rho_next = load_rho(ez0);
+    if constexpr (kOwnQ) load_own(ez0, oq[0]);
     issue(ez0 + 2, S[0]);
   }
   T s_below = (T)0;  // s of the element below (diagonal of the residual mode)
@@ -514,6 +540,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     constexpr int P = decltype(parity)::value;
     const T s = scale_of(ez, rho_next);
     rho_next = load_rho(ez + 1);
+    if constexpr (kOwnQ) load_own(ez + 1, oq[P ^ 1]);
     if constexpr (MODE == MODE_CGF) {
       issue_f(ez + 2, SF);
     } else {
@@ -592,15 +619,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           const bool zout = A.invD || A.invD_out;
           T* const yd = wr ? A.y + o : sink;
           T* const zd = (wr && zout) ? A.z + o : sink + 3;
-          const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // a valid address either way
           T fv[3], rv[3], dv[3];
           const T D = ((dcol + dcorn[cb * TS + tl1]) + dcorn[cb * TS + tlb]) + dcorn[cb * TS + tlbb];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            fv[c] = A.f[o + c];
-            const T dl = dsrc[c];
+            const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // valid either way
+            fv[c] = kOwnQ ? oq[P][r][0][c] : A.f[o + c];
+            const T dl = kOwnQ ? oq[P][r][1][c] : dsrc[c];
             rv[c] = fv[c] - acc[c];
-            yd[c] = rv[c];
             if (A.invD_out) {  // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements
               T d = (T)A.ke_diag * D;
               if (m & 8u)
@@ -613,10 +639,17 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
             }
           }
           T* const dd = (wr && A.invD_out) ? A.invD_out + 3 * n : sink + 6;  // sink + 6 .. 8
+          // one vector per output (the outputs may alias: sink)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) yd[c] = rv[c];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) zd[c] = dv[c] * rv[c];
+          if (A.invD_out) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dd[c] = dv[c];
+          }
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            if (A.invD_out) dd[c] = dv[c];
-            zd[c] = dv[c] * rv[c];
             part[4 * r + 0] += own_only((double)rv[c] * (double)rv[c]);
             part[4 * r + 1] = fmax(part[4 * r + 1], own_only(fabs((double)rv[c])));
             part[4 * r + 2] += own_only((double)fv[c] * (double)fv[c]);
@@ -628,7 +661,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           if constexpr (MODE == MODE_CG) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              const T rv = A.r[o + c];
+              const T rv = kOwnQ ? oq[P][r][0][c] : A.r[o + c];
               part[4 * r + 0] += own_only((double)rv * (double)pv[c]);      // r.z
               part[4 * r + 1] += own_only((double)acc[c] * (double)pv[c]);  // w.z
               part[4 * r + 2] += own_only((double)rv * (double)rv);         // r.r
@@ -743,6 +776,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int plane = G.nxn * G.nyn;
   const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
   const bool elem_owner = writer && ex < G.nx && ey < G.ny;
+  // As in k_apply, every load and store of the z-march is issued without a
+  // branch around it: threads without a far node restage their own node,
+  // planes past the slab are loaded and staged but never read, and stores
+  // without an owner go to the sink.
   const bool has_extra = tid <= BX + BY;
   int li[2], gcol[2];
   li[0] = tx + NW * ty;
@@ -751,9 +788,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     const int lx = tid <= BY ? BX : tid - BY - 1;
     const int ly = tid <= BY ? tid : BY;
     const int i1 = x0 + lx, j1 = y0 + ly;
-    li[1] = has_extra ? lx + NW * ly : 0;
-    gcol[1] = (has_extra && i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1;
+    li[1] = has_extra ? lx + NW * ly : li[0];
+    gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
   }
+  T* const sink = A.sink + kSinkStride * tid;
 
   // step coefficients (every block, same order)
   const bool first = A.step == 0;
@@ -778,23 +816,28 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     const bool own = kv && writer && k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
       const bool ok = kv && gcol[sl] >= 0;
       const int n = ok ? gcol[sl] + k * plane : 0;
-      S.m[sl] = ok ? (unsigned)A.mask[n] : 7u;
+      const unsigned mv = A.mask[n];
+      S.m[sl] = ok ? mv : 7u;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         S.x[sl][c] = A.xi[3 * n + c];
         S.r[sl][c] = A.ri[3 * n + c];
         S.d[sl][c] = A.invD[3 * n + c];
-        S.p[sl][c] = first ? (T)0 : A.pi[3 * n + c];
+        const T pv = A.pi[3 * n + c];  // allocated on the first step too, its contents unused
+        S.p[sl][c] = first ? (T)0 : pv;
       }
-      if (sl == 0 && own) {
+      if (sl == 0) {  // used by the owner only: other threads all read node 0 (one cached line)
+        const int no = own ? n : 0;
+        const T* const fsrc = A.fvec ? A.fvec + 3 * no : A.wi + 3 * no;  // valid either way
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          S.w[c] = A.wi[3 * n + c];
-          S.s[c] = first ? (T)0 : A.si[3 * n + c];
-          S.f[c] = A.fvec ? A.fvec[3 * n + c] : (T)0;
+          S.w[c] = A.wi[3 * no + c];
+          const T sv = A.si[3 * no + c];
+          S.s[c] = first ? (T)0 : sv;
+          const T fv = fsrc[c];
+          S.f[c] = A.fvec ? fv : (T)0;
         }
       }
     }
@@ -804,19 +847,23 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     const bool own = k >= 0 && k <= G.nz && writer && k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      if (sl == 1 && !has_extra) break;
-      const int n = (sl == 0 && own) ? gcol[0] + k * plane : 0;
+      T xn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T pn = S.d[sl][c] * S.r[sl][c] + be * S.p[sl][c];
-        const T xn = S.x[sl][c] + al * pn;
-        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : xn;
-        if (sl == 0 && own) {
-          A.xo[3 * n + c] = xn;
+        xn[c] = S.x[sl][c] + al * pn;
+        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : xn[c];
+      }
+      if (sl == 0) {
+        T* const xo = own ? A.xo + 3 * (gcol[0] + k * plane) : sink;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
           const T rn = S.r[0][c] - al * (S.w[c] + be * S.s[c]);
-          part[0] += (double)rn * (double)rn;
-          part[1] = fmax(part[1], fabs((double)rn));
-          part[2] += (double)S.f[c] * (double)xn;
+          part[0] += own ? (double)rn * (double)rn : 0.0;
+          part[1] = fmax(part[1], own ? fabs((double)rn) : 0.0);
+          part[2] += own ? (double)S.f[c] * (double)xn[c] : 0.0;
         }
       }
     }
@@ -831,22 +878,35 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int c = 0; c < 3; ++c) u4[a][c] = nb[c * NS + li[0] + o4[a]];
     face_modes(u4, F);
   };
+  // density and 1/Hs of the element of a layer, loaded a layer ahead
+  const bool col_elem = elem_owner;
+  auto load_elem = [&](int ez, T (&v)[2]) {
+    const bool el = col_elem && ez >= k0 && ez < elem_end;
+    const int e = el ? ex + G.nx * (ey + G.ny * ez) : 0;
+    v[0] = A.rho[e];
+    const T hv = (A.Hsi ? A.Hsi : A.rho)[e];  // valid either way
+    v[1] = A.Hsi ? hv : (T)1;
+  };
 
   SensStage<T> S;
   T F[2][4][3];
+  T ev[2][2];
   issue(ez0, S);
   stage(S, ez0 & 1, ez0);
   issue(ez0 + 1, S);
   stage(S, (ez0 + 1) & 1, ez0 + 1);
+  load_elem(ez0, ev[0]);
   __syncthreads();
   read_face(ez0 & 1, F[0]);
   __syncthreads();
 
   auto layer = [&](auto parity, int ez) {
     constexpr int P = decltype(parity)::value;
-    if (ez + 2 <= kend) issue(ez + 2, S);
+    load_elem(ez + 1, ev[P ^ 1]);
+    issue(ez + 2, S);
     read_face((ez + 1) & 1, F[P ^ 1]);
-    if (elem_owner && ez >= k0 && ez < elem_end) {
+    {
+      const bool el = elem_owner && ez >= k0 && ez < elem_end;
       T c[3][8], z[3][8];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -863,12 +923,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int q = 1; q < 8; ++q) en += (double)c[i][q] * (double)z[i][q];
-      const int e = ex + G.nx * (ey + G.ny * ez);
-      double val = -(double)simp_ds<T>(A.rho[e], A.sp) * en;
-      if (A.Hsi) val *= (double)A.Hsi[e];
-      A.dobj[e] = (T)val;
+      const int e = el ? ex + G.nx * (ey + G.ny * ez) : 0;
+      const double val = -(double)simp_ds<T>(ev[P][0], A.sp) * en * (double)ev[P][1];
+      T* const dst = el ? A.dobj + e : sink + 3;
+      *dst = (T)val;
     }
-    if (ez + 2 <= kend) stage(S, ez & 1, ez + 2);
+    stage(S, ez & 1, ez + 2);
     __syncthreads();
   };
   for (int ez = ez0; ez < kend; ez += 2) {
@@ -1070,6 +1130,7 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
   A.xo = x;
   A.dobj = dobj;
   A.Hsi = Hsi;
+  A.sink = static_cast<T*>(g->sink);
   A.fvec = f;
   A.step = step;
   A.n_apply = n_apply;
@@ -1300,26 +1361,41 @@ __global__ void __launch_bounds__(1024)
   cnt[3 * NR + 1] = info ? n_e : 0;
   cnt[3 * NR + 2] = info ? n_e : 0;
   cnt[3 * NR + 3] = info ? n_gsum : 0;
+  // the scalars read by the lead thread are loaded before the reduction,
+  // so their latency overlaps it
+  double st_in[NR], proj_status = 0.0, lam = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int R = 0; R < NR; ++R) st_in[R] = sc->status[R];
+    proj_status = sc->proj_status;
+    lam = sc->lam;
+  }
   constexpr unsigned MM = 0x492u | (1u << (3 * NR + 2));
   reduce_parts<3 * NR + 4, MM>(v, src, cnt);
   if (threadIdx.x == 0) {
     double rinf = 0.0, rrel = 0.0, status = 0.0;
+#pragma unroll
     for (int R = 0; R < NR; ++R) {
-      sc->rnorm2[R] = sqrt(v[3 * R]);
+      const double rn = sqrt(v[3 * R]), fnrm = sqrt(v[3 * R + 2]);
+      sc->rnorm2[R] = rn;
       sc->rinf[R] = v[3 * R + 1];
-      sc->fnorm2[R] = sqrt(v[3 * R + 2]);
-      if (!isfinite(v[3 * R]) && sc->status[R] == 0.0) sc->status[R] = (double)FBTO_ERR_NONFINITE;
-      rinf = fmax(rinf, sc->rinf[R]);
-      rrel = fmax(rrel, sc->fnorm2[R] > 0.0 ? sc->rnorm2[R] / sc->fnorm2[R] : sc->rnorm2[R]);
-      if (sc->status[R] != 0.0) status = sc->status[R];
+      sc->fnorm2[R] = fnrm;
+      double stR = st_in[R];
+      if (!isfinite(v[3 * R]) && stR == 0.0) {
+        stR = (double)FBTO_ERR_NONFINITE;
+        sc->status[R] = stR;
+      }
+      rinf = fmax(rinf, v[3 * R + 1]);
+      rrel = fmax(rrel, fnrm > 0.0 ? rn / fnrm : rn);
+      if (stR != 0.0) status = stR;
     }
     if (info) {
-      if (sc->proj_status > 0.0) status = sc->proj_status;
+      if (proj_status > 0.0) status = proj_status;
       sc->dot[0] = v[3 * NR];
       info[FBTO_OI_COMPLIANCE] = v[3 * NR];
       info[FBTO_OI_DX_INF] = v[3 * NR + 2];
       info[FBTO_OI_R_INF] = rinf;
-      info[FBTO_OI_LAMBDA] = sc->lam;
+      info[FBTO_OI_LAMBDA] = lam;
       info[FBTO_OI_VOLUME] = v[3 * NR + 1];
       info[FBTO_OI_RREL] = rrel;
       info[FBTO_OI_STATUS] = status;
