@@ -63,24 +63,29 @@ Vecs& vecs<float>(fbto_grid_s* g) { return g->v32; }
 //             W_l(q) = prod_{k != l} M(q_k),
 //   coupling  to component j, mode q ^ (1<<i) ^ (1<<j) when q_i != q_j:
 //             lambda/4 M(q_k) if q_i = d, else mu/4 M(q_k).
+// The diagonal depends on q only through q_i and how many of the other two
+// bits are set (W_l is a product over the other axes), so it is stored as
+// dg[q_i][count] and computed for component 0 at a representative mode.
 void modal_coefficients(double young, double poisson, Modal<double>& km, double& ke_diag) {
   const double lam = young * poisson / ((1.0 + poisson) * (1.0 - 2.0 * poisson));
   const double mu = young / (2.0 * (1.0 + poisson));
   const double M[2] = {0.25, 1.0 / 12.0};
-  for (int i = 0; i < 3; ++i) {
-    for (int q = 0; q < 8; ++q) {
+  for (int qi = 0; qi < 2; ++qi) {
+    for (int cnt = 0; cnt < 3; ++cnt) {
+      const int q = qi | (cnt >= 1 ? 2 : 0) | (cnt >= 2 ? 4 : 0);
       double W[3];
       for (int l = 0; l < 3; ++l) {
         W[l] = 1.0;
         for (int k = 0; k < 3; ++k)
           if (k != l) W[l] *= M[(q >> k) & 1];
       }
-      double d = ((q >> i) & 1) ? (lam + mu) * W[i] : 0.0;
+      double d = qi ? (lam + mu) * W[0] : 0.0;
       for (int l = 0; l < 3; ++l)
         if ((q >> l) & 1) d += mu * W[l];
-      km.dg[i][q] = q == 0 ? 0.0 : d;
+      km.dg[qi][cnt] = d;
     }
   }
+  // dg[0][0] is mode 0 (rigid translation): no energy, computed as 0
   for (int b = 0; b < 2; ++b) {
     km.lam4[b] = 0.25 * lam * M[b];
     km.mu4[b] = 0.25 * mu * M[b];
@@ -398,8 +403,8 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   G.rnxn = 1.0 / G.nxn;
   G.rnyn = 1.0 / G.nyn;
   modal_coefficients(d->young, d->poisson, g->km64, g->ke_diag);
-  for (int i = 0; i < 3; ++i)
-    for (int q = 0; q < 8; ++q) g->km32.dg[i][q] = (float)g->km64.dg[i][q];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 3; ++c) g->km32.dg[a][c] = (float)g->km64.dg[a][c];
   for (int b = 0; b < 2; ++b) {
     g->km32.lam4[b] = (float)g->km64.lam4[b];
     g->km32.mu4[b] = (float)g->km64.mu4[b];

@@ -190,7 +190,7 @@ __device__ __forceinline__ void modal_ke(const T (&c)[3][8], const Modal<T>& km,
   for (int i = 0; i < 3; ++i) {
     z[i][0] = (T)0;
 #pragma unroll
-    for (int q = 1; q < 8; ++q) z[i][q] = km.dg[i][q] * c[i][q];
+    for (int q = 1; q < 8; ++q) z[i][q] = km.dg[(q >> i) & 1][__builtin_popcount((unsigned)q & ~(1u << i))] * c[i][q];
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) {

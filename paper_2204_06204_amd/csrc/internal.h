@@ -21,7 +21,8 @@ struct Geo {
 // Element stiffness in the sum/difference ("modal") basis.  Per axis the
 // two nodal values (u0, u1) map to (u0 + u1, u1 - u0); on the unit cube the
 // 24x24 KE becomes a 45-entry sparse matrix:
-//   diagonal  dg[i][q]                      (component i, mode q)
+//   diagonal  dg[q_i][number of the other two bits of q that are set]
+//             (component i, mode q; by the cube's symmetry six values)
 //   coupling  component i, mode q  <-  component j, mode q ^ (1<<i) ^ (1<<j)
 //             whenever bits i and j of q differ, with weight
 //             lam4[bit k of q] if bit i of q is set, else mu4[bit k of q]
@@ -29,7 +30,7 @@ struct Geo {
 // along axis b.  Derived from the 1D integrals of the basis {1/2, t - 1/2}.
 template <typename T>
 struct Modal {
-  T dg[3][8];
+  T dg[2][3];
   T lam4[2];
   T mu4[2];
 };
