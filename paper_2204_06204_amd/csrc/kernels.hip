@@ -375,10 +375,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 #pragma unroll
   for (int i = 0; i < NP; ++i) part[i] = 0.0;
 
-  // fused CG step: coefficients of step k from its partials (every block)
+  // fused CG step: coefficients of step k from its partials (every block;
+  // called in the prologue, after the first planes' loads are issued, so
+  // the two latencies overlap)
   T al = (T)0, be = (T)0;
   const bool first = A.step == 0;
-  if constexpr (MODE == MODE_CGF) {
+  auto cg_prologue = [&]() {
     const int par = A.step & 1;
     double pre[4];
     const double* src[4] = {pslot(A.P, P_RZ0 + par, rhs0, A.maxp), pslot(A.P, P_PQ0 + par, rhs0, A.maxp),
@@ -390,7 +392,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
                     lb == 0 && tid == 0, alpha, beta);
     al = (T)alpha;
     be = (T)beta;
-  }
+  };
   // fused CG step: loads of one plane, and the update at staging time
   auto issue_f = [&](int k, FusedStage<T>& S) {
     const bool kv = k >= 0 && k <= G.nz;
@@ -505,13 +507,15 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     }
   };
   if constexpr (MODE == MODE_CGF) {
+    FusedStage<T> SF1;
     issue_f(ez0, SF);
+    rho_next = load_rho(ez0);
+    issue_f(ez0 + 1, SF1);
+    cg_prologue();
     stage_f(SF, ez0 & 1, ez0, rq[0][0]);
     mq = SF.m[0] & 0xffu;
-    rho_next = load_rho(ez0);  // the density before the plane, as in every layer
-    issue_f(ez0 + 1, SF);
-    stage_f(SF, (ez0 + 1) & 1, ez0 + 1, rq[1][0]);
-    mq |= (SF.m[0] & 0xffu) << 8;
+    stage_f(SF1, (ez0 + 1) & 1, ez0 + 1, rq[1][0]);
+    mq |= (SF1.m[0] & 0xffu) << 8;
   } else {
     issue(ez0, S[0]);
     issue(ez0 + 1, S[1]);
@@ -793,10 +797,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   }
   T* const sink = A.sink + kSinkStride * tid;
 
-  // step coefficients (every block, same order)
+  // step coefficients (every block, same order; called after the first
+  // planes' loads are issued, so the two latencies overlap)
   const bool first = A.step == 0;
-  T al, be;
-  {
+  T al = (T)0, be = (T)0;
+  auto coefficients = [&]() {
     const int par = A.step & 1;
     double pre[4];
     const double* src[4] = {pslot(A.P, P_RZ0 + par, 0, A.maxp), pslot(A.P, P_PQ0 + par, 0, A.maxp),
@@ -808,7 +813,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
                     lb == 0 && tid == 0, alpha, beta);
     al = (T)alpha;
     be = (T)beta;
-  }
+  };
   double part[3] = {0.0, 0.0, 0.0};  // r'.r', max|r'|, f.x'
 
   auto issue = [&](int k, SensStage<T>& S) {
@@ -891,10 +896,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   SensStage<T> S;
   T F[2][4][3];
   T ev[2][2];
-  issue(ez0, S);
-  stage(S, ez0 & 1, ez0);
-  issue(ez0 + 1, S);
-  stage(S, (ez0 + 1) & 1, ez0 + 1);
+  {
+    SensStage<T> S1;
+    issue(ez0, S);
+    issue(ez0 + 1, S1);
+    coefficients();
+    stage(S, ez0 & 1, ez0);
+    stage(S1, (ez0 + 1) & 1, ez0 + 1);
+  }
   load_elem(ez0, ev[0]);
   __syncthreads();
   read_face(ez0 & 1, F[0]);
