@@ -316,12 +316,16 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
   }
 
+  // Planes past the slab's last one (kend) are staged but never read: their
+  // loads re-read plane kend, which the block has just loaded (a cache hit,
+  // no HBM traffic).
   auto issue = [&](int k, ApplyStage<T, NR>& S) {
-    const bool kv = k >= 0 && k <= G.nz;
+    const int kc = k < kend ? k : kend;
+    const bool kv = kc >= 0 && kc <= G.nz;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + k * plane : 0;
+      const int n = ok ? gcol[sl] + kc * plane : 0;
       const unsigned mv = A.mask[n];
       S.m[sl] = ok ? mv : 7u;
 #pragma unroll
@@ -361,7 +365,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   // the wave wait for every load issued before it (the counter is in order),
   // including the node planes prefetched for the next layers.
   auto load_rho = [&](int ez) -> T {
-    const bool el = col_elem && ez >= 0 && ez < G.nz;
+    const bool el = col_elem && ez >= 0 && ez < G.nz && ez < kend;  // element layers of this block
     return A.rho[el ? ex + G.nx * (ey + G.ny * ez) : 0];
   };
   auto scale_of = [&](int ez, T rv) -> T {
@@ -395,12 +399,13 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   };
   // fused CG step: loads of one plane, and the update at staging time
   auto issue_f = [&](int k, FusedStage<T>& S) {
-    const bool kv = k >= 0 && k <= G.nz;
+    const int kc = k < kend ? k : kend;  // as in issue
+    const bool kv = kc >= 0 && kc <= G.nz;
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + k * plane : 0;
+      const int n = ok ? gcol[sl] + kc * plane : 0;
       const int64_t o = (int64_t)rhs0 * G.ndof + 3 * n;
       const unsigned mv = A.mask[n];
       S.m[sl] = ok ? mv : 7u;
@@ -488,7 +493,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   constexpr bool kOwnQ = sizeof(T) == 4 && (MODE == MODE_RESID || MODE == MODE_CG);
   T oq[2][NR][2][3];
   auto load_own = [&](int k, T (&q)[NR][2][3]) {
-    const bool ok = gcol[0] >= 0 && k <= G.nz;
+    const bool ok = gcol[0] >= 0 && k < kend;  // planes this block outputs
     const int n = ok ? gcol[0] + k * plane : 0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -817,12 +822,13 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   double part[3] = {0.0, 0.0, 0.0};  // r'.r', max|r'|, f.x'
 
   auto issue = [&](int k, SensStage<T>& S) {
-    const bool kv = k >= 0 && k <= G.nz;
-    const bool own = kv && writer && k >= k0 && k < kend;
+    const int kc = k < kend ? k : kend;  // planes past kend are never read: re-load plane kend
+    const bool kv = kc >= 0 && kc <= G.nz;
+    const bool own = k >= 0 && k <= G.nz && writer && k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + k * plane : 0;
+      const int n = ok ? gcol[sl] + kc * plane : 0;
       const unsigned mv = A.mask[n];
       S.m[sl] = ok ? mv : 7u;
 #pragma unroll
