@@ -12,7 +12,9 @@ Prints ONE JSON line (rank 0).  The value is outer iterations per second
 of the FP32 path (FP32 storage and arithmetic, FP64 reductions); the same
 line carries the FP64 path, the K(rho)u rate in GDOF/s with its roofline
 fraction, the time to a fixed residual (FP32 + FP64 refinement vs FP64),
-and the CPU oracle timed on the host cores.
+and the CPU oracle timed on the host cores.  `roofline` is that of the
+kernel that dominates the step, the fused Jacobi-PCG step; `outer_roofline`
+sets the whole iteration against its algorithmic bytes.
 """
 from __future__ import annotations
 
@@ -41,11 +43,11 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel_key: str):
+def measured_traffic(kernel_key: str, summary: str = "apply_K_pmc.json"):
     """HBM bytes (fetch + write) per launch of the named kernel from the
     committed rocprofv3 PMC summary, scaled by the calibration copy, if it
     was taken on the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", "apply_K_pmc.json")
+    path = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(path):
         return None
     try:
@@ -99,11 +101,16 @@ def outer_loop(g, p, dtype, steps, warmup, torch):
                 "volume": inf[4], "status": inf[6], "k_last": k - 1}
 
 
-def apply_timing(g, p, dtype, reps, torch, cold=False):
+def apply_timing(g, p, dtype, reps, torch, cold=False, binary=False):
     """Average duration of one fbto_apply_K launch, from HIP events recorded
-    on the stream the kernel runs on (the current torch stream)."""
+    on the stream the kernel runs on (the current torch stream).  `binary`:
+    a near-binary density (rho_min or 1, 30% solid) instead of the seeded
+    U[0.2, 0.4] field, to show the time does not depend on the data."""
     dev = torch.device("cuda:0")
     rho = torch.tensor(p.x0, dtype=dtype, device=dev)
+    if binary:
+        sel = torch.rand(rho.shape, generator=torch.Generator(device=dev).manual_seed(3), device=dev) < 0.3
+        rho = torch.where(sel, torch.ones_like(rho), torch.full_like(rho, 1e-3))
     u = torch.randn(p.ndof, dtype=dtype, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
     y = torch.empty_like(u)
     st = torch.cuda.current_stream()
@@ -130,6 +137,32 @@ def apply_timing(g, p, dtype, reps, torch, cold=False):
         torch.cuda.synchronize()
         tot += e0.elapsed_time(e1) * 1e-3
     return tot / n
+
+
+def fused_step_timing(g, p, torch, reps=20, n1=9, n2=41):
+    """Average duration of one fused CG step launch (FP32), the kernel that
+    dominates the outer iteration.  A solve of n steps runs n - 1 fused
+    launches beside a fixed set of other kernels, so the difference of the
+    average times of n2- and n1-step solves (HIP events on the launch
+    stream) over n2 - n1 is one fused launch."""
+    dev = torch.device("cuda:0")
+    rho = torch.tensor(p.x0, dtype=torch.float32, device=dev)
+    f = torch.tensor(p.loads[0], dtype=torch.float32, device=dev)
+    u = torch.zeros_like(f)
+    st = torch.cuda.current_stream()
+    def avg(n):
+        tot = 0.0
+        for i in range(reps + 2):
+            u.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            g.inner_solve(rho, f, u, n, rtol=0.0)
+            e1.record(st)
+            torch.cuda.synchronize()
+            if i >= 2:
+                tot += e0.elapsed_time(e1) * 1e-3
+        return tot / reps
+    return (avg(n2) - avg(n1)) / (n2 - n1)
 
 
 def fixed_error(g, p, torch, rtol=1e-8):
@@ -271,12 +304,29 @@ def main():
     t_apply64 = apply_timing(g, p, torch.float64, args.apply_reps, torch)
     t_apply32_cold = apply_timing(g, p, torch.float32, args.apply_reps, torch, cold=True)
     t_apply64_cold = apply_timing(g, p, torch.float64, args.apply_reps, torch, cold=True)
+    t_apply32_bin = apply_timing(g, p, torch.float32, args.apply_reps, torch, binary=True)
+    t_fused = fused_step_timing(g, p, torch)
 
     ndof, E = p.ndof, p.E
+    N = ndof // 3
     bytes32 = 2 * ndof * 4 + E * 4          # read u, write y, read one density per element
     bytes64 = 2 * ndof * 8 + E * 8
-    achieved = bytes32 / t_apply32 / 1e9
-    traffic = measured_traffic("k_apply<float, 1, 0>")
+    # fused CG step: read x, r, p, s, w, D^-1 and write x, r, p, s, w (3N floats
+    # each), read the mask byte per node and one density per element
+    bytes_fused = 11 * ndof * 4 + N + E * 4
+    achieved = bytes_fused / t_fused / 1e9
+    traffic = measured_traffic("k_apply<float, 1, 3>", "outer_step_pmc.json")
+    # algorithmic bytes of one outer iteration (FP32, m inner steps), kernel by kernel
+    m = p.inner_steps
+    bytes_outer = (3 * E * 4                                    # filter: x, 1/Hs in, rho out
+                   + 5 * ndof * 4 + N + E * 4                   # residual: u, f in; r, z, D^-1 out
+                   + 3 * ndof * 4 + N + E * 4                   # step 0 product: z, r in; w out
+                   + (m - 1) * bytes_fused                      # fused steps
+                   + 8 * ndof * 4 + N + 3 * E * 4               # last step + sensitivity: x r p s w D^-1 f in, x out; rho, 1/Hs in, g out
+                   + 2 * E * 4                                  # filter transpose
+                   + 3 * E * 4                                  # step: x, g in, y out
+                   + 2 * E * 4                                  # projection: one or two working passes
+                   + 3 * E * 4)                                 # final projection pass: y, x_old in, x out
 
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
     sizes = None if args.no_sizes else apply_sizes(torch)
@@ -304,6 +354,8 @@ def main():
                    "precision": "fp32 storage and arithmetic, fp64 dot products / norms / projection"},
         "apply_K": {
             "fp32_us": t_apply32 * 1e6, "fp32_gdof_s": ndof / t_apply32 / 1e9,
+            "fp32_hbm_frac": bytes32 / t_apply32 / 1e9 / HBM_PEAK_GBS,
+            "fp32_binary_density_us": t_apply32_bin * 1e6,
             "fp64_us": t_apply64 * 1e6, "fp64_gdof_s": ndof / t_apply64 / 1e9,
             "fp32_cold_us": t_apply32_cold * 1e6, "fp32_cold_gdof_s": ndof / t_apply32_cold / 1e9,
             "fp64_cold_us": t_apply64_cold * 1e6, "fp64_cold_gdof_s": ndof / t_apply64_cold / 1e9,
@@ -316,8 +368,11 @@ def main():
         "final_state": {"fp32": st32, "fp64": st64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_apply<float> (fbto_apply_K), algorithmic bytes 2*3N*4 + E*4 = "
-                               f"{bytes32} per launch"},
+                     "kernel": "k_apply<float, 1, CGF> (fused Jacobi-PCG step, 7 of the 8 steps of an "
+                               "outer iteration), algorithmic bytes 11*3N*4 + N + E*4 = "
+                               f"{bytes_fused} per launch, {t_fused * 1e6:.2f} us per launch"},
+        "outer_roofline": {"bytes_per_iter": bytes_outer, "ceiling_iter_s": HBM_PEAK_GBS * 1e9 / bytes_outer,
+                           "frac": value * bytes_outer / (HBM_PEAK_GBS * 1e9)},
         "fixed_error": fixed,
         "cpu_baseline": cpu,
         "kernel_hash": kernel_hash(),
