@@ -22,7 +22,7 @@ gradient.
 from .element import material_lame, element_stiffness, KE_DIAG
 from .grid import Grid
 from .operator import simp_scale, simp_dscale, assemble_K, apply_K, apply_K_rows, jacobi_diag
-from .solve import solve_direct, pcg_ref, pcg_to_tol
+from .solve import solve_direct, pcg_ref, pcg_to_tol, krylov_step_ref
 from .sensitivity import element_energy, element_bilinear, compliance_gradient, adjoint_gradient
 from .density_filter import cone_filter_matrix, filter_forward, filter_transpose
 from .projection import project_alg4, project_bisect, box_clamp
@@ -31,7 +31,7 @@ from .outer import outer_step_ref, run_outer_ref, step_size
 __all__ = [
     "material_lame", "element_stiffness", "KE_DIAG", "Grid",
     "simp_scale", "simp_dscale", "assemble_K", "apply_K", "apply_K_rows", "jacobi_diag",
-    "solve_direct", "pcg_ref", "pcg_to_tol",
+    "solve_direct", "pcg_ref", "pcg_to_tol", "krylov_step_ref",
     "element_energy", "element_bilinear", "compliance_gradient", "adjoint_gradient",
     "cone_filter_matrix", "filter_forward", "filter_transpose",
     "project_alg4", "project_bisect", "box_clamp",

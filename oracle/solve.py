@@ -7,7 +7,8 @@ preconditioner commuting with K.  The inner step used here is a few steps of
 Jacobi-preconditioned conjugate gradients, restarted each outer iteration
 and warm-started from the previous displacement (the Jacobi preconditioner
 is among the lightweight preconditioners Sec. 4.1 names).  The plain
-gradient step of Alg. 1 and a damped Jacobi step are kept as variants.
+gradient step of Alg. 1 and a damped Jacobi step are kept as variants, and
+Alg. 3's step with the Krylov preconditioner of Eq. LSP (krylov_step_ref).
 
 ``operator`` arguments are callables u -> K_bc u (CSR matvec or the element
 loop), so that every solver here is a textbook recurrence over a black box.
@@ -69,6 +70,39 @@ def damped_jacobi_ref(apply, diag, f, u0, steps, omega):
     u = np.array(u0, dtype=np.float64, copy=True)
     for _ in range(steps):
         u = u - omega * (apply(u) - f) / diag
+    return u, f - apply(u)
+
+
+def krylov_step_ref(apply, f, u0, D, beta=1.0):
+    """One low-level step of Alg. 3 (CPFBTO) with the Krylov preconditioner
+    of Eq. LSP (Sec. 4.1):
+
+        delta = K u - f
+        c*    = argmin_c || delta - sum_{i=1}^{D+1} c_{i-1} K^i delta ||
+        M^-1 delta = sum_{i=0}^{D} c*_i K^i delta
+        u    <- u - beta M^-1 delta
+
+    The least-squares problem is solved as the paper does, by Householder QR
+    of the monomial Krylov matrix [K delta, ..., K^(D+1) delta] (LAPACK's
+    geqrf behind numpy.linalg.qr).  With beta = 1 the new residual is the
+    smallest over u + span{delta, ..., K^D delta}: one GMRES(D + 1) cycle.
+    Returns (u_new, f - K u_new)."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    delta = apply(u) - f
+    cols = []
+    v = delta
+    for _ in range(D + 1):
+        v = apply(v)
+        cols.append(v)
+    A = np.stack(cols, axis=1)
+    Q, R = np.linalg.qr(A)
+    c = np.linalg.solve(R, Q.T @ delta)
+    minv = np.zeros_like(u)
+    v = delta
+    for i in range(D + 1):
+        minv += c[i] * v
+        v = apply(v)
+    u = u - beta * minv
     return u, f - apply(u)
 
 

@@ -1,7 +1,10 @@
 """Pins for the oracle's inner solvers (CPU only): pcg_ref follows SciPy's
 preconditioned CG iterate for iterate, reaches the direct solution when run
 long enough, and the Alg. 1 / damped-Jacobi variants are checked against
-their fixed points."""
+their fixed points.  The Krylov step of Alg. 3 (Eq. LSP) is pinned against
+SciPy's GMRES with one cycle of D + 1 steps, against the exact solve when
+the operator has D + 1 distinct eigenvalues, and by the monotone decrease
+of its residual in D."""
 import numpy as np
 import scipy.sparse.linalg as spla
 
@@ -66,3 +69,57 @@ def test_pcg_to_tol_and_variants():
         e = um - u_ex
         errs.append(e @ (K @ e))
     assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:]))
+
+
+def test_krylov_step_is_one_gmres_cycle():
+    """Eq. LSP with beta = 1 minimises the residual over u + span{delta, ...,
+    K^D delta}, which is what one GMRES(D + 1) cycle from u computes (by a
+    different, Arnoldi-based route)."""
+    g, p, s, K, D = _system(6, 4, 3)
+    f = p.loads[0]
+    rng = np.random.default_rng(1)
+    u0 = np.where(p.fixed_mask == 0, rng.standard_normal(g.ndof) * 1e-2, 0.0)
+    for deg in (2, 5, 10):
+        u1, r1 = oracle.krylov_step_ref(lambda v: K @ v, f, u0, deg)
+        ug, _ = spla.gmres(K, f, x0=u0.copy(), restart=deg + 1, maxiter=1, rtol=0.0, atol=0.0)
+        assert np.abs(u1 - ug).max() <= 1e-9 * np.abs(ug - u0).max(), deg
+        assert np.abs(r1 - (f - K @ u1)).max() <= 1e-12 * np.abs(f).max()
+    # D = 20: the monomial basis is ill-conditioned; the least-squares
+    # residual it reaches is still within 1e-3 of the optimum
+    u1, r1 = oracle.krylov_step_ref(lambda v: K @ v, f, u0, 20)
+    ug, _ = spla.gmres(K, f, x0=u0.copy(), restart=21, maxiter=1, rtol=0.0, atol=0.0)
+    rg = np.linalg.norm(f - K @ ug)
+    assert rg <= np.linalg.norm(r1) <= rg * (1.0 + 1e-3)
+
+
+def test_krylov_step_exact_with_few_eigenvalues():
+    """An SPD operator with 4 distinct eigenvalues is solved exactly by the
+    degree-3 Krylov step (its minimal polynomial has degree 4)."""
+    rng = np.random.default_rng(2)
+    n = 40
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.repeat([0.5, 1.0, 2.0, 4.0], n // 4)
+    Kd = (Qm * lam) @ Qm.T
+    f = rng.standard_normal(n)
+    u0 = rng.standard_normal(n)
+    u1, r1 = oracle.krylov_step_ref(lambda v: Kd @ v, f, u0, 3)
+    u_ex = np.linalg.solve(Kd, f)
+    assert np.abs(u1 - u_ex).max() <= 1e-10 * np.abs(u_ex).max()
+    # the damped step moves a fraction beta of the way
+    uh, _ = oracle.krylov_step_ref(lambda v: Kd @ v, f, u0, 3, beta=0.25)
+    assert np.abs(uh - (u0 + 0.25 * (u_ex - u0))).max() <= 1e-10 * np.abs(u_ex).max()
+
+
+def test_krylov_step_residual_decreases_with_degree():
+    """A larger Krylov space can only lower the minimal residual, and any
+    D >= 0 lowers it below the starting one for an SPD K (the contraction
+    the convergence argument of Alg. 3 relies on)."""
+    g, p, s, K, D = _system(5, 3, 3)
+    f = p.loads[0]
+    u0 = np.zeros(g.ndof)
+    prev = np.linalg.norm(f)
+    for deg in (0, 1, 2, 4, 8):
+        _, r = oracle.krylov_step_ref(lambda v: K @ v, f, u0, deg)
+        cur = np.linalg.norm(r)
+        assert cur < prev
+        prev = cur
