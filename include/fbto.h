@@ -70,7 +70,8 @@ typedef enum fbto_prec { FBTO_F64 = 0, FBTO_F32 = 1 } fbto_prec_t;
 typedef enum fbto_method {
   FBTO_PCG_JACOBI = 0,
   FBTO_RICHARDSON = 1,
-  FBTO_DAMPED_JACOBI = 2
+  FBTO_DAMPED_JACOBI = 2,
+  FBTO_KRYLOV = 3
 } fbto_method_t;
 
 typedef struct fbto_grid_desc {
@@ -143,7 +144,15 @@ fbto_status_t fbto_apply_K(fbto_grid_t g, fbto_prec_t prec, const void* rho_phys
  * PCG_JACOBI runs the textbook preconditioned CG recurrence rearranged as in
  * Chronopoulos and Gear (one reduction phase per step; same iterates in
  * exact arithmetic).
- *   omega   step of RICHARDSON (beta) or DAMPED_JACOBI (omega); unused by PCG.
+ * KRYLOV is ONE low-level step of Alg. 3 with the Krylov preconditioner of
+ * Eq. LSP (Sec. 4.1), of degree D = `steps` (0 .. 1000):
+ *   u <- u - omega M^-1 (K u - f),  M^-1 b = sum_{i<=D} c_i K^i b,
+ *   c = argmin || b - sum_{i=1}^{D+1} c_{i-1} K^i b ||,
+ * computed by the MINRES recurrence (D + 1 products; the same minimiser as
+ * the paper's QR of the monomial basis, by a stable route).  The RHS are
+ * processed one after another.
+ *   omega   step of RICHARDSON (beta), DAMPED_JACOBI (omega) or KRYLOV
+ *           (Alg. 3's beta_k; 1 is the paper's choice); unused by PCG.
  *   rtol    0: run exactly `steps` steps, asynchronously.  rtol > 0 (PCG
  *           only): stop once ||r||_2 <= rtol ||f||_2 or after `steps`
  *           steps; this mode synchronises the stream every 64 steps.

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbto.so"
 FBTO_OK, FBTO_ERR_ARG, FBTO_ERR_ALLOC, FBTO_ERR_HIP = 0, 1, 2, 3
 FBTO_ERR_INFEASIBLE, FBTO_ERR_BREAKDOWN, FBTO_ERR_NONFINITE, FBTO_ERR_UNSUPPORTED = 4, 5, 6, 7
 FBTO_F64, FBTO_F32 = 0, 1
-FBTO_PCG_JACOBI, FBTO_RICHARDSON, FBTO_DAMPED_JACOBI = 0, 1, 2
+FBTO_PCG_JACOBI, FBTO_RICHARDSON, FBTO_DAMPED_JACOBI, FBTO_KRYLOV = 0, 1, 2, 3
 FBTO_SOLVE_INFO = 8
 FBTO_OUTER_INFO = 8
 SI = dict(rnorm2=0, rnormi=1, fnorm2=2, steps=3, status=4)

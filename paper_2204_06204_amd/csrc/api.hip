@@ -324,6 +324,44 @@ fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs
   return residual_norms<T>(g, rho, u, f, r, invD, nrhs, st);
 }
 
+// One low-level step of Alg. 3 with the Krylov preconditioner of degree D
+// (Eq. LSP), per RHS: u <- u + damp * (u_D - u), where u_D minimises the
+// residual over u + span{r, ..., K^D r} (MINRES, D + 1 iterations; see
+// k_minres).  Workspace: w[0] (products), r[0..1] (Lanczos vectors), p[0..1]
+// (MINRES directions).
+template <typename T>
+fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int D, double damp,
+                         hipStream_t st) {
+  Vecs& V = vecs<T>(g);
+  const int64_t nd = g->geo.ndof;
+  T* Y = (T*)V.w[0];
+  const int last = D + 2;
+  for (int R = 0; R < nrhs; ++R) {
+    T* x = u + R * nd;
+    const T* fr = f + R * nd;
+    T* R1 = (T*)V.r[1];
+    T* R2 = (T*)V.r[0];
+    T* Wc = (T*)V.p[0];
+    T* W2 = (T*)V.p[1];
+    HIP_TRY(launch_resid<T>(g, rho, x, fr, R2, (const T*)nullptr, (T*)nullptr, 1, st, nullptr));  // R2 = f - K u
+    int nb_v = 0, nb_a = 0;
+    HIP_TRY(launch_minres<T>(g, 0, last, Y, R1, R2, W2, Wc, x, 0, 0, damp, st, &nb_v));
+    for (int itn = 1; itn <= D + 1; ++itn) {
+      // Y = K R2 with <A.r, R2> and <Y, R2>; A.r = R1 (R2 on the first iteration, where R1 is unused)
+      HIP_TRY(launch_apply_cg<T>(g, rho, R2, itn == 1 ? R2 : R1, Y, 1, itn, st, &nb_a));
+      int nb = 0;
+      HIP_TRY(launch_minres<T>(g, itn, last, Y, R1, R2, W2, Wc, x, nb_a, nb_v, damp, st, &nb));
+      nb_v = nb;
+      std::swap(R1, R2);                 // R1 <- R2, R2 <- the new Lanczos vector
+      if (itn >= 2) std::swap(Wc, W2);   // W <- the new direction, W2 <- W
+    }
+    HIP_TRY(launch_minres<T>(g, last, last, Y, R1, R2, W2, Wc, x, 0, nb_v, damp, st, nullptr));
+  }
+  T* invD = (T*)V.invD;
+  HIP_TRY(launch_diag<T>(g, rho, invD, st));
+  return residual_norms<T>(g, rho, u, f, (T*)V.r[0], invD, nrhs, st);
+}
+
 template <typename T>
 fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k, double alpha0,
                         int inner_steps, int mean_project, double lo, double vmax, double* info,
@@ -529,29 +567,38 @@ fbto_status_t fbto_inner_solve(fbto_grid_t g, fbto_prec_t prec, const void* rho_
   if (!rho_phys || !f || !u) return fail(FBTO_ERR_ARG, "rho_phys, f and u must be non-NULL");
   if (steps < 0) return fail(FBTO_ERR_ARG, "steps must be >= 0");
   if (!(rtol >= 0.0)) return fail(FBTO_ERR_ARG, "rtol must be >= 0");
-  if (method != FBTO_PCG_JACOBI && method != FBTO_RICHARDSON && method != FBTO_DAMPED_JACOBI)
+  if (method != FBTO_PCG_JACOBI && method != FBTO_RICHARDSON && method != FBTO_DAMPED_JACOBI &&
+      method != FBTO_KRYLOV)
     return fail(FBTO_ERR_ARG, "unknown method %d", (int)method);
   if (method != FBTO_PCG_JACOBI && rtol > 0.0)
     return fail(FBTO_ERR_UNSUPPORTED, "rtol > 0 is supported for PCG only");
   if (method != FBTO_PCG_JACOBI && !(std::isfinite(omega) && omega > 0.0))
     return fail(FBTO_ERR_ARG, "omega must be finite and > 0");
+  if (method == FBTO_KRYLOV && steps > 1000) return fail(FBTO_ERR_ARG, "Krylov degree %d > 1000", (int)steps);
   hipStream_t st = (hipStream_t)stream;
   fbto_status_t s;
   if (prec == FBTO_F64) {
     if ((s = ensure_vecs<double>(g))) return s;
-    s = method == FBTO_PCG_JACOBI
-            ? pcg_solve<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, rtol, st)
-            : relax_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, omega,
-                                method == FBTO_DAMPED_JACOBI, st);
+    if (method == FBTO_PCG_JACOBI)
+      s = pcg_solve<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, rtol, st);
+    else if (method == FBTO_KRYLOV)
+      s = krylov_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, omega, st);
+    else
+      s = relax_run<double>(g, (const double*)rho_phys, (const double*)f, (double*)u, nrhs, steps, omega,
+                            method == FBTO_DAMPED_JACOBI, st);
   } else {
     if ((s = ensure_vecs<float>(g))) return s;
-    s = method == FBTO_PCG_JACOBI
-            ? pcg_solve<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, rtol, st)
-            : relax_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, omega,
-                               method == FBTO_DAMPED_JACOBI, st);
+    if (method == FBTO_PCG_JACOBI)
+      s = pcg_solve<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, rtol, st);
+    else if (method == FBTO_KRYLOV)
+      s = krylov_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, omega, st);
+    else
+      s = relax_run<float>(g, (const float*)rho_phys, (const float*)f, (float*)u, nrhs, steps, omega,
+                           method == FBTO_DAMPED_JACOBI, st);
   }
   if (s) return s;
-  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, method == FBTO_PCG_JACOBI ? -1.0 : (double)steps, st));
+  const double steps_done = method == FBTO_PCG_JACOBI ? -1.0 : (method == FBTO_KRYLOV ? steps + 1.0 : steps);
+  if (info) HIP_TRY(launch_solve_info(g, info, nrhs, steps_done, st));
   return ok();
 }
 

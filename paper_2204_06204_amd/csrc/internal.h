@@ -70,6 +70,11 @@ struct Scalars {
   double gsum;         // sum of the filtered gradient
   double gmean;
   double work[8];
+  // Krylov step (MINRES recurrence), carried from one vector pass to the
+  // next: beta (||current Lanczos vector||), alpha of the last iteration,
+  // and the Givens state dbar, epsln, phibar, cs, sn.  Pass t writes
+  // kr[t & 1] while its blocks read kr[(t + 1) & 1].
+  double kr[2][8];
 };
 
 // Per-block FP64 partial results.  A producing kernel writes one value per
@@ -90,6 +95,7 @@ enum PartSlot {
   P_E0,                // projection pass: 11 consecutive slots P_E0 .. P_E0+10
   P_VOL = P_E0 + 11,   // sum x_new
   P_DX,                // max |x_new - x_old|
+  P_KRN0, P_KRN1,      // Krylov step: ||y||^2 of the new Lanczos vector, by iteration parity
   P_COUNT
 };
 constexpr int kMaxVecBlocks = 1024;
@@ -237,5 +243,10 @@ hipError_t launch_ir_accum(fbto_grid_s* g, double* u64, const float* d32, int nr
                            hipStream_t st);
 hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double steps_override,
                              hipStream_t st);
+// One vector pass of the Krylov step (MINRES recurrence), iteration `itn`
+// of 0 .. last (see k_minres); returns the block count of its partials.
+template <typename T>
+hipError_t launch_minres(fbto_grid_s* g, int itn, int last, const T* Y, T* R1, const T* R2, T* W2, const T* W,
+                         T* x, int n_apply, int n_prev, double damp, hipStream_t st, int* nb_out);
 
 }  // namespace fbto

@@ -1466,6 +1466,132 @@ hipError_t launch_relax_update(fbto_grid_s* g, T* u, const T* r, const T* invD, 
 }
 
 // ===========================================================================
+// Krylov step of Alg. 3 (Eq. LSP, beta = 1): the new iterate minimises the
+// residual over u + span{r, K r, ..., K^D r}.  It is computed by the MINRES
+// recurrence (Lanczos vectors and Givens rotations, as in Paige and
+// Saunders), D + 1 iterations from u.  Iteration itn (1 .. D + 1) is one
+// CG-mode apply Y = K R2 (partials <R1, R2>, <Y, R2>) and one pass of this
+// kernel, which
+//   - reduces beta = ||R2|| (the previous pass's partials) and, from the
+//     apply's partials, alpha = <v, K v - (beta/oldb) R1> with v = R2/beta;
+//   - finishes iteration itn - 1: its Givens rotation needs beta, then
+//     w = (v' - oldeps w'' - delta w') / gamma, x += damp * phi * w, where
+//     v' = R1 / oldb is that iteration's Lanczos vector;
+//   - forms the next Lanczos vector y = K v - (beta/oldb) R1 - (alpha/beta) R2
+//     into R1's buffer and leaves ||y||^2 as partials.
+// Pass 0 only leaves ||R2||^2 (R2 = f - K u); pass D + 2 only finishes
+// iteration D + 1.  Every block runs the scalar recurrence on the same
+// reduced values in the same order; block 0 keeps its state for the next
+// pass.  The caller rotates the buffers: R1 <- R2, R2 <- the buffer y went
+// to, W <- the buffer w went to (W2), W2 <- W.  `damp` scales the step
+// (Alg. 3's beta_k).
+// ===========================================================================
+template <typename T>
+__global__ void __launch_bounds__(kVecBlock)
+    k_minres(int64_t n, int itn, int last, const T* Y, T* R1, const T* R2, T* W2, const T* W, T* x,
+             double* P, int maxp, int n_apply, int n_prev, Scalars* sc, double damp) {
+  double beta = 0.0;
+  if (itn >= 1) {
+    double v[1];
+    const double* src[1] = {pslot(P, P_KRN0 + ((itn - 1) & 1), 0, maxp)};
+    const int cnt[1] = {n_prev};
+    reduce_parts<1, 0u>(v, src, cnt);
+    beta = sqrt(fmax(v[0], 0.0));
+  }
+  const bool lanczos = itn >= 1 && itn < last;
+  const bool finish = itn >= 2;
+  double yr2 = 0.0, r12 = 0.0;
+  if (lanczos) {
+    double v[2];
+    const double* src[2] = {pslot(P, P_RZ0 + (itn & 1), 0, maxp), pslot(P, P_PQ0 + (itn & 1), 0, maxp)};
+    const int cnt[2] = {n_apply, n_apply};
+    reduce_parts<2, 0u>(v, src, cnt);
+    r12 = v[0];
+    yr2 = v[1];
+  }
+  // state carried from the previous pass
+  double oldb = 0.0, alfa_prev = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta, cs = -1.0, sn = 0.0;
+  if (itn >= 2) {
+    const double* k = sc->kr[(itn + 1) & 1];  // written by pass itn - 1
+    oldb = k[0];
+    alfa_prev = k[1];
+    dbar = k[2];
+    epsln = k[3];
+    phibar = k[4];
+    cs = k[5];
+    sn = k[6];
+  }
+  // Givens rotation of iteration itn - 1
+  double oldeps = 0.0, delta = 0.0, gamma = 1.0, phi = 0.0;
+  if (finish) {
+    oldeps = epsln;
+    delta = cs * dbar + sn * alfa_prev;
+    const double gbar = sn * dbar - cs * alfa_prev;
+    epsln = sn * beta;
+    dbar = -cs * beta;
+    gamma = fmax(sqrt(gbar * gbar + beta * beta), 1e-300);
+    cs = gbar / gamma;
+    sn = beta / gamma;
+    phi = cs * phibar;
+    phibar = sn * phibar;
+  }
+  // Lanczos step of iteration itn
+  const double s = beta > 0.0 ? 1.0 / beta : 0.0;
+  const double c1 = (itn >= 2 && oldb > 0.0) ? beta / oldb : 0.0;
+  const double alfa = lanczos ? s * (s * yr2 - c1 * r12) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && itn >= 1) {
+    double* k = sc->kr[itn & 1];
+    k[0] = beta;
+    k[1] = alfa;
+    k[2] = dbar;
+    k[3] = epsln;
+    k[4] = phibar;
+    k[5] = cs;
+    k[6] = sn;
+  }
+  const int j = itn - 1;  // the iteration finished here
+  const T inv_oldb = (T)(oldb > 0.0 ? 1.0 / oldb : 0.0);
+  const T wc1 = (T)oldeps, wc2 = (T)delta, inv_gamma = (T)(1.0 / gamma), step = (T)(damp * phi);
+  const T ts = (T)s, tc1 = (T)c1, ta = (T)(alfa * s);
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T r1 = R1[i];
+    if (finish) {
+      const T w1v = W[i], w2v = W2[i];  // w of iterations j - 1 and j - 2 (zero before the first)
+      const T wp = j >= 2 ? w1v : (T)0, wpp = j >= 3 ? w2v : (T)0;
+      const T wn = (r1 * inv_oldb - wc1 * wpp - wc2 * wp) * inv_gamma;
+      W2[i] = wn;
+      x[i] += step * wn;
+    }
+    if (itn == 0) {
+      const T r2 = R2[i];
+      acc += (double)r2 * (double)r2;
+    } else if (lanczos) {
+      const T r1m = itn >= 2 ? r1 : (T)0;  // R1 holds no vector yet on the first iteration
+      const T yn = ts * Y[i] - tc1 * r1m - ta * R2[i];
+      R1[i] = yn;
+      acc += (double)yn * (double)yn;
+    }
+  }
+  if (itn == 0 || lanczos) {
+    double v[1] = {acc};
+    double* dst[1] = {pslot(P, P_KRN0 + (itn & 1), 0, maxp)};
+    write_parts<1, 0u>(v, dst, blockIdx.x);
+  }
+}
+
+template <typename T>
+hipError_t launch_minres(fbto_grid_s* g, int itn, int last, const T* Y, T* R1, const T* R2, T* W2, const T* W,
+                         T* x, int n_apply, int n_prev, double damp, hipStream_t st, int* nb_out) {
+  const int nb = vec_blocks(g->geo.ndof);
+  if (nb > g->max_partials || n_apply > g->max_partials) return hipErrorInvalidValue;
+  if (nb_out) *nb_out = nb;
+  hipLaunchKernelGGL((k_minres<T>), dim3(nb), dim3(kVecBlock), 0, st, g->geo.ndof, itn, last, Y, R1, R2, W2, W,
+                     x, g->partials, g->max_partials, n_apply, n_prev, g->sc, damp);
+  return hipGetLastError();
+}
+
+// ===========================================================================
 // Sensitivity: dobj_e = -ds_e sum_r lam_{r,e}^T KE u_{r,e} (times 1/Hs_e when
 // Hsi is given, which turns the filter transpose into a plain weighted sum),
 // element strains recomputed from the nodal vectors (one element per thread).
@@ -2130,6 +2256,8 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   template hipError_t launch_diag<T>(fbto_grid_s*, const T*, T*, hipStream_t);                         \
   template hipError_t launch_relax_update<T>(fbto_grid_s*, T*, const T*, const T*, int, double, int,    \
                                              hipStream_t);                                             \
+  template hipError_t launch_minres<T>(fbto_grid_s*, int, int, const T*, T*, const T*, T*, const T*, T*, \
+                                       int, int, double, hipStream_t, int*);                          \
   template hipError_t launch_sens<T>(fbto_grid_s*, const T*, const T*, const T*, int, T*, const T*,    \
                                      hipStream_t);                                                     \
   template hipError_t launch_dot<T>(fbto_grid_s*, const T*, const T*, int, hipStream_t);               \

@@ -120,7 +120,7 @@ class Grid:
     def inner_solve(self, rho, f, u, steps: int, method: str = "pcg", omega: float = 0.0,
                     rtol: float = 0.0, info: Optional[torch.Tensor] = None, stream=None):
         meth = {"pcg": _lib.FBTO_PCG_JACOBI, "richardson": _lib.FBTO_RICHARDSON,
-                "jacobi": _lib.FBTO_DAMPED_JACOBI}[method]
+                "jacobi": _lib.FBTO_DAMPED_JACOBI, "krylov": _lib.FBTO_KRYLOV}[method]
         nr = self._nrhs(u)
         check(self.lib.fbto_inner_solve(self.handle, _prec(u), _ptr(rho, u.dtype, self.E, "rho"),
                                         _ptr(f, u.dtype, u.numel(), "f"), _ptr(u, name="u"), nr,
