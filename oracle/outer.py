@@ -6,7 +6,9 @@ here (the text of Sec. 4 uses the inexact result *after* the low-level
 step for the sensitivity):
   1. rho = C(x)                      density filter (Remark, Sec. 3)
   2. s, ds, diag(K) from rho          modified SIMP (Sec. 3)
-  3. u <- m Jacobi-PCG steps from u   low-level refinement (Alg. 1 / 3)
+  3. u <- m Jacobi-PCG steps from u   low-level refinement (Alg. 1 / 3);
+     or, for Alg. 3 (CPFBTO), one step with the Krylov preconditioner of
+     Eq. LSP (low_level=("krylov", D, beta))
   4. c = f^T u,  g_rho = -ds w        approximate sensitivity (Alg. 1)
   5. g_x = C^T g_rho
   6. g_x <- g_x - mean(g_x)           mean-projected gradient (Sec. 4.2)
@@ -27,7 +29,7 @@ from .grid import Grid
 from .operator import apply_K, assemble_K, jacobi_diag, simp_dscale, simp_scale
 from .projection import project_alg4
 from .sensitivity import element_energy
-from .solve import pcg_ref
+from .solve import krylov_step_ref, pcg_ref
 
 
 def step_size(alpha0: float, k: int) -> float:
@@ -67,8 +69,11 @@ class OuterContext:
 
 
 def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, vmax,
-                   mean_project=True):
-    """Returns (x_new, u_new, OuterRecord, g_x)."""
+                   mean_project=True, low_level=None):
+    """Returns (x_new, u_new, OuterRecord, g_x).  low_level=None runs
+    `inner_steps` Jacobi-PCG steps; ("krylov", D, beta) runs Alg. 3's one
+    preconditioned step u <- u - beta M^-1 (K u - f) (r_inf is then the true
+    residual after the step)."""
     g = ctx.grid
     rho = filter_forward(ctx.H, ctx.Hs, x)
     s = simp_scale(rho, ctx.penal, ctx.rho_min)
@@ -79,7 +84,11 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
     U = np.array(np.atleast_2d(u), dtype=np.float64, copy=True)
     r_inf = 0.0
     for r in range(F.shape[0]):
-        U[r], res = pcg_ref(A, D, F[r], U[r], inner_steps)
+        if low_level is None:
+            U[r], res = pcg_ref(A, D, F[r], U[r], inner_steps)
+        else:
+            _, deg, beta = low_level
+            U[r], res = krylov_step_ref(A, F[r], U[r], deg, beta)
         r_inf = max(r_inf, float(np.abs(res).max()))
     c = float(sum(F[r] @ U[r] for r in range(F.shape[0])))
     g_rho = -ds * element_energy(g, U, ctx.fixed, ctx.KE)
@@ -94,7 +103,7 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
 
 
 def run_outer_ref(ctx: OuterContext, x_init, f, iters, alpha0, inner_steps, lo, hi, vmax,
-                  mean_project=True, u0=None):
+                  mean_project=True, u0=None, low_level=None):
     """x_0 = Proj_X(x_init), u_0 = 0 (or u0); then `iters` outer steps."""
     x = project_alg4(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
     F = np.atleast_2d(f)
@@ -102,7 +111,7 @@ def run_outer_ref(ctx: OuterContext, x_init, f, iters, alpha0, inner_steps, lo, 
     recs, xs = [], [x.copy()]
     for k in range(1, iters + 1):
         x, u, rec, _ = outer_step_ref(ctx, x, u, F, k, alpha0, inner_steps, lo, hi, vmax,
-                                      mean_project)
+                                      mean_project, low_level)
         recs.append(rec)
         xs.append(x.copy())
     return x, u, recs, xs

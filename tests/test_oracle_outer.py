@@ -50,3 +50,25 @@ def test_exact_inner_solve_gives_projected_gradient_descent():
     ref = oracle.project_bisect(x - 0.3 * 0.5 * g, 0.0, 1.0, p.vmax)
     assert np.abs(x1 - ref).max() < 1e-9
     assert abs(rec.compliance - p.loads[0] @ u) < 1e-9 * abs(rec.compliance)
+
+
+def test_cpfbto_step_uses_one_gmres_cycle():
+    """Alg. 3's outer step with the Krylov preconditioner (beta = 1) equals the
+    same outer step whose low-level update is one GMRES(D + 1) cycle from u
+    (SciPy), and its r_inf is that update's true residual."""
+    import scipy.sparse.linalg as spla
+    from oracle.density_filter import filter_forward
+    p = synth.config("cfg1")
+    ctx = _ctx(p)
+    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    rng = np.random.default_rng(3)
+    u0 = np.where(p.fixed_mask == 0, rng.standard_normal(p.ndof) * 1e-2, 0.0)
+    deg = 6
+    x1, u1, rec, _ = outer_step_ref(ctx, x, u0, p.loads[0], 1, 0.05, 0, 0.0, 1.0, p.vmax,
+                                    low_level=("krylov", deg, 1.0))
+    s = oracle.simp_scale(filter_forward(ctx.H, ctx.Hs, x))
+    K = oracle.assemble_K(ctx.grid, s, p.fixed_mask)
+    ug, _ = spla.gmres(K, p.loads[0], x0=u0.copy(), restart=deg + 1, maxiter=1, rtol=0.0, atol=0.0)
+    assert np.abs(u1 - ug).max() <= 1e-9 * np.abs(ug - u0).max()
+    assert abs(rec.r_inf - np.abs(p.loads[0] - K @ ug).max()) <= 1e-9 * rec.r_inf
+    assert abs(rec.compliance - p.loads[0] @ ug) <= 1e-9 * abs(rec.compliance)
