@@ -223,6 +223,16 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
                               int32_t inner_steps, int32_t mean_project, double lo,
                               double vmax, double* info, void* stream);
 
+/* One outer iteration k of Alg. 3 (CPFBTO): as fbto_outer_step, with the
+ * low-level update replaced by one step with the Krylov preconditioner of
+ * degree `degree` (Eq. LSP, fbto_inner_solve's FBTO_KRYLOV):
+ *   u <- u - beta M^-1 (K(rho) u - f),  beta > 0 (the paper uses 1).
+ * info's R_INF is the true residual after that step.  degree: 0 .. 1000. */
+fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
+                                     const void* f, int32_t nrhs, int32_t k, double alpha0,
+                                     int32_t degree, double beta, int32_t mean_project,
+                                     double lo, double vmax, double* info, void* stream);
+
 /* Message of the last error on this thread ("" if none). */
 const char* fbto_last_error(void);
 

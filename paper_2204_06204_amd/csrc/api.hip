@@ -331,7 +331,7 @@ fbto_status_t relax_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs
 // (MINRES directions).
 template <typename T>
 fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrhs, int D, double damp,
-                         hipStream_t st) {
+                         hipStream_t st, CgCounts* cn_out = nullptr) {
   Vecs& V = vecs<T>(g);
   const int64_t nd = g->geo.ndof;
   T* Y = (T*)V.w[0];
@@ -359,20 +359,32 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
   }
   T* invD = (T*)V.invD;
   HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  return residual_norms<T>(g, rho, u, f, (T*)V.r[0], invD, nrhs, st);
+  if (!cn_out) return residual_norms<T>(g, rho, u, f, (T*)V.r[0], invD, nrhs, st);
+  // inside an outer step: leave the residual norms and f . u as partials
+  // for the step's final reduction
+  int nb = 0;
+  HIP_TRY(launch_resid<T>(g, rho, u, f, (T*)V.r[0], invD, (T*)V.q, nrhs, st, &nb));
+  HIP_TRY(launch_dot<T>(g, f, u, nrhs, st));
+  *cn_out = CgCounts{nb, nb, vec_blocks(g->geo.ndof)};
+  return FBTO_OK;
 }
 
+// One outer iteration: Alg. 1 with `inner_steps` Jacobi-PCG steps, or
+// (krylov_degree >= 0) Alg. 3 with one Krylov-preconditioned step of that
+// degree and step beta.
 template <typename T>
 fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k, double alpha0,
                         int inner_steps, int mean_project, double lo, double vmax, double* info,
-                        hipStream_t st) {
+                        hipStream_t st, int krylov_degree = -1, double beta = 1.0) {
   Vecs& V = vecs<T>(g);
   T* rho = (T*)V.rho;
   HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
   CgCounts cn{};
   bool sens_done = false;
-  fbto_status_t s = pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn, (T*)V.ge, (const T*)V.Hs,
-                               &sens_done);
+  fbto_status_t s = krylov_degree >= 0
+                        ? krylov_run<T>(g, rho, f, u, nrhs, krylov_degree, beta, st, &cn)
+                        : pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn, (T*)V.ge,
+                                     (const T*)V.Hs, &sens_done);
   if (s != FBTO_OK) return s;
   // element gradient already divided by Hs, so the filter transpose is a plain sum
   if (!sens_done) HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
@@ -749,6 +761,34 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
     if ((s = ensure_vecs<float>(g))) return s;
     s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, inner_steps,
                          mean_project, lo, vmax, info, st);
+  }
+  if (s) return s;
+  return ok();
+}
+
+fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, void* u, const void* f,
+                                     int32_t nrhs, int32_t k, double alpha0, int32_t degree, double beta,
+                                     int32_t mean_project, double lo, double vmax, double* info,
+                                     void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!x || !u || !f) return fail(FBTO_ERR_ARG, "x, u and f must be non-NULL");
+  if (k < 1) return fail(FBTO_ERR_ARG, "k is 1-based");
+  if (degree < 0 || degree > 1000) return fail(FBTO_ERR_ARG, "Krylov degree must be in [0, 1000]");
+  if (!(std::isfinite(beta) && beta > 0.0)) return fail(FBTO_ERR_ARG, "beta must be finite and > 0");
+  if (!(std::isfinite(alpha0) && alpha0 >= 0.0)) return fail(FBTO_ERR_ARG, "alpha0 must be finite and >= 0");
+  if (!(std::isfinite(lo) && lo <= 1.0)) return fail(FBTO_ERR_ARG, "need lo <= 1");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g", vmax, lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    s = outer_run<double>(g, (double*)x, (double*)u, (const double*)f, nrhs, k, alpha0, 0, mean_project, lo,
+                          vmax, info, st, degree, beta);
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, 0, mean_project, lo, vmax,
+                         info, st, degree, beta);
   }
   if (s) return s;
   return ok();

@@ -174,14 +174,22 @@ class Grid:
         return x
 
     def outer_step(self, x, u, f, k: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
-                   mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None):
+                   mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None,
+                   method: str = "pcg", beta: float = 1.0):
+        """method "pcg": Alg. 1 with `inner_steps` Jacobi-PCG steps
+        (fbto_outer_step); "krylov": Alg. 3 with one Krylov-preconditioned
+        step of degree `inner_steps` and step `beta` (fbto_outer_step_krylov)."""
         nr = self._nrhs(u)
-        check(self.lib.fbto_outer_step(self.handle, _prec(x), _ptr(x, None, self.E, "x"),
-                                       _ptr(u, x.dtype, None, "u"), _ptr(f, x.dtype, u.numel(), "f"),
-                                       nr, int(k), float(alpha0), int(inner_steps),
-                                       1 if mean_project else 0, float(lo), float(vmax),
-                                       _ptr(info, torch.float64, None, "info"), _stream(stream)),
-              self.lib)
+        common = (self.handle, _prec(x), _ptr(x, None, self.E, "x"), _ptr(u, x.dtype, None, "u"),
+                  _ptr(f, x.dtype, u.numel(), "f"), nr, int(k), float(alpha0))
+        tail = (1 if mean_project else 0, float(lo), float(vmax), _ptr(info, torch.float64, None, "info"),
+                _stream(stream))
+        if method == "pcg":
+            check(self.lib.fbto_outer_step(*common, int(inner_steps), *tail), self.lib)
+        elif method == "krylov":
+            check(self.lib.fbto_outer_step_krylov(*common, int(inner_steps), float(beta), *tail), self.lib)
+        else:
+            raise ValueError(f"unknown method {method!r}")
         return x
 
 

@@ -103,7 +103,8 @@ def test_projection_inactive_and_infeasible():
         g.project_volume(y, lo=0.5, hi=1.0, vmax=0.1 * p.E)
 
 
-def _run_gpu(p, iters, alpha0, dtype, g=None):
+def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None):
+    """krylov=(D, beta): Alg. 3's outer step (fbto_outer_step_krylov)."""
     g = g or _grid(p)
     x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
     u = torch.zeros(p.nrhs * p.ndof, dtype=dtype, device=DEV)
@@ -111,7 +112,11 @@ def _run_gpu(p, iters, alpha0, dtype, g=None):
     info = torch.zeros(8, dtype=torch.float64, device=DEV)
     recs, xs = [], []
     for k in range(1, iters + 1):
-        g.outer_step(x, u, f, k, alpha0, p.inner_steps, 0.0, p.vmax, info=info)
+        if krylov is None:
+            g.outer_step(x, u, f, k, alpha0, p.inner_steps, 0.0, p.vmax, info=info)
+        else:
+            g.outer_step(x, u, f, k, alpha0, krylov[0], 0.0, p.vmax, info=info, method="krylov",
+                         beta=krylov[1])
         recs.append(host(info).copy())
         xs.append(host(x).copy())
     return recs, xs, host(u)
@@ -191,3 +196,58 @@ def test_outer_steps_bitwise_reproducible():
     assert all(np.array_equal(a, b) for a, b in zip(r1[1], r2[1]))
     assert np.array_equal(r1[2], r2[2])
     assert all(np.array_equal(a, b) for a, b in zip(r1[0], r2[0]))
+
+
+def test_cpfbto_trajectory_cfg1_fp64(monkeypatch):
+    """Alg. 3 (CPFBTO): 20 outer iterations with one Krylov-preconditioned
+    low-level step of degree 6 (beta = 1) in FP64 against the oracle, whose
+    step solves Eq. LSP by Householder QR of the monomial basis.
+    This run turns sensitive to rounding after ten iterations: the oracle
+    itself, with the least-squares problem solved by SciPy's GMRES instead
+    (the same minimiser by another route), drifts from its QR run by 1e-7
+    at iteration 13 and 1e-3 at iteration 15.  The GPU (a third route, the
+    MINRES recurrence) must stay within 1e-9 plus ten times that envelope."""
+    import scipy.sparse.linalg as spla
+    import oracle.outer as outer_mod
+    say("cpfbto cfg1 fp64")
+    p = synth.config("cfg1")
+    alpha0 = 0.0016874513029055756
+    recs, xs, _ = _run_gpu(p, 20, alpha0, torch.float64, krylov=(6, 1.0))
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 20, alpha0, 0, 0.0, 1.0, p.vmax,
+                                      low_level=("krylov", 6, 1.0))
+
+    def gmres_step(apply, f, u0, deg, beta=1.0):
+        A = spla.LinearOperator((len(u0), len(u0)), matvec=apply)
+        ug, _ = spla.gmres(A, f, x0=u0.copy(), restart=deg + 1, maxiter=1, rtol=0.0, atol=0.0)
+        u = u0 + beta * (ug - u0)
+        return u, f - apply(u)
+    monkeypatch.setattr(outer_mod, "krylov_step_ref", gmres_step)
+    _, _, grecs, gxs = run_outer_ref(ctx, p.x0, p.loads, 20, alpha0, 0, 0.0, 1.0, p.vmax,
+                                     low_level=("krylov", 6, 1.0))
+    for k in range(20):
+        env_c = abs(grecs[k].compliance - rrecs[k].compliance) / rrecs[k].compliance
+        env_x = np.abs(gxs[k + 1] - rxs[k + 1]).max()
+        c, cr = recs[k][0], rrecs[k].compliance
+        assert abs(c - cr) <= (1e-9 + 10 * env_c) * abs(cr), (k, c, cr, env_c)
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= 1e-9 + 10 * env_x, (k, env_x)
+        assert abs(recs[k][4] - rrecs[k].volume) <= 1e-9 * p.vmax
+        if k < 10:  # before the sensitive stretch: the plain bar
+            assert abs(c - cr) <= 1e-9 * abs(cr)
+            assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-7 * rrecs[k].r_inf
+
+
+def test_cpfbto_fp32_one_step_against_oracle():
+    """One FP32 step of Alg. 3 (degree 10) on a grid of several tiles against
+    the FP64 oracle."""
+    say("cpfbto fp32 one step")
+    p = synth.cantilever(40, 20, 12, volfrac=0.25, filter_radius=2.0, outer_iters=2, inner_steps=8, seed=3)
+    alpha0 = 0.002
+    recs, xs, u = _run_gpu(p, 2, alpha0, torch.float32, krylov=(10, 1.0))
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 2, alpha0, 0, 0.0, 1.0, p.vmax,
+                                      low_level=("krylov", 10, 1.0))
+    for k in range(2):
+        assert abs(recs[k][0] - rrecs[k].compliance) <= 2e-5 * rrecs[k].compliance
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= 2e-5
+        assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-3 * rrecs[k].r_inf
