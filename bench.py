@@ -33,6 +33,7 @@ HBM_PEAK_GBS = 8000.0
 ALPHA0_CFG3 = 0.0016591384929631413      # tests/golden/alpha0.json (oracle-generated)
 KERNEL_SOURCES = ("paper_2204_06204_amd/csrc/kernels.hip", "paper_2204_06204_amd/csrc/device.h")
 COPY_BYTES = 256 << 20                   # calibration copy of the HBM counters
+KRYLOV_DEGREE = 20                       # D of Alg. 3's Krylov preconditioner (the paper's choice)
 
 
 def kernel_hash() -> str:
@@ -73,26 +74,33 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sizes", action="store_true",
                     help="skip the K(rho)u timings at 256x128x128 and 384x192x192")
-    ap.add_argument("--profile-only", choices=["apply", "outer"], default=None,
+    ap.add_argument("--profile-only", choices=["apply", "outer", "cpfbto"], default=None,
                     help="run only a short loop of one kind (for rocprofv3)")
     return ap.parse_args()
 
 
-def outer_loop(g, p, dtype, steps, warmup, torch):
-    """Times `steps` outer iterations after `warmup` untimed ones."""
+def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None):
+    """Times `steps` outer iterations after `warmup` untimed ones (Alg. 1
+    with Jacobi-PCG, or with krylov=D Alg. 3 with the Krylov preconditioner
+    of degree D, beta = 1)."""
     dev = torch.device("cuda:0")
     x = g.project_volume(torch.tensor(p.x0, dtype=dtype, device=dev), lo=0.0, hi=1.0, vmax=p.vmax)
     u = torch.zeros(p.ndof, dtype=dtype, device=dev)
     f = torch.tensor(p.loads[0], dtype=dtype, device=dev)
     info = torch.zeros(8, dtype=torch.float64, device=dev)
     k = 1
+    def step(k):
+        if krylov is None:
+            g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+        else:
+            g.outer_step(x, u, f, k, ALPHA0_CFG3, krylov, 0.0, p.vmax, info=info, method="krylov", beta=1.0)
     for _ in range(warmup):
-        g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+        step(k)
         k += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+        step(k)
         k += 1
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -285,8 +293,10 @@ def main():
         if args.profile_only == "apply":
             for dtype in (torch.float32, torch.float64):
                 apply_timing(g, p, dtype, args.apply_reps, torch)
-        else:
+        elif args.profile_only == "outer":
             outer_loop(g, p, torch.float32, args.steps, args.warmup, torch)
+        else:
+            outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, krylov=KRYLOV_DEGREE)
         # a streaming kernel that reads and writes COPY_BYTES (b = 2 a, plain
         # global loads and stores) scales the HBM counters
         a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
@@ -300,6 +310,8 @@ def main():
     dt32, st32 = outer_loop(g, p, torch.float32, args.steps, args.warmup, torch)
     steps64 = max(10, args.steps // 2)
     dt64, st64 = outer_loop(g, p, torch.float64, steps64, args.warmup // 2, torch)
+    steps_cp = max(10, args.steps // 4)
+    dtcp, stcp = outer_loop(g, p, torch.float32, steps_cp, args.warmup // 2, torch, krylov=KRYLOV_DEGREE)
     t_apply32 = apply_timing(g, p, torch.float32, args.apply_reps, torch)
     t_apply64 = apply_timing(g, p, torch.float64, args.apply_reps, torch)
     t_apply32_cold = apply_timing(g, p, torch.float32, args.apply_reps, torch, cold=True)
@@ -365,6 +377,11 @@ def main():
         },
         "apply_K_sizes": sizes,
         "fp64_path": {"outer_iter_s": steps64 / dt64, "ms_per_step": dt64 / steps64 * 1e3},
+        "cpfbto_path": {"outer_iter_s": steps_cp / dtcp, "ms_per_step": dtcp / steps_cp * 1e3,
+                        "krylov_degree": KRYLOV_DEGREE, "beta": 1.0, "products_per_step": KRYLOV_DEGREE + 3,
+                        "final_state": stcp,
+                        "note": "Alg. 3 (CPFBTO): one low-level step with the Krylov preconditioner of "
+                                "Eq. LSP per outer iteration, FP32"},
         "final_state": {"fp32": st32, "fp64": st64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
