@@ -346,7 +346,35 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
     HIP_TRY(launch_resid<T>(g, rho, x, fr, R2, (const T*)nullptr, (T*)nullptr, 1, st, nullptr));  // R2 = f - K u
     int nb_v = 0, nb_a = 0;
     HIP_TRY(launch_minres<T>(g, 0, last, Y, R1, R2, W2, Wc, x, 0, 0, damp, st, &nb_v));
-    for (int itn = 1; itn <= D + 1; ++itn) {
+    int itn0 = 1;
+    if constexpr (sizeof(T) == 4) {
+      // FP32: iterations 1 .. D fused (vector pass t with the product of
+      // t + 1); products alternate between two buffers, the Lanczos
+      // vectors rotate through three (halo nodes read them while their
+      // owners write the next one)
+      T* Yb[2] = {(T*)V.w[0], (T*)V.w[1]};
+      T* R3 = (T*)V.s[0];
+      HIP_TRY(launch_apply_cg<T>(g, rho, R2, R2, Yb[1], 1, 1, st, &nb_a));
+      for (int itn = 1; itn <= D; ++itn) {
+        int nb = 0;
+        HIP_TRY(launch_minres_fused<T>(g, rho, itn, Yb[itn & 1], R1, R2, R3, Wc, W2, x, Yb[(itn + 1) & 1], nb_a,
+                                       nb_v, damp, st, &nb));
+        nb_a = nb_v = nb;
+        T* t = R1;
+        R1 = R2;
+        R2 = R3;
+        R3 = t;
+        if (itn >= 2) std::swap(Wc, W2);
+      }
+      // iteration D + 1: the unfused vector pass on the last product
+      int nb = 0;
+      HIP_TRY(launch_minres<T>(g, D + 1, last, Yb[(D + 1) & 1], R1, R2, W2, Wc, x, nb_a, nb_v, damp, st, &nb));
+      nb_v = nb;
+      std::swap(R1, R2);
+      if (D + 1 >= 2) std::swap(Wc, W2);
+      itn0 = D + 2;
+    }
+    for (int itn = itn0; itn <= D + 1; ++itn) {
       // Y = K R2 with <A.r, R2> and <Y, R2>; A.r = R1 (R2 on the first iteration, where R1 is unused)
       HIP_TRY(launch_apply_cg<T>(g, rho, R2, itn == 1 ? R2 : R1, Y, 1, itn, st, &nb_a));
       int nb = 0;

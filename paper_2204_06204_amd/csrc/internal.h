@@ -166,7 +166,7 @@ struct fbto_grid_s {
   int device = 0;
   int n_cu = 256;
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
-  fbto::TileChoice tiles[2][2][5] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
+  fbto::TileChoice tiles[2][2][6] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
 };
 
 namespace fbto {
@@ -248,5 +248,11 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
 template <typename T>
 hipError_t launch_minres(fbto_grid_s* g, int itn, int last, const T* Y, T* R1, const T* R2, T* W2, const T* W,
                          T* x, int n_apply, int n_prev, double damp, hipStream_t st, int* nb_out);
+// FP32: the vector pass of iteration itn (1 .. D) fused with iteration
+// itn + 1's product (k_apply's MRF mode): y -> R3, K y -> Ynext.
+template <typename T>
+hipError_t launch_minres_fused(fbto_grid_s* g, const T* rho, int itn, const T* Y, const T* R1, const T* R2, T* R3,
+                               const T* W, T* W2, T* x, T* Ynext, int n_apply, int n_kr, double damp,
+                               hipStream_t st, int* nb_out);
 
 }  // namespace fbto

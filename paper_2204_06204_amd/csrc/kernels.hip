@@ -101,7 +101,13 @@ static int flat_grid(int64_t n) {
 //          Input and output sets are distinct buffers: halo nodes of a tile
 //          are read by its neighbours while their owner writes the update.
 // ===========================================================================
-enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4 };
+//   MRF    the fused MINRES step of the Krylov low-level step (one RHS):
+//          the vector pass of iteration t (see k_minres) done where each
+//          node is staged, and iteration t + 1's product K y of the new
+//          Lanczos vector y in the same pass.  Y, R1, R2 are read at halo
+//          nodes too, so y goes to a third buffer R3 and the product to the
+//          other Y buffer.
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4, MODE_MRF = 5 };
 constexpr int kApplyMaxThreads = 512;
 constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
@@ -142,6 +148,11 @@ struct ApplyArgs {
   T* dobj;                           // [E] -ds_e x_e^T KE x_e (times Hsi_e)
   const T* Hsi;                      // [E] 1/Hs_e, or NULL
   const T* fvec;                     // loads, for f . x (NULL: not formed)
+  // MRF only (fused MINRES step; `step` is the iteration t, A.y the product)
+  const T *mY, *mR1, *mR2, *mW;      // K R2 of iteration t, Lanczos vectors t - 1 and t, direction t - 2
+  T *mR3, *mW2, *mx;                 // new Lanczos vector; direction t - 3 in, t - 1 out; iterate
+  int n_kr;                          // partial count of ||R2||^2
+  double damp;                       // step size of the low-level step
 };
 
 // Step coefficients of the Chronopoulos-Gear recurrence for one RHS from
@@ -261,6 +272,14 @@ struct FusedStage {
   unsigned m[2];
 };
 
+// Loads of one node plane for the fused MINRES step.
+template <typename T>
+struct MinresStage {
+  T w[3], w2[3], x[3];                    // owned node only
+  T y[2][3], r1[2][3], r2[2][3];
+  unsigned m[2];
+};
+
 template <typename T, int NR, int MODE>
 __global__ void __launch_bounds__(kApplyMaxThreads)
     k_apply(ApplyArgs<T> A, int rhs0) {
@@ -374,6 +393,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   };
 
   static_assert(MODE != MODE_CGF || NR == 1, "the fused CG step handles one RHS per launch");
+  static_assert(MODE != MODE_MRF || NR == 1, "the fused MINRES step handles one RHS per launch");
   constexpr int NP = MODE == MODE_APPLY ? 1 : 4 * NR;  // partial values per block
   double part[NP];
 #pragma unroll
@@ -471,8 +491,141 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     }
   };
 
+  // fused MINRES step: the scalar recurrence of iteration t (every block,
+  // same order; block 0 keeps the state), as in k_minres
+  T ms = (T)0, mc1 = (T)0, mas = (T)0, minvb = (T)0, mwc1 = (T)0, mwc2 = (T)0, minvg = (T)0, mstep = (T)0;
+  auto uniform = [](T v) -> T {  // the value is the same in every lane: keep it in a scalar register
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+    else return v;
+  };
+  auto mrf_prologue = [&]() {
+    const int itn = A.step;
+    double v[3];
+    const double* src[3] = {pslot(A.P, P_KRN0 + ((itn - 1) & 1), 0, A.maxp), pslot(A.P, P_RZ0 + (itn & 1), 0, A.maxp),
+                            pslot(A.P, P_PQ0 + (itn & 1), 0, A.maxp)};
+    const int cnt[3] = {A.n_kr, A.n_apply, A.n_apply};
+    reduce_parts<3, 0u>(v, src, cnt);
+    const double beta = sqrt(fmax(v[0], 0.0)), r12 = v[1], yr2 = v[2];
+    double oldb = 0.0, alfa_prev = 0.0, dbar = 0.0, epsln = 0.0, phibar = beta, cs = -1.0, sn = 0.0;
+    Scalars* sc = const_cast<Scalars*>(A.sc);
+    if (itn >= 2) {
+      const double* k = sc->kr[(itn + 1) & 1];
+      oldb = k[0];
+      alfa_prev = k[1];
+      dbar = k[2];
+      epsln = k[3];
+      phibar = k[4];
+      cs = k[5];
+      sn = k[6];
+    }
+    double oldeps = 0.0, delta = 0.0, gamma = 1.0, phi = 0.0;
+    if (itn >= 2) {
+      oldeps = epsln;
+      delta = cs * dbar + sn * alfa_prev;
+      const double gbar = sn * dbar - cs * alfa_prev;
+      epsln = sn * beta;
+      dbar = -cs * beta;
+      gamma = fmax(sqrt(gbar * gbar + beta * beta), 1e-300);
+      cs = gbar / gamma;
+      sn = beta / gamma;
+      phi = cs * phibar;
+      phibar = sn * phibar;
+    }
+    const double sv = beta > 0.0 ? 1.0 / beta : 0.0;
+    const double c1 = (itn >= 2 && oldb > 0.0) ? beta / oldb : 0.0;
+    const double alfa = sv * (sv * yr2 - c1 * r12);
+    if (lb == 0 && tid == 0) {
+      double* k = sc->kr[itn & 1];
+      k[0] = beta;
+      k[1] = alfa;
+      k[2] = dbar;
+      k[3] = epsln;
+      k[4] = phibar;
+      k[5] = cs;
+      k[6] = sn;
+    }
+    ms = uniform((T)sv);
+    mc1 = uniform((T)c1);
+    mas = uniform((T)(alfa * sv));
+    minvb = uniform((T)(oldb > 0.0 ? 1.0 / oldb : 0.0));
+    mwc1 = uniform((T)oldeps);
+    mwc2 = uniform((T)delta);
+    minvg = uniform((T)(1.0 / gamma));
+    mstep = uniform((T)(A.damp * phi));
+  };
+  auto issue_m = [&](int k, MinresStage<T>& S) {
+    const bool kv = k >= 0 && k <= G.nz;
+    const bool own_plane = k >= k0 && k < kend;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const bool ok = kv && gcol[sl] >= 0;
+      const int n = ok ? gcol[sl] + k * plane : 0;
+      const unsigned mv = A.mask[n];
+      S.m[sl] = ok ? mv : 7u;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        S.y[sl][c] = A.mY[3 * n + c];
+        S.r1[sl][c] = A.mR1[3 * n + c];
+        S.r2[sl][c] = A.mR2[3 * n + c];
+      }
+      if (sl == 0) {  // the iterate and the directions: owner only, other threads read node 0
+        const int no = (own_plane && writer && ok) ? n : 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          S.w[c] = A.mW[3 * no + c];
+          S.w2[c] = A.mW2[3 * no + c];
+          S.x[c] = A.mx[3 * no + c];
+        }
+      }
+    }
+  };
+  auto stage_m = [&](const MinresStage<T>& S, int buf, int k, T (&zq)[3]) {
+    T* nb = nodes + buf * (3 * NS);
+    const bool own_plane = k >= k0 && k < kend;
+    const int itn = A.step;
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      T yn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const T r1m = itn >= 2 ? S.r1[sl][c] : (T)0;  // R1 holds no vector yet on the first iteration
+        yn[c] = ms * S.y[sl][c] - mc1 * r1m - mas * S.r2[sl][c];
+        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : yn[c];
+      }
+      if (sl == 0) {
+        const bool owner = writer && own_plane;
+        const int64_t o = 3 * (int64_t)(owner ? gcol[0] + k * plane : 0);
+        T* const sink = A.sink + kSinkStride * tid;
+        T* r3o = owner ? A.mR3 + o : sink;
+        T* w2o = owner ? A.mW2 + o : sink + 3;
+        T* xo = owner ? A.mx + o : sink + 6;
+        T wn[3], xn[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          zq[c] = yn[c];  // unmasked: the output of a fixed DOF
+          const T wm = itn >= 3 ? S.w[c] : (T)0, w2m = itn >= 4 ? S.w2[c] : (T)0;
+          wn[c] = (S.r1[0][c] * minvb - mwc1 * w2m - mwc2 * wm) * minvg;
+          xn[c] = S.x[c] + mstep * wn[c];
+          if (owner) {
+            part[0] += (double)yn[c] * (double)yn[c];        // ||y||^2
+            part[2] += (double)S.r2[0][c] * (double)yn[c];   // <R2, y>: R1.R2 of iteration t + 1
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r3o[c] = yn[c];
+        if (itn >= 2) {  // finishes iteration t - 1 (uniform)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) w2o[c] = wn[c];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) xo[c] = xn[c];
+        }
+      }
+    }
+  };
+
   ApplyStage<T, NR> S[2];
   FusedStage<T> SF;
+  MinresStage<T> SM;
   T F[2][NR][4][3];
   T own[2][NR][3];
   T carry[NR][4][3];
@@ -521,6 +674,16 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     mq = SF.m[0] & 0xffu;
     stage_f(SF1, (ez0 + 1) & 1, ez0 + 1, rq[1][0]);
     mq |= (SF1.m[0] & 0xffu) << 8;
+  } else if constexpr (MODE == MODE_MRF) {
+    MinresStage<T> SM1;
+    issue_m(ez0, SM);
+    rho_next = load_rho(ez0);
+    issue_m(ez0 + 1, SM1);
+    mrf_prologue();
+    stage_m(SM, ez0 & 1, ez0, rq[0][0]);
+    mq = SM.m[0] & 0xffu;
+    stage_m(SM1, (ez0 + 1) & 1, ez0 + 1, rq[1][0]);
+    mq |= (SM1.m[0] & 0xffu) << 8;
   } else {
     issue(ez0, S[0]);
     issue(ez0 + 1, S[1]);
@@ -552,6 +715,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     if constexpr (kOwnQ) load_own(ez + 1, oq[P ^ 1]);
     if constexpr (MODE == MODE_CGF) {
       issue_f(ez + 2, SF);
+    } else if constexpr (MODE == MODE_MRF) {
+      issue_m(ez + 2, SM);
     } else {
       issue(ez + 3, S[P ^ 1]);
     }
@@ -578,6 +743,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     if constexpr (MODE == MODE_CGF) {
       stage_f(SF, ez & 1, ez + 2, rq[2][0]);
       mq |= (SF.m[0] & 0xffu) << 16;
+    } else if constexpr (MODE == MODE_MRF) {
+      stage_m(SM, ez & 1, ez + 2, rq[2][0]);
+      mq |= (SM.m[0] & 0xffu) << 16;
     } else {
       stage(S[P], ez & 1);
       mq |= (S[P].m[0] & 0xffu) << 16;
@@ -677,9 +845,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
               part[4 * r + 3] = fmax(part[4 * r + 3], own_only(fabs((double)rv)));
             }
           }
-          if constexpr (MODE == MODE_CGF) {
+          if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) part[1] += own_only((double)acc[c] * (double)pv[c]);  // w'.z'
+            for (int c = 0; c < 3; ++c) part[1] += own_only((double)acc[c] * (double)pv[c]);  // w'.z' / <K y, y>
           }
         }
       }
@@ -711,6 +879,15 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       dst[4 * r + 3] = pslot(A.P, P_RI0 + par, rhs0 + r, A.maxp);
     }
     write_parts<4 * NR, 0x8888u>(part, dst, lb);
+  }
+  if constexpr (MODE == MODE_MRF) {
+    // ||y||^2 -> the norm slot of iteration t; <K y, y> and <R2, y> -> the
+    // product partials of iteration t + 1
+    const int itn = A.step;
+    double v[3] = {part[0], part[1], part[2]};
+    double* dst[3] = {pslot(A.P, P_KRN0 + (itn & 1), 0, A.maxp), pslot(A.P, P_PQ0 + ((itn + 1) & 1), 0, A.maxp),
+                      pslot(A.P, P_RZ0 + ((itn + 1) & 1), 0, A.maxp)};
+    write_parts<3, 0u>(v, dst, lb);
   }
   if constexpr (MODE == MODE_RESID) {
     if (A.invD == nullptr && A.invD_out == nullptr) return;
@@ -1184,6 +1361,26 @@ hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, con
     A.n_fn = n_fn;
     A.rtol = rtol;
     return launch_apply_mode<T, MODE_CGF>(g, A, nrhs, st, nb_out);
+  }
+}
+
+template <typename T>
+hipError_t launch_minres_fused(fbto_grid_s* g, const T* rho, int itn, const T* Y, const T* R1, const T* R2, T* R3,
+                               const T* W, T* W2, T* x, T* Ynext, int n_apply, int n_kr, double damp,
+                               hipStream_t st, int* nb_out) {
+  if constexpr (sizeof(T) == 8) {
+    return hipErrorNotSupported;
+  } else {
+    ApplyArgs<T> A{};
+    A.rho = rho;
+    A.y = Ynext;
+    A.step = itn;
+    A.mY = Y; A.mR1 = R1; A.mR2 = R2; A.mW = W;
+    A.mR3 = R3; A.mW2 = W2; A.mx = x;
+    A.n_apply = n_apply;
+    A.n_kr = n_kr;
+    A.damp = damp;
+    return launch_apply_mode<T, MODE_MRF>(g, A, 1, st, nb_out);
   }
 }
 
@@ -2258,6 +2455,8 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
                                              hipStream_t);                                             \
   template hipError_t launch_minres<T>(fbto_grid_s*, int, int, const T*, T*, const T*, T*, const T*, T*, \
                                        int, int, double, hipStream_t, int*);                          \
+  template hipError_t launch_minres_fused<T>(fbto_grid_s*, const T*, int, const T*, const T*, const T*, T*,  \
+                                             const T*, T*, T*, T*, int, int, double, hipStream_t, int*);  \
   template hipError_t launch_sens<T>(fbto_grid_s*, const T*, const T*, const T*, int, T*, const T*,    \
                                      hipStream_t);                                                     \
   template hipError_t launch_dot<T>(fbto_grid_s*, const T*, const T*, int, hipStream_t);               \
