@@ -223,6 +223,17 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
                               int32_t inner_steps, int32_t mean_project, double lo,
                               double vmax, double* info, void* stream);
 
+/* One step of projected gradient descent with an exact low-level solve,
+ * the baseline the paper compares against (Sec. 5): as fbto_outer_step,
+ * but u is refined by Jacobi-PCG until ||f - K u||_2 <= rtol ||f||_2 (or
+ * max_steps steps), so the gradient is that of the true objective and
+ * info's compliance is the true objective f^T K^-1 f (to rtol).  The
+ * stream is synchronised every 64 PCG steps.  rtol: (0, 1). */
+fbto_status_t fbto_outer_step_exact(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
+                                    const void* f, int32_t nrhs, int32_t k, double alpha0,
+                                    double rtol, int32_t max_steps, int32_t mean_project,
+                                    double lo, double vmax, double* info, void* stream);
+
 /* One outer iteration k of Alg. 3 (CPFBTO): as fbto_outer_step, with the
  * low-level update replaced by one step with the Krylov preconditioner of
  * degree `degree` (Eq. LSP, fbto_inner_solve's FBTO_KRYLOV):

@@ -29,7 +29,7 @@ from .grid import Grid
 from .operator import apply_K, assemble_K, jacobi_diag, simp_dscale, simp_scale
 from .projection import project_alg4
 from .sensitivity import element_energy
-from .solve import krylov_step_ref, pcg_ref
+from .solve import krylov_step_ref, pcg_ref, solve_direct
 
 
 def step_size(alpha0: float, k: int) -> float:
@@ -73,7 +73,8 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
     """Returns (x_new, u_new, OuterRecord, g_x).  low_level=None runs
     `inner_steps` Jacobi-PCG steps; ("krylov", D, beta) runs Alg. 3's one
     preconditioned step u <- u - beta M^-1 (K u - f) (r_inf is then the true
-    residual after the step)."""
+    residual after the step); ("exact",) solves K u = f directly (sparse LU),
+    the projected-gradient-descent baseline."""
     g = ctx.grid
     rho = filter_forward(ctx.H, ctx.Hs, x)
     s = simp_scale(rho, ctx.penal, ctx.rho_min)
@@ -83,9 +84,14 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
     F = np.atleast_2d(f)
     U = np.array(np.atleast_2d(u), dtype=np.float64, copy=True)
     r_inf = 0.0
+    if low_level is not None and low_level[0] == "exact":
+        Kx = assemble_K(g, s, ctx.fixed, ctx.springs, ctx.KE)
     for r in range(F.shape[0]):
         if low_level is None:
             U[r], res = pcg_ref(A, D, F[r], U[r], inner_steps)
+        elif low_level[0] == "exact":
+            U[r] = solve_direct(Kx, F[r])
+            res = F[r] - Kx @ U[r]
         else:
             _, deg, beta = low_level
             U[r], res = krylov_step_ref(A, F[r], U[r], deg, beta)

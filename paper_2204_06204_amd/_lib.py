@@ -43,6 +43,8 @@ _SIGS = {
                                       _VP, _VP]),
     "fbto_outer_step": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                   C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
+    "fbto_outer_step_exact": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
+                                        C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_krylov": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                          C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_last_error": (C.c_char_p, []),

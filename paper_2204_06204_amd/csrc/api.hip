@@ -403,7 +403,7 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
 template <typename T>
 fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k, double alpha0,
                         int inner_steps, int mean_project, double lo, double vmax, double* info,
-                        hipStream_t st, int krylov_degree = -1, double beta = 1.0) {
+                        hipStream_t st, int krylov_degree = -1, double beta = 1.0, double inner_rtol = 0.0) {
   Vecs& V = vecs<T>(g);
   T* rho = (T*)V.rho;
   HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
@@ -411,7 +411,7 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   bool sens_done = false;
   fbto_status_t s = krylov_degree >= 0
                         ? krylov_run<T>(g, rho, f, u, nrhs, krylov_degree, beta, st, &cn)
-                        : pcg_run<T>(g, rho, f, u, nrhs, inner_steps, 0.0, st, true, &cn, (T*)V.ge,
+                        : pcg_run<T>(g, rho, f, u, nrhs, inner_steps, inner_rtol, st, true, &cn, (T*)V.ge,
                                      (const T*)V.Hs, &sens_done);
   if (s != FBTO_OK) return s;
   // element gradient already divided by Hs, so the filter transpose is a plain sum
@@ -789,6 +789,33 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
     if ((s = ensure_vecs<float>(g))) return s;
     s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, inner_steps,
                          mean_project, lo, vmax, info, st);
+  }
+  if (s) return s;
+  return ok();
+}
+
+fbto_status_t fbto_outer_step_exact(fbto_grid_t g, fbto_prec_t prec, void* x, void* u, const void* f,
+                                    int32_t nrhs, int32_t k, double alpha0, double rtol, int32_t max_steps,
+                                    int32_t mean_project, double lo, double vmax, double* info, void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!x || !u || !f) return fail(FBTO_ERR_ARG, "x, u and f must be non-NULL");
+  if (k < 1) return fail(FBTO_ERR_ARG, "k is 1-based");
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(FBTO_ERR_ARG, "rtol must be in (0, 1)");
+  if (max_steps < 1) return fail(FBTO_ERR_ARG, "max_steps must be >= 1");
+  if (!(std::isfinite(alpha0) && alpha0 >= 0.0)) return fail(FBTO_ERR_ARG, "alpha0 must be finite and >= 0");
+  if (!(std::isfinite(lo) && lo <= 1.0)) return fail(FBTO_ERR_ARG, "need lo <= 1");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g", vmax, lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    s = outer_run<double>(g, (double*)x, (double*)u, (const double*)f, nrhs, k, alpha0, max_steps, mean_project,
+                          lo, vmax, info, st, -1, 1.0, rtol);
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, max_steps, mean_project, lo,
+                         vmax, info, st, -1, 1.0, rtol);
   }
   if (s) return s;
   return ok();

@@ -175,10 +175,12 @@ class Grid:
 
     def outer_step(self, x, u, f, k: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
                    mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None,
-                   method: str = "pcg", beta: float = 1.0):
+                   method: str = "pcg", beta: float = 1.0, rtol: float = 1e-8):
         """method "pcg": Alg. 1 with `inner_steps` Jacobi-PCG steps
         (fbto_outer_step); "krylov": Alg. 3 with one Krylov-preconditioned
-        step of degree `inner_steps` and step `beta` (fbto_outer_step_krylov)."""
+        step of degree `inner_steps` and step `beta` (fbto_outer_step_krylov);
+        "exact": projected gradient descent with the low-level problem solved
+        to `rtol` in at most `inner_steps` PCG steps (fbto_outer_step_exact)."""
         nr = self._nrhs(u)
         common = (self.handle, _prec(x), _ptr(x, None, self.E, "x"), _ptr(u, x.dtype, None, "u"),
                   _ptr(f, x.dtype, u.numel(), "f"), nr, int(k), float(alpha0))
@@ -188,6 +190,8 @@ class Grid:
             check(self.lib.fbto_outer_step(*common, int(inner_steps), *tail), self.lib)
         elif method == "krylov":
             check(self.lib.fbto_outer_step_krylov(*common, int(inner_steps), float(beta), *tail), self.lib)
+        elif method == "exact":
+            check(self.lib.fbto_outer_step_exact(*common, float(rtol), int(inner_steps), *tail), self.lib)
         else:
             raise ValueError(f"unknown method {method!r}")
         return x

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("fbto_setup_grid", "fbto_apply_K", "fbto_inner_solve", "fbto_sensitivity",
               "fbto_filter", "fbto_project_volume", "fbto_outer_step", "fbto_solve_refined",
-              "fbto_outer_step_krylov", "fbto_destroy_grid", "fbto_last_error"):
+              "fbto_outer_step_krylov", "fbto_outer_step_exact", "fbto_destroy_grid", "fbto_last_error"):
         assert n in names
 
 
@@ -70,5 +70,7 @@ def test_host_side_argument_errors(lib):
     assert lib.fbto_outer_step(None, 0, None, None, None, 1, 1, 0.1, 1, 1, 0.0, 1.0, None, None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_outer_step_krylov(None, 0, None, None, None, 1, 1, 0.1, 20, 1.0, 1, 0.0, 1.0, None,
                                       None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_outer_step_exact(None, 0, None, None, None, 1, 1, 0.1, 1e-8, 100, 1, 0.0, 1.0, None,
+                                     None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_project_volume(None, 0, None, None, 0.0, 1.0, 1.0, None, None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_version().decode().startswith("fbto")

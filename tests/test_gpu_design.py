@@ -103,8 +103,10 @@ def test_projection_inactive_and_infeasible():
         g.project_volume(y, lo=0.5, hi=1.0, vmax=0.1 * p.E)
 
 
-def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None):
-    """krylov=(D, beta): Alg. 3's outer step (fbto_outer_step_krylov)."""
+def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None, exact_rtol=None):
+    """krylov=(D, beta): Alg. 3's outer step (fbto_outer_step_krylov);
+    exact_rtol: projected gradient descent with the solve run to that
+    tolerance (fbto_outer_step_exact)."""
     g = g or _grid(p)
     x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
     u = torch.zeros(p.nrhs * p.ndof, dtype=dtype, device=DEV)
@@ -112,7 +114,9 @@ def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None):
     info = torch.zeros(8, dtype=torch.float64, device=DEV)
     recs, xs = [], []
     for k in range(1, iters + 1):
-        if krylov is None:
+        if exact_rtol is not None:
+            g.outer_step(x, u, f, k, alpha0, 20000, 0.0, p.vmax, info=info, method="exact", rtol=exact_rtol)
+        elif krylov is None:
             g.outer_step(x, u, f, k, alpha0, p.inner_steps, 0.0, p.vmax, info=info)
         else:
             g.outer_step(x, u, f, k, alpha0, krylov[0], 0.0, p.vmax, info=info, method="krylov",
@@ -251,3 +255,28 @@ def test_cpfbto_fp32_one_step_against_oracle():
         assert abs(recs[k][0] - rrecs[k].compliance) <= 2e-5 * rrecs[k].compliance
         assert np.abs(xs[k] - rxs[k + 1]).max() <= 2e-5
         assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-3 * rrecs[k].r_inf
+
+
+def test_pgd_with_exact_solves_cfg1_fp64():
+    """The paper's baseline: projected gradient descent with the low-level
+    problem solved exactly (here to 1e-12).  Against the oracle's outer step
+    with 4,000 PCG steps (exact to rounding at this size) over 5 iterations:
+    compliance and design to 1e-9; the reported compliance is the true
+    objective f^T K^-1 f of the filtered design (direct solve)."""
+    from oracle.density_filter import filter_forward
+    say("pgd exact cfg1 fp64")
+    p = synth.config("cfg1")
+    alpha0 = 0.0016874513029055756
+    recs, xs, _ = _run_gpu(p, 5, alpha0, torch.float64, exact_rtol=1e-12)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 5, alpha0, 0, 0.0, 1.0, p.vmax,
+                                      low_level=("exact",))
+    for k in range(5):
+        assert abs(recs[k][0] - rrecs[k].compliance) <= 1e-9 * rrecs[k].compliance, k
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= 1e-9, k
+        # true objective at the design the step started from
+        s = oracle.simp_scale(filter_forward(ctx.H, ctx.Hs, rxs[k]))
+        K = oracle.assemble_K(ctx.grid, s, p.fixed_mask)
+        f = p.loads[0]
+        c_true = float(f @ oracle.solve_direct(K, f))
+        assert abs(recs[k][0] - c_true) <= 1e-9 * c_true, k

@@ -72,3 +72,17 @@ def test_cpfbto_step_uses_one_gmres_cycle():
     assert np.abs(u1 - ug).max() <= 1e-9 * np.abs(ug - u0).max()
     assert abs(rec.r_inf - np.abs(p.loads[0] - K @ ug).max()) <= 1e-9 * rec.r_inf
     assert abs(rec.compliance - p.loads[0] @ ug) <= 1e-9 * abs(rec.compliance)
+
+
+def test_exact_low_level_equals_many_pcg_steps():
+    """The oracle's direct low-level solve (the PGD baseline) gives the same
+    outer step as Jacobi-PCG run to convergence."""
+    p = synth.cantilever(4, 3, 3, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=1, seed=1)
+    ctx = _ctx(p)
+    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    u0 = np.zeros(p.ndof)
+    xe, ue, re_, _ = outer_step_ref(ctx, x, u0, p.loads[0], 1, 0.05, 0, 0.0, 1.0, p.vmax, low_level=("exact",))
+    xp, up, rp, _ = outer_step_ref(ctx, x, u0, p.loads[0], 1, 0.05, 150, 0.0, 1.0, p.vmax)
+    assert np.abs(ue - up).max() <= 1e-9 * np.abs(ue).max()
+    assert np.abs(xe - xp).max() <= 1e-10
+    assert abs(re_.compliance - rp.compliance) <= 1e-10 * re_.compliance
