@@ -34,6 +34,7 @@ ALPHA0_CFG3 = 0.0016591384929631413      # tests/golden/alpha0.json (oracle-gene
 KERNEL_SOURCES = ("paper_2204_06204_amd/csrc/kernels.hip", "paper_2204_06204_amd/csrc/device.h")
 COPY_BYTES = 256 << 20                   # calibration copy of the HBM counters
 KRYLOV_DEGREE = 20                       # D of Alg. 3's Krylov preconditioner (the paper's choice)
+PGD_RTOL = 1e-5                          # low-level tolerance of the exact-solve baseline (FP32 solves)
 
 
 def kernel_hash() -> str:
@@ -79,10 +80,11 @@ def parse():
     return ap.parse_args()
 
 
-def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None):
+def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None):
     """Times `steps` outer iterations after `warmup` untimed ones (Alg. 1
     with Jacobi-PCG, or with krylov=D Alg. 3 with the Krylov preconditioner
-    of degree D, beta = 1)."""
+    of degree D, beta = 1, or with exact_rtol projected gradient descent
+    with the low-level problem solved to that relative residual)."""
     dev = torch.device("cuda:0")
     x = g.project_volume(torch.tensor(p.x0, dtype=dtype, device=dev), lo=0.0, hi=1.0, vmax=p.vmax)
     u = torch.zeros(p.ndof, dtype=dtype, device=dev)
@@ -90,7 +92,9 @@ def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None):
     info = torch.zeros(8, dtype=torch.float64, device=dev)
     k = 1
     def step(k):
-        if krylov is None:
+        if exact_rtol is not None:
+            g.outer_step(x, u, f, k, ALPHA0_CFG3, 100000, 0.0, p.vmax, info=info, method="exact", rtol=exact_rtol)
+        elif krylov is None:
             g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
         else:
             g.outer_step(x, u, f, k, ALPHA0_CFG3, krylov, 0.0, p.vmax, info=info, method="krylov", beta=1.0)
@@ -106,7 +110,19 @@ def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None):
     dt = time.perf_counter() - t0
     inf = info.cpu().tolist()
     return dt, {"compliance": inf[0], "dx_inf": inf[1], "r_inf": inf[2], "lambda": inf[3],
-                "volume": inf[4], "status": inf[6], "k_last": k - 1}
+                "volume": inf[4], "status": inf[6], "k_last": k - 1,
+                "true_compliance": true_compliance(g, p, x, torch)}
+
+
+def true_compliance(g, p, x, torch):
+    """f^T K(C(x))^-1 f at design x, solved in FP64 with FP32 inner solves and
+    FP64 refinement to a relative residual of 1e-9 (the objective the inexact
+    low-level solves track)."""
+    rho = g.filter(x.double().contiguous())
+    f = torch.tensor(p.loads[0], dtype=torch.float64, device=x.device)
+    u = torch.zeros_like(f)
+    g.solve_refined(rho, f, u, 1e-9, 100, 20000, inner_dtype=torch.float32, inner_rtol=1e-3)
+    return float(torch.dot(f, u))
 
 
 def apply_timing(g, p, dtype, reps, torch, cold=False, binary=False):
@@ -312,6 +328,8 @@ def main():
     dt64, st64 = outer_loop(g, p, torch.float64, steps64, args.warmup // 2, torch)
     steps_cp = max(10, args.steps // 4)
     dtcp, stcp = outer_loop(g, p, torch.float32, steps_cp, args.warmup // 2, torch, krylov=KRYLOV_DEGREE)
+    steps_pgd = 10
+    dtpgd, stpgd = outer_loop(g, p, torch.float32, steps_pgd, 2, torch, exact_rtol=PGD_RTOL)
     t_apply32 = apply_timing(g, p, torch.float32, args.apply_reps, torch)
     t_apply64 = apply_timing(g, p, torch.float64, args.apply_reps, torch)
     t_apply32_cold = apply_timing(g, p, torch.float32, args.apply_reps, torch, cold=True)
@@ -390,6 +408,10 @@ def main():
                                f"{bytes_fused} per launch, {t_fused * 1e6:.2f} us per launch"},
         "outer_roofline": {"bytes_per_iter": bytes_outer, "ceiling_iter_s": HBM_PEAK_GBS * 1e9 / bytes_outer,
                            "frac": value * bytes_outer / (HBM_PEAK_GBS * 1e9)},
+        "pgd_path": {"outer_iter_s": steps_pgd / dtpgd, "ms_per_step": dtpgd / steps_pgd * 1e3,
+                     "rtol": PGD_RTOL, "final_state": stpgd,
+                     "note": "projected gradient descent with the low-level problem solved to rtol "
+                             "(FP32 Jacobi-PCG, warm-started), the paper's baseline"},
         "fixed_error": fixed,
         "cpu_baseline": cpu,
         "kernel_hash": kernel_hash(),
