@@ -80,7 +80,7 @@ def parse():
     return ap.parse_args()
 
 
-def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None):
+def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None, alpha0=None, true_obj=True):
     """Times `steps` outer iterations after `warmup` untimed ones (Alg. 1
     with Jacobi-PCG, or with krylov=D Alg. 3 with the Krylov preconditioner
     of degree D, beta = 1, or with exact_rtol projected gradient descent
@@ -91,13 +91,14 @@ def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None):
     f = torch.tensor(p.loads[0], dtype=dtype, device=dev)
     info = torch.zeros(8, dtype=torch.float64, device=dev)
     k = 1
+    a0 = ALPHA0_CFG3 if alpha0 is None else alpha0
     def step(k):
         if exact_rtol is not None:
-            g.outer_step(x, u, f, k, ALPHA0_CFG3, 100000, 0.0, p.vmax, info=info, method="exact", rtol=exact_rtol)
+            g.outer_step(x, u, f, k, a0, 100000, 0.0, p.vmax, info=info, method="exact", rtol=exact_rtol)
         elif krylov is None:
-            g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+            g.outer_step(x, u, f, k, a0, p.inner_steps, 0.0, p.vmax, info=info)
         else:
-            g.outer_step(x, u, f, k, ALPHA0_CFG3, krylov, 0.0, p.vmax, info=info, method="krylov", beta=1.0)
+            g.outer_step(x, u, f, k, a0, krylov, 0.0, p.vmax, info=info, method="krylov", beta=1.0)
     for _ in range(warmup):
         step(k)
         k += 1
@@ -111,7 +112,7 @@ def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None):
     inf = info.cpu().tolist()
     return dt, {"compliance": inf[0], "dx_inf": inf[1], "r_inf": inf[2], "lambda": inf[3],
                 "volume": inf[4], "status": inf[6], "k_last": k - 1,
-                "true_compliance": true_compliance(g, p, x, torch)}
+                "true_compliance": true_compliance(g, p, x, torch) if true_obj else None}
 
 
 def true_compliance(g, p, x, torch):
@@ -221,6 +222,38 @@ def fixed_error(g, p, torch, rtol=1e-8):
                                    "rel_residual": imix[0] / imix[2],
                                    "compliance_rel_diff_vs_fp64": abs(cmix - c64) / abs(c64)}
     out["speedup_mixed_vs_fp64"] = t64 / tmix if tmix > 0 else None
+    return out
+
+
+def outer_sizes(torch):
+    """Outer iterations/s of the two smaller workloads as configured (16x8x8
+    with 5 PCG steps, 64x32x32 with 8), FP32 and FP64, step sizes from
+    tests/golden/alpha0.json."""
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+    a0 = json.load(open(os.path.join(ROOT, "tests", "golden", "alpha0.json")))
+    out = {}
+    for name in ("cfg1", "cfg2"):
+        p = synth.config(name)
+        g = Grid.from_problem(p)
+        for dtype, tag in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            dt, st = outer_loop(g, p, dtype, 100, 10, torch, alpha0=a0[name], true_obj=False)
+            out[f"{name}_{tag}"] = {"outer_iter_s": 100 / dt, "grid": [p.nx, p.ny, p.nz],
+                                    "inner_steps": p.inner_steps, "compliance": st["compliance"]}
+        g.close()
+    return out
+
+
+def fixed_error_cfg4(torch):
+    """The fixed-error comparison on the 256x128x128 bridge (supports at the
+    two bottom edges, uniform traction on the top face), seeded density."""
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+    p = synth.config("cfg4")
+    g = Grid.from_problem(p)
+    out = fixed_error(g, p, torch)
+    g.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -360,6 +393,8 @@ def main():
 
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
     sizes = None if args.no_sizes else apply_sizes(torch)
+    osizes = None if args.no_sizes else outer_sizes(torch)
+    fixed4 = None if (args.no_sizes or args.no_fixed_err) else fixed_error_cfg4(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(p, args.cpu_seconds)
 
     value = args.steps / dt32
@@ -413,6 +448,8 @@ def main():
                      "note": "projected gradient descent with the low-level problem solved to rtol "
                              "(FP32 Jacobi-PCG, warm-started), the paper's baseline"},
         "fixed_error": fixed,
+        "fixed_error_cfg4": fixed4,
+        "outer_sizes": osizes,
         "cpu_baseline": cpu,
         "kernel_hash": kernel_hash(),
     }
