@@ -112,6 +112,7 @@ constexpr int kApplyMaxThreads = 512;
 constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
 constexpr int kSinkStride = 16;  // sink entries per thread
+constexpr double kTinyNorm = 1e-30;  // Krylov step: a norm below this is zero (FP32 reciprocals stay finite)
 static_assert(kApplyMaxThreads * kSinkStride * sizeof(double) <= kSinkBytes, "sink too small");
 
 template <typename T>
@@ -531,8 +532,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       phi = cs * phibar;
       phibar = sn * phibar;
     }
-    const double sv = beta > 0.0 ? 1.0 / beta : 0.0;
-    const double c1 = (itn >= 2 && oldb > 0.0) ? beta / oldb : 0.0;
+    const double sv = beta > kTinyNorm ? 1.0 / beta : 0.0;  // as in k_minres
+    const double c1 = (itn >= 2 && oldb > kTinyNorm) ? beta / oldb : 0.0;
     const double alfa = sv * (sv * yr2 - c1 * r12);
     if (lb == 0 && tid == 0) {
       double* k = sc->kr[itn & 1];
@@ -547,10 +548,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     ms = uniform((T)sv);
     mc1 = uniform((T)c1);
     mas = uniform((T)(alfa * sv));
-    minvb = uniform((T)(oldb > 0.0 ? 1.0 / oldb : 0.0));
+    minvb = uniform((T)(oldb > kTinyNorm ? 1.0 / oldb : 0.0));
     mwc1 = uniform((T)oldeps);
     mwc2 = uniform((T)delta);
-    minvg = uniform((T)(1.0 / gamma));
+    minvg = uniform((T)(gamma > kTinyNorm ? 1.0 / gamma : 0.0));
     mstep = uniform((T)(A.damp * phi));
   };
   auto issue_m = [&](int k, MinresStage<T>& S) {
@@ -1732,9 +1733,12 @@ __global__ void __launch_bounds__(kVecBlock)
     phi = cs * phibar;
     phibar = sn * phibar;
   }
-  // Lanczos step of iteration itn
-  const double s = beta > 0.0 ? 1.0 / beta : 0.0;
-  const double c1 = (itn >= 2 && oldb > 0.0) ? beta / oldb : 0.0;
+  // Lanczos step of iteration itn.  Norms below kTinyNorm mean the Krylov
+  // space is exhausted (the residual is zero to rounding): the
+  // reciprocals are then taken as 0, so every further vector and update is
+  // 0 rather than 0 * inf in FP32.
+  const double s = beta > kTinyNorm ? 1.0 / beta : 0.0;
+  const double c1 = (itn >= 2 && oldb > kTinyNorm) ? beta / oldb : 0.0;
   const double alfa = lanczos ? s * (s * yr2 - c1 * r12) : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && itn >= 1) {
     double* k = sc->kr[itn & 1];
@@ -1747,8 +1751,9 @@ __global__ void __launch_bounds__(kVecBlock)
     k[6] = sn;
   }
   const int j = itn - 1;  // the iteration finished here
-  const T inv_oldb = (T)(oldb > 0.0 ? 1.0 / oldb : 0.0);
-  const T wc1 = (T)oldeps, wc2 = (T)delta, inv_gamma = (T)(1.0 / gamma), step = (T)(damp * phi);
+  const T inv_oldb = (T)(oldb > kTinyNorm ? 1.0 / oldb : 0.0);
+  const T wc1 = (T)oldeps, wc2 = (T)delta, inv_gamma = (T)(gamma > kTinyNorm ? 1.0 / gamma : 0.0);
+  const T step = (T)(damp * phi);
   const T ts = (T)s, tc1 = (T)c1, ta = (T)(alfa * s);
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {

@@ -234,14 +234,16 @@ def test_krylov_step_cfg3_residual_decreases():
         prev = rn
 
 
-def test_krylov_step_at_the_solution_is_a_fixed_point():
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_krylov_step_at_the_solution_is_a_fixed_point(dtype):
     """Degenerate case: from the exact solution the residual is zero, every
-    Lanczos vector vanishes, and the step must leave u unchanged (no 0/0)."""
+    Lanczos vector vanishes, and the step must leave u unchanged (no 0/0,
+    no 0 * inf in FP32)."""
     p = synth.cantilever(6, 4, 3, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=1, seed=2)
-    og, g, rho_t, s, K, D = _setup(p, torch.float64, 2)
+    og, g, rho_t, s, K, D = _setup(p, dtype, 2)
     f = np.zeros(p.ndof)                      # f = 0: u = 0 is exact, r = 0 exactly
-    u_t = torch.zeros(p.ndof, dtype=torch.float64, device=DEV)
+    u_t = torch.zeros(p.ndof, dtype=dtype, device=DEV)
     info = torch.zeros(8, dtype=torch.float64, device=DEV)
-    g.inner_solve(rho_t, dev(f), u_t, 5, method="krylov", omega=1.0, info=info)
+    g.inner_solve(rho_t, dev(f, dtype), u_t, 5, method="krylov", omega=1.0, info=info)
     assert torch.count_nonzero(u_t) == 0
     assert host(info)[0] == 0.0 and host(info)[4] == 0
