@@ -75,7 +75,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sizes", action="store_true",
                     help="skip the K(rho)u timings at 256x128x128 and 384x192x192")
-    ap.add_argument("--profile-only", choices=["apply", "outer", "cpfbto"], default=None,
+    ap.add_argument("--profile-only", choices=["apply", "outer", "cpfbto", "project"], default=None,
                     help="run only a short loop of one kind (for rocprofv3)")
     return ap.parse_args()
 
@@ -296,6 +296,54 @@ def apply_sizes(torch):
     return out
 
 
+def projection_timing(torch, reps=20):
+    """The two device projections onto {0 <= x <= 1, sum x <= vmax}
+    (fbto_project_volume: safeguarded Newton; fbto_project_volume_sorted:
+    Alg. 4 as a radix sort and scans) at 128x64x64 and 384x192x192, FP32
+    and FP64, from HIP events on the launch stream.  The input is a
+    gradient step from a U[0.2, 0.4] density (the multiplier is positive).
+    Streaming bytes of the sorted path per element, with b bytes per value:
+    keys 2b; per 8-bit pass histogram b + scatter 2b; prefix sums b + b + 8;
+    bracket b (its searches hit cache); clamp 2b."""
+    import numpy as np
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+    out = {}
+    dev = torch.device("cuda:0")
+    st = torch.cuda.current_stream()
+    for name, shape, vf in (("128x64x64", (128, 64, 64), 0.25), ("384x192x192", (384, 192, 192), 0.1)):
+        p = synth.cantilever(*shape, volfrac=vf, filter_radius=1.0, outer_iters=1, inner_steps=1)
+        g = Grid.from_problem(p)
+        rng = np.random.default_rng(5)
+        y64 = rng.uniform(0.2, 0.4, p.E) - 0.05 * rng.normal(0.0, 1.0, p.E)
+        for dtype, b in ((torch.float32, 4), (torch.float64, 8)):
+            y = torch.tensor(y64, dtype=dtype, device=dev)
+            x = torch.empty_like(y)
+            lam = torch.zeros(2, dtype=torch.float64, device=dev)
+            rec = {}
+            for i, method in enumerate(("newton", "sort")):
+                for _ in range(3):
+                    g.project_volume(y, x, 0.0, 1.0, p.vmax, lam=lam[i:i + 1], method=method)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+                for _ in range(reps):
+                    g.project_volume(y, x, 0.0, 1.0, p.vmax, lam=lam[i:i + 1], method=method)
+                e1.record(st)
+                torch.cuda.synchronize()
+                rec[f"{method}_us"] = e0.elapsed_time(e1) * 1e3 / reps
+            passes = 8 * b // 8
+            nbytes = p.E * (2 * b + passes * 3 * b + 2 * b + 8 + b + 2 * b)
+            rec["sort_bytes"] = nbytes
+            rec["sort_hbm_frac"] = nbytes / (rec["sort_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+            lv = lam.cpu().tolist()
+            rec["lambda_newton"], rec["lambda_sort"] = lv[0], lv[1]
+            out[f"{name}_{'fp32' if b == 4 else 'fp64'}"] = rec
+            del y, x
+        g.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(p, seconds):
     """The CPU FP64 oracle (as it stands) running outer iterations of the same
     workload on the host cores for about `seconds`."""
@@ -342,6 +390,8 @@ def main():
         if args.profile_only == "apply":
             for dtype in (torch.float32, torch.float64):
                 apply_timing(g, p, dtype, args.apply_reps, torch)
+        elif args.profile_only == "project":
+            print(json.dumps(projection_timing(torch)), flush=True)
         elif args.profile_only == "outer":
             outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, true_obj=False)
         else:
@@ -395,6 +445,7 @@ def main():
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
     sizes = None if args.no_sizes else apply_sizes(torch)
     osizes = None if args.no_sizes else outer_sizes(torch)
+    proj = None if args.no_sizes else projection_timing(torch)
     fixed4 = None if (args.no_sizes or args.no_fixed_err) else fixed_error_cfg4(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(p, args.cpu_seconds)
 
@@ -451,6 +502,7 @@ def main():
         "fixed_error": fixed,
         "fixed_error_cfg4": fixed4,
         "outer_sizes": osizes,
+        "projection": proj,
         "cpu_baseline": cpu,
         "kernel_hash": kernel_hash(),
     }

@@ -211,6 +211,28 @@ fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y
                                   void* x, double lo, double hi, double vmax,
                                   double* lambda, void* stream);
 
+/* The same projection computed the way Alg. 4 does it, in its GPU form
+ * (Sec. 4.3: a radix sort and parallel scans), as a cross-check of
+ * fbto_project_volume:
+ *   - y is sorted once (LSD radix sort, 8-bit digits: 4 passes in FP32, 8 in
+ *     FP64).  The nodes y_e - lo and y_e - hi of Eq. piecewiseLinearEQ are
+ *     this order shifted by a constant.
+ *   - FP64 prefix sums of the sorted values give the sum of
+ *     clamp(y - t, lo, hi) at any t in closed form (the running RHS of
+ *     Alg. 4).  It is evaluated at all 2E nodes in parallel.
+ *   - The nodes on either side of vmax bound one linear piece, and lambda
+ *     solves it.  lambda = 0 when clamp(y, lo, hi) is feasible.
+ * Arguments, aliasing, lambda and the errors are those of
+ * fbto_project_volume.  Where the root is not unique (a flat piece at
+ * vmax), x is the same for every root; lambda may differ.
+ * A non-finite y gives lambda = NaN and x = NaN.
+ * The first call on a grid allocates the workspace, about
+ * 24 bytes per element + 8 KiB per 2048 elements.  Errors: as
+ * fbto_project_volume; FBTO_ERR_ARG if E >= 2^31. */
+fbto_status_t fbto_project_volume_sorted(fbto_grid_t g, fbto_prec_t prec, const void* y,
+                                         void* x, double lo, double hi, double vmax,
+                                         double* lambda, void* stream);
+
 /* One outer iteration k (1-based) of the first-order bilevel method
  * (Alg. 1 with the Jacobi-PCG low-level step):
  *   rho = C(x); u <- inner_steps PCG steps on K(rho) u = f from u;

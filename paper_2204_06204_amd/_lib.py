@@ -41,6 +41,8 @@ _SIGS = {
     "fbto_filter": (C.c_int, [_VP, C.c_int, C.c_int32, _VP, _VP, _VP]),
     "fbto_project_volume": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_double, C.c_double,
                                       _VP, _VP]),
+    "fbto_project_volume_sorted": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_double, C.c_double,
+                                             _VP, _VP]),
     "fbto_outer_step": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                   C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_exact": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,

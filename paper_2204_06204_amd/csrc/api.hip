@@ -132,6 +132,14 @@ fbto_status_t ensure_vecs(fbto_grid_s* g) {
   return FBTO_OK;
 }
 
+fbto_status_t ensure_sort(fbto_grid_s* g) {
+  SortWs& W = g->sort;
+  if (W.base) return FBTO_OK;
+  HIP_TRY(hipMalloc(&W.base, sort_ws_layout(g->geo.E, nullptr)));
+  (void)sort_ws_layout(g->geo.E, &W);
+  return FBTO_OK;
+}
+
 void free_vecs(Vecs& V) {
   void* ps[] = {V.r[0], V.r[1], V.p[0], V.p[1], V.s[0], V.s[1], V.w[0], V.w[1], V.x1, V.q,
                 V.invD, V.rho, V.ge, V.gx, V.y, V.Hs};
@@ -569,7 +577,7 @@ fbto_status_t fbto_destroy_grid(fbto_grid_t g) {
   if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
   (void)hipDeviceSynchronize();
   void* ps[] = {g->mask, g->spring_dof, g->spring_k64, g->spring_k32, g->stencil_off,
-                g->stencil_w64, g->stencil_w32, g->sc, g->partials, g->sink};
+                g->stencil_w64, g->stencil_w32, g->sc, g->partials, g->sink, g->sort.base};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   free_vecs(g->v64);
@@ -764,6 +772,26 @@ fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y
     HIP_TRY(launch_project<double>(g, (const double*)y, (double*)x, lo, hi, vmax, 0, nullptr, lambda, st));
   else
     HIP_TRY(launch_project<float>(g, (const float*)y, (float*)x, lo, hi, vmax, 0, nullptr, lambda, st));
+  return ok();
+}
+
+fbto_status_t fbto_project_volume_sorted(fbto_grid_t g, fbto_prec_t prec, const void* y, void* x, double lo,
+                                         double hi, double vmax, double* lambda, void* stream) {
+  if (check_grid(g) || check_prec(prec)) return FBTO_ERR_ARG;
+  if (!y || !x) return fail(FBTO_ERR_ARG, "y and x must be non-NULL");
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo <= hi)) return fail(FBTO_ERR_ARG, "need finite lo <= hi");
+  if (!std::isfinite(vmax)) return fail(FBTO_ERR_ARG, "vmax must be finite");
+  if (g->geo.E > (int64_t)INT32_MAX) return fail(FBTO_ERR_ARG, "the sort ranks keys in 32 bits: E must be < 2^31");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g: the feasible set is empty", vmax,
+                lo * (double)g->geo.E);
+  fbto_status_t s;
+  if ((s = ensure_sort(g))) return s;
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == FBTO_F64)
+    HIP_TRY(launch_project_sorted<double>(g, (const double*)y, (double*)x, lo, hi, vmax, lambda, st));
+  else
+    HIP_TRY(launch_project_sorted<float>(g, (const float*)y, (float*)x, lo, hi, vmax, lambda, st));
   return ok();
 }
 

@@ -142,6 +142,22 @@ struct StencilPt {
 
 }  // namespace fbto
 
+namespace fbto {
+constexpr int kSortBracketBlocks = 2048;
+// Workspace of the sort-based projection (one allocation, carved by
+// sort_ws_layout; allocated on the first call).
+struct SortWs {
+  void* base = nullptr;
+  void* keys[2] = {nullptr, nullptr};  // [E] sort keys, 8 bytes per entry (FP32 keys use 4)
+  double* S = nullptr;                 // [E + 1] exclusive prefix sums of the sorted values
+  uint32_t* hist = nullptr;            // [256][tiles] digit counts per tile, then their offsets
+  uint32_t* tot = nullptr;             // [256] digit totals
+  double* part = nullptr;              // [tiles] tile sums of the prefix scan, then their offsets
+  double* brk = nullptr;               // [2][kSortBracketBlocks] per-block bracket of the root
+  double* lam = nullptr;               // the multiplier
+};
+}  // namespace fbto
+
 struct fbto_grid_s {
   fbto_grid_desc_t desc;
   fbto::Geo geo;
@@ -167,6 +183,7 @@ struct fbto_grid_s {
   int n_cu = 256;
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
   fbto::TileChoice tiles[2][2][6] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
+  fbto::SortWs sort;                     // sort-based projection
 };
 
 namespace fbto {
@@ -230,6 +247,13 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
                        int mean_project, double lo, double hi, hipStream_t st);
 template <typename T>
 hipError_t launch_hs(fbto_grid_s* g, T* Hs, hipStream_t st);
+// Sort-based projection (project_sort.hip).  sort_ws_layout returns the
+// workspace bytes for E elements and, when W->base is set, points W's arrays
+// into it.
+size_t sort_ws_layout(int64_t E, SortWs* W);
+template <typename T>
+hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, double hi, double vmax,
+                                 double* lam_out, hipStream_t st);
 template <typename T>
 hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi,
                           double vmax, int seeded, const T* x_old, double* lam_out,

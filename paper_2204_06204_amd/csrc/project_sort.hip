@@ -1,0 +1,394 @@
+// Projection onto X = {lo <= x <= hi, sum x <= vmax} by sorting (Sec. 4.2,
+// Alg. 4 and its GPU form in Sec. 4.3: one radix sort and parallel scans).
+//
+// The multiplier lambda solves sum_e clamp(y_e - lambda, lo, hi) = vmax
+// (Eq. piecewiseLinearEQ).  Its left-hand side phi(lambda) is piecewise
+// linear with nodes y_e - lo and y_e - hi.  Both families are the values of
+// y shifted by a constant, so one sort of y orders all 2E nodes.  With S
+// the exclusive prefix sums of the sorted values, phi at any lambda is
+//   lo * c_lo + hi * (E - c_hi) + S[c_hi] - S[c_lo] - lambda * (c_hi - c_lo),
+//   c_lo = #{y_e <= lambda + lo},  c_hi = #{y_e < lambda + hi},
+// which is the running RHS of Alg. 4 in closed form (the running SLOPE is
+// c_lo - c_hi).  Every node is evaluated in parallel.  The largest node
+// with phi >= vmax and the smallest with phi <= vmax bound the linear piece
+// that holds the root, which is then solved exactly.
+//
+// Kernels, in launch order:
+//   k_sort_keys      y -> order-preserving unsigned keys
+//   k_radix_hist     per 2048-key tile, counts of the current 8-bit digit
+//   k_radix_scan     per digit, exclusive scan of the tile counts
+//   k_radix_scatter  stable scatter of each tile (wave ballots rank the keys)
+//                    (the three above run 4 times for FP32, 8 for FP64)
+//   k_prefix_part    FP64 sum of each tile of sorted values
+//   k_prefix_top     exclusive scan of the tile sums (one block)
+//   k_prefix_down    S[i] for every i, S[E] = the total
+//   k_bracket        phi at both nodes of every element; per-block bracket
+//   k_lambda         one block: the bracket, phi(0), lambda
+//   k_clamp          x = clamp(y - lambda, lo, hi)
+#include "device.h"
+
+namespace fbto {
+namespace {
+
+constexpr int kSortBlock = 256;  // four waves; every kernel here assumes it
+constexpr int kSortItems = 8;
+constexpr int kSortTile = kSortBlock * kSortItems;
+constexpr int kRadix = 256;
+constexpr int kRadixBits = 8;
+constexpr int kBracketBlocks = kSortBracketBlocks;
+
+template <typename T> struct KeyOf;
+template <> struct KeyOf<float> { using type = uint32_t; };
+template <> struct KeyOf<double> { using type = uint64_t; };
+
+// IEEE values to unsigned keys whose unsigned order is the numeric order
+// (negative values: all bits flipped; others: the sign bit set).
+__device__ __forceinline__ uint32_t to_key(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ uint64_t to_key(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ __forceinline__ double from_key(uint32_t k) {
+  const uint32_t u = (k & 0x80000000u) ? (k ^ 0x80000000u) : ~k;
+  return (double)__uint_as_float(u);
+}
+__device__ __forceinline__ double from_key(uint64_t k) {
+  const uint64_t u = (k >> 63) ? (k ^ (1ull << 63)) : ~k;
+  return __longlong_as_double((long long)u);
+}
+
+// Inclusive scans over the 64 lanes of a wave (shift-up steps, fixed order).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ double wave_scan_incl(double v) {
+  const int lane = __lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const double t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over the block of kSortBlock threads; `total` receives the
+// block's sum.  Every thread must call it (it synchronises twice).
+template <typename V>
+__device__ __forceinline__ V block_scan_excl(V v, V* sh, V& total) {
+  const int w = threadIdx.x >> 6;
+  const V incl = wave_scan_incl(v);
+  if (__lane_id() == 63) sh[w] = incl;
+  __syncthreads();
+  V off = V(0), tot = V(0);
+#pragma unroll
+  for (int k = 0; k < kSortBlock / 64; ++k) {
+    if (k < w) off += sh[k];
+    tot += sh[k];
+  }
+  __syncthreads();
+  total = tot;
+  return off + incl - v;
+}
+
+template <typename T, typename K>
+__global__ void __launch_bounds__(kSortBlock) k_sort_keys(const T* y, K* keys, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock)
+    keys[i] = to_key(y[i]);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock)
+    k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist, int ntiles) {
+  __shared__ uint32_t h[kRadix];
+  const int tid = threadIdx.x;
+  h[tid] = 0u;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + k * kSortBlock + tid;
+    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
+}
+
+// One block per digit: the tile counts of the digit become the number of
+// keys with that digit in earlier tiles; tot[digit] the digit's total.
+__global__ void __launch_bounds__(kSortBlock) k_radix_scan(uint32_t* hist, int ntiles, uint32_t* tot) {
+  __shared__ uint32_t sh[kSortBlock / 64];
+  uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
+  uint32_t carry = 0u;
+  for (int c = 0; c < ntiles; c += kSortBlock) {
+    const int j = c + threadIdx.x;
+    const uint32_t v = j < ntiles ? row[j] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_scan_excl(v, sh, total);
+    if (j < ntiles) row[j] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) tot[blockIdx.x] = carry;
+}
+
+// Stable scatter of one tile by the current digit.  The tile is read in
+// kSortItems rounds of kSortBlock consecutive keys, so round order, wave
+// order and lane order are the key order.  In a round, the lanes of a wave
+// that hold the same digit are found with eight ballots (one per digit
+// bit); a key's rank is the digit's offset (earlier tiles, earlier rounds)
+// plus the same-digit keys of earlier waves and earlier lanes.
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock)
+    k_radix_scatter(const K* in, K* out, int64_t n, int shift, const uint32_t* hist, const uint32_t* tot,
+                    int ntiles) {
+  __shared__ uint32_t off[kRadix];
+  __shared__ uint32_t wcnt[kSortBlock / 64][kRadix];
+  __shared__ uint32_t sh[kSortBlock / 64];
+  const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
+  uint32_t total;
+  const uint32_t dstart = block_scan_excl(tot[tid], sh, total);
+  off[tid] = dstart + hist[(int64_t)tid * ntiles + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < kSortBlock / 64; ++q) wcnt[q][tid] = 0u;
+  __syncthreads();
+  const uint64_t earlier = (1ull << lane) - 1ull;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + (int64_t)k * kSortBlock + tid;
+    const bool valid = i < n;
+    const K key = valid ? in[i] : (K)0;
+    const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const uint64_t m = __ballot(bit);
+      same &= bit ? m : ~m;
+    }
+    const uint32_t before = (uint32_t)__popcll(same & earlier);
+    if (valid && before == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = off[d] + before;
+      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      if ((int64_t)pos < n) out[pos] = key;  // always true when the counts are consistent
+    }
+    __syncthreads();
+    uint32_t adv = 0u;
+#pragma unroll
+    for (int q = 0; q < kSortBlock / 64; ++q) {
+      adv += wcnt[q][tid];
+      wcnt[q][tid] = 0u;
+    }
+    off[tid] += adv;
+    __syncthreads();
+  }
+}
+
+// The kSortItems consecutive sorted values of a thread and their sum.
+template <typename K>
+__device__ __forceinline__ double load_run(const K* sk, int64_t n, int64_t first, double (&v)[kSortItems]) {
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    v[j] = (first + j < n) ? from_key(sk[first + j]) : 0.0;
+    s += v[j];
+  }
+  return s;
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock) k_prefix_part(const K* sk, int64_t n, double* part) {
+  __shared__ double sh[kSortBlock / 64];
+  double v[kSortItems];
+  const double s = load_run(sk, n, (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems, v);
+  double total;
+  (void)block_scan_excl(s, sh, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(kSortBlock) k_prefix_top(double* part, int nb) {
+  __shared__ double sh[kSortBlock / 64];
+  double carry = 0.0;
+  for (int c = 0; c < nb; c += kSortBlock) {
+    const int j = c + threadIdx.x;
+    const double v = j < nb ? part[j] : 0.0;
+    double total;
+    const double ex = block_scan_excl(v, sh, total);
+    if (j < nb) part[j] = carry + ex;
+    carry += total;
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock) k_prefix_down(const K* sk, int64_t n, const double* part, double* S) {
+  __shared__ double sh[kSortBlock / 64];
+  double v[kSortItems];
+  const int64_t first = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
+  const double s = load_run(sk, n, first, v);
+  double total;
+  double run = part[blockIdx.x] + block_scan_excl(s, sh, total);
+#pragma unroll
+  for (int j = 0; j < kSortItems; ++j) {
+    if (first + j < n) {
+      S[first + j] = run;
+      run += v[j];
+      if (first + j == n - 1) S[n] = run;
+    }
+  }
+}
+
+// phi(t) = sum_e clamp(y_e - t, lo, hi) from the sorted values and S.
+template <typename K>
+__device__ double phi_at(const K* sk, const double* S, int64_t n, double t, double lo, double hi) {
+  const double a = t + lo, b = t + hi;
+  int64_t l = 0, r = n;                // first index with y > a
+  while (l < r) {
+    const int64_t m = (l + r) >> 1;
+    if (from_key(sk[m]) <= a) l = m + 1;
+    else r = m;
+  }
+  const int64_t c_lo = l;
+  r = n;                               // first index >= c_lo with y >= b
+  while (l < r) {
+    const int64_t m = (l + r) >> 1;
+    if (from_key(sk[m]) < b) l = m + 1;
+    else r = m;
+  }
+  const int64_t c_hi = l;
+  return lo * (double)c_lo + hi * (double)(n - c_hi) + (S[c_hi] - S[c_lo]) - t * (double)(c_hi - c_lo);
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock)
+    k_bracket(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax, double* brk, int nb) {
+  double v[2] = {-INFINITY, -INFINITY};  // max node with phi >= vmax; -(min node with phi <= vmax)
+  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock) {
+    const double yi = from_key(sk[i]);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const double t = s == 0 ? yi - hi : yi - lo;
+      const double f = phi_at(sk, S, n, t, lo, hi);
+      if (f >= vmax) v[0] = fmax(v[0], t);
+      if (f <= vmax) v[1] = fmax(v[1], -t);
+    }
+  }
+  block_reduce<2, 0x3u>(v);
+  if (threadIdx.x == 0) {
+    brk[blockIdx.x] = v[0];
+    brk[nb + blockIdx.x] = v[1];
+  }
+}
+
+template <typename K>
+__global__ void __launch_bounds__(kSortBlock)
+    k_lambda(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax, const double* brk, int nb,
+             double* lam_ws, double* lam_out) {
+  double v[2] = {-INFINITY, -INFINITY};
+  for (int b = threadIdx.x; b < nb; b += kSortBlock) {
+    v[0] = fmax(v[0], brk[b]);
+    v[1] = fmax(v[1], brk[nb + b]);
+  }
+  block_reduce<2, 0x3u>(v);
+  if (threadIdx.x != 0) return;
+  double lam;
+  if (!isfinite(S[n])) {
+    lam = NAN;                                   // a non-finite y
+  } else if (phi_at(sk, S, n, 0.0, lo, hi) <= vmax) {
+    lam = 0.0;                                   // the clamped point is feasible
+  } else {
+    const double tl = v[0], tu = -v[1];
+    if (!(tl > -INFINITY && tu < INFINITY)) {
+      lam = NAN;                                 // no bracket: vmax < lo * E (checked on the host)
+    } else {
+      const double fl = phi_at(sk, S, n, tl, lo, hi), fu = phi_at(sk, S, n, tu, lo, hi);
+      lam = fl > fu ? tl + (fl - vmax) * (tu - tl) / (fl - fu) : tl;
+      lam = fmin(fmax(lam, tl), tu);
+    }
+  }
+  *lam_ws = lam;
+  if (lam_out) *lam_out = lam;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kSortBlock)
+    k_clamp(const T* y, T* x, int64_t n, double lo, double hi, const double* lam_ws) {
+  const double lam = *lam_ws;
+  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock)
+    x[i] = isnan(lam) ? (T)NAN : (T)fmin(fmax((double)y[i] - lam, lo), hi);
+}
+
+}  // namespace
+
+size_t sort_ws_layout(int64_t E, SortWs* W) {
+  const int64_t ntiles = (E + kSortTile - 1) / kSortTile;
+  const size_t sz[7] = {(size_t)E * 8, (size_t)E * 8, (size_t)(E + 1) * 8, (size_t)kRadix * ntiles * 4,
+                        (size_t)kRadix * 4, (size_t)ntiles * 8, (size_t)2 * kBracketBlocks * 8 + 8};
+  size_t off[7], tot = 0;
+  for (int i = 0; i < 7; ++i) {
+    off[i] = tot;
+    tot += (sz[i] + 255) & ~(size_t)255;
+  }
+  if (W && W->base) {
+    char* p = (char*)W->base;
+    W->keys[0] = p + off[0];
+    W->keys[1] = p + off[1];
+    W->S = (double*)(p + off[2]);
+    W->hist = (uint32_t*)(p + off[3]);
+    W->tot = (uint32_t*)(p + off[4]);
+    W->part = (double*)(p + off[5]);
+    W->brk = (double*)(p + off[6]);
+    W->lam = W->brk + 2 * kBracketBlocks;
+  }
+  return tot;
+}
+
+template <typename T>
+hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, double hi, double vmax,
+                                 double* lam_out, hipStream_t st) {
+  using K = typename KeyOf<T>::type;
+  const SortWs& W = g->sort;
+  const int64_t n = g->geo.E;
+  const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
+  K* a = (K*)W.keys[0];
+  K* b = (K*)W.keys[1];
+  const int nv = vec_blocks(n);
+  hipLaunchKernelGGL((k_sort_keys<T, K>), dim3(nv), dim3(kSortBlock), 0, st, y, a, n);
+  for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += kRadixBits) {
+    hipLaunchKernelGGL((k_radix_hist<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n, shift, W.hist,
+                       ntiles);
+    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kSortBlock), 0, st, W.hist, ntiles, W.tot);
+    hipLaunchKernelGGL((k_radix_scatter<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, b, n, shift,
+                       (const uint32_t*)W.hist, (const uint32_t*)W.tot, ntiles);
+    K* t = a;
+    a = b;
+    b = t;
+  }
+  hipLaunchKernelGGL((k_prefix_part<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n, W.part);
+  hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kSortBlock), 0, st, W.part, ntiles);
+  hipLaunchKernelGGL((k_prefix_down<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n,
+                     (const double*)W.part, W.S);
+  const int64_t nbr64 = (n + kSortBlock - 1) / kSortBlock;
+  const int nbr = (int)(nbr64 < kBracketBlocks ? nbr64 : kBracketBlocks);
+  hipLaunchKernelGGL((k_bracket<K>), dim3(nbr), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n, lo,
+                     hi, vmax, W.brk, nbr);
+  hipLaunchKernelGGL((k_lambda<K>), dim3(1), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n, lo, hi,
+                     vmax, (const double*)W.brk, nbr, W.lam, lam_out);
+  hipLaunchKernelGGL((k_clamp<T>), dim3(nv), dim3(kSortBlock), 0, st, y, x, n, lo, hi, (const double*)W.lam);
+  return hipGetLastError();
+}
+
+template hipError_t launch_project_sorted<float>(fbto_grid_s*, const float*, float*, double, double, double,
+                                                 double*, hipStream_t);
+template hipError_t launch_project_sorted<double>(fbto_grid_s*, const double*, double*, double, double, double,
+                                                  double*, hipStream_t);
+
+}  // namespace fbto

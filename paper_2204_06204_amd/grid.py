@@ -164,13 +164,21 @@ class Grid:
         return out
 
     def project_volume(self, y, x=None, lo: float = 0.0, hi: float = 1.0, vmax: float = None,
-                       lam: Optional[torch.Tensor] = None, stream=None):
+                       lam: Optional[torch.Tensor] = None, stream=None, method: str = "newton"):
+        """method "newton": fbto_project_volume (safeguarded Newton on the
+        multiplier); "sort": fbto_project_volume_sorted (Alg. 4 by radix sort
+        and scans)."""
         if x is None:
             x = torch.empty_like(y)
-        check(self.lib.fbto_project_volume(self.handle, _prec(y), _ptr(y, None, self.E, "y"),
-                                           _ptr(x, y.dtype, self.E, "x"), float(lo), float(hi),
-                                           float(vmax), _ptr(lam, torch.float64, None, "lambda"),
-                                           _stream(stream)), self.lib)
+        if method == "newton":
+            fn = self.lib.fbto_project_volume
+        elif method == "sort":
+            fn = self.lib.fbto_project_volume_sorted
+        else:
+            raise ValueError(f"unknown method {method!r}")
+        check(fn(self.handle, _prec(y), _ptr(y, None, self.E, "y"), _ptr(x, y.dtype, self.E, "x"),
+                 float(lo), float(hi), float(vmax), _ptr(lam, torch.float64, None, "lambda"),
+                 _stream(stream)), self.lib)
         return x
 
     def outer_step(self, x, u, f, k: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
