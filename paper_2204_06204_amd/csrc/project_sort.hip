@@ -9,9 +9,11 @@
 //   lo * c_lo + hi * (E - c_hi) + S[c_hi] - S[c_lo] - lambda * (c_hi - c_lo),
 //   c_lo = #{y_e <= lambda + lo},  c_hi = #{y_e < lambda + hi},
 // which is the running RHS of Alg. 4 in closed form (the running SLOPE is
-// c_lo - c_hi).  Every node is evaluated in parallel.  The largest node
-// with phi >= vmax and the smallest with phi <= vmax bound the linear piece
-// that holds the root, which is then solved exactly.
+// c_lo - c_hi).  The largest node with phi >= vmax and the smallest with
+// phi <= vmax bound the linear piece that holds the root, which is then
+// solved exactly.  phi is monotone along each family, so a coarse pass over
+// every 256th node finds the windows that hold these two nodes, and a fine
+// pass evaluates the nodes of those windows.
 //
 // Kernels, in launch order:
 //   k_sort_keys      y -> order-preserving unsigned keys
@@ -22,8 +24,10 @@
 //   k_prefix_part    FP64 sum of each tile of sorted values
 //   k_prefix_top     exclusive scan of the tile sums (one block)
 //   k_prefix_down    S[i] for every i, S[E] = the total
-//   k_bracket        phi at both nodes of every element; per-block bracket
-//   k_lambda         one block: the bracket, phi(0), lambda
+//   k_bracket_coarse phi at every 256th node of each family, and phi(0)
+//   k_bracket_fine   phi at every node of the four windows that hold the
+//                    crossing of vmax
+//   k_lambda         one thread: lambda
 //   k_clamp          x = clamp(y - lambda, lo, hi)
 #include "device.h"
 
@@ -36,6 +40,9 @@ constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kRadixBits = 8;
 constexpr int kBracketBlocks = kSortBracketBlocks;
+constexpr int kCoarseStride = 256;  // nodes between the coarse samples of a family
+constexpr int kFineBlock = 320;     // threads of a fine window: kCoarseStride + 1 nodes
+static_assert(kFineBlock >= kCoarseStride + 1 && kFineBlock % 64 == 0, "fine window");
 
 template <typename T> struct KeyOf;
 template <> struct KeyOf<float> { using type = uint32_t; };
@@ -139,33 +146,42 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scan(uint32_t* hist, int n
   if (threadIdx.x == 0) tot[blockIdx.x] = carry;
 }
 
-// Stable scatter of one tile by the current digit.  The tile is read in
-// kSortItems rounds of kSortBlock consecutive keys, so round order, wave
-// order and lane order are the key order.  In a round, the lanes of a wave
-// that hold the same digit are found with eight ballots (one per digit
-// bit); a key's rank is the digit's offset (earlier tiles, earlier rounds)
-// plus the same-digit keys of earlier waves and earlier lanes.
+// Stable scatter of one tile by the current digit.
+//  1. Rank: the tile is read in kSortItems rounds of kSortBlock consecutive
+//     keys, so round, wave and lane order are the key order.  In a round the
+//     lanes of a wave that hold the same digit are found with eight ballots
+//     (one per digit bit).  A key's rank within its digit in the tile is the
+//     digit's count in earlier rounds plus the same-digit keys of earlier
+//     waves and lanes.
+//  2. The keys are placed in LDS in digit order (the tile's digit starts are
+//     a scan of its digit counts).
+//  3. LDS entry j goes to the digit's global start for this tile plus its
+//     offset in the digit's run, so consecutive threads write consecutive
+//     addresses within each run.
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
     k_radix_scatter(const K* in, K* out, int64_t n, int shift, const uint32_t* hist, const uint32_t* tot,
                     int ntiles) {
-  __shared__ uint32_t off[kRadix];
+  __shared__ K stage[kSortTile];
+  __shared__ uint32_t cnt[kRadix];                 // keys of each digit ranked so far
   __shared__ uint32_t wcnt[kSortBlock / 64][kRadix];
+  __shared__ uint32_t tstart[kRadix];              // tile-local start of each digit
+  __shared__ uint32_t gbase[kRadix];               // global position minus tile-local start (mod 2^32)
   __shared__ uint32_t sh[kSortBlock / 64];
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
-  uint32_t total;
-  const uint32_t dstart = block_scan_excl(tot[tid], sh, total);
-  off[tid] = dstart + hist[(int64_t)tid * ntiles + blockIdx.x];
+  cnt[tid] = 0u;
 #pragma unroll
   for (int q = 0; q < kSortBlock / 64; ++q) wcnt[q][tid] = 0u;
   __syncthreads();
   const uint64_t earlier = (1ull << lane) - 1ull;
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  K key[kSortItems];
+  uint32_t rank[kSortItems];
+#pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const int64_t i = base + (int64_t)k * kSortBlock + tid;
-    const bool valid = i < n;
-    const K key = valid ? in[i] : (K)0;
-    const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+    const bool valid = base + (int64_t)k * kSortBlock + tid < n;
+    key[k] = valid ? in[base + (int64_t)k * kSortBlock + tid] : (K)0;
+    const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
     uint64_t same = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -176,11 +192,9 @@ __global__ void __launch_bounds__(kSortBlock)
     const uint32_t before = (uint32_t)__popcll(same & earlier);
     if (valid && before == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
     __syncthreads();
-    if (valid) {
-      uint32_t pos = off[d] + before;
-      for (int q = 0; q < w; ++q) pos += wcnt[q][d];
-      if ((int64_t)pos < n) out[pos] = key;  // always true when the counts are consistent
-    }
+    uint32_t r = cnt[d] + before;
+    for (int q = 0; q < w; ++q) r += wcnt[q][d];
+    rank[k] = r;
     __syncthreads();
     uint32_t adv = 0u;
 #pragma unroll
@@ -188,31 +202,46 @@ __global__ void __launch_bounds__(kSortBlock)
       adv += wcnt[q][tid];
       wcnt[q][tid] = 0u;
     }
-    off[tid] += adv;
+    cnt[tid] += adv;
     __syncthreads();
   }
-}
-
-// The kSortItems consecutive sorted values of a thread and their sum.
-template <typename K>
-__device__ __forceinline__ double load_run(const K* sk, int64_t n, int64_t first, double (&v)[kSortItems]) {
-  double s = 0.0;
+  uint32_t total;
+  const uint32_t ts = block_scan_excl(cnt[tid], sh, total);
+  const uint32_t ds = block_scan_excl(tot[tid], sh, total);
+  tstart[tid] = ts;
+  gbase[tid] = ds + hist[(int64_t)tid * ntiles + blockIdx.x] - ts;
+  __syncthreads();
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    v[j] = (first + j < n) ? from_key(sk[first + j]) : 0.0;
-    s += v[j];
+  for (int k = 0; k < kSortItems; ++k) {
+    if (base + (int64_t)k * kSortBlock + tid < n) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
+      const uint32_t j = tstart[d] + rank[k];
+      if (j < (uint32_t)kSortTile) stage[j] = key[k];  // always true when the counts are consistent
+    }
   }
-  return s;
+  __syncthreads();
+  const int64_t left = n - base;
+  const int tile_n = left < kSortTile ? (int)left : kSortTile;
+  for (int j = tid; j < tile_n; j += kSortBlock) {
+    const K kk = stage[j];
+    const uint32_t pos = gbase[(uint32_t)(kk >> shift) & (kRadix - 1)] + (uint32_t)j;
+    if ((int64_t)pos < n) out[pos] = kk;  // always true when the counts are consistent
+  }
 }
 
+// FP64 prefix sums of the sorted values, tile by tile in the striped order
+// of the sort (round k of a tile: kSortBlock consecutive values).
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_prefix_part(const K* sk, int64_t n, double* part) {
-  __shared__ double sh[kSortBlock / 64];
-  double v[kSortItems];
-  const double s = load_run(sk, n, (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems, v);
-  double total;
-  (void)block_scan_excl(s, sh, total);
-  if (threadIdx.x == 0) part[blockIdx.x] = total;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  double v[1] = {0.0};
+#pragma unroll
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + (int64_t)k * kSortBlock + threadIdx.x;
+    v[0] += i < n ? from_key(sk[i]) : 0.0;
+  }
+  block_reduce<1, 0u>(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
 __global__ void __launch_bounds__(kSortBlock) k_prefix_top(double* part, int nb) {
@@ -231,18 +260,17 @@ __global__ void __launch_bounds__(kSortBlock) k_prefix_top(double* part, int nb)
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock) k_prefix_down(const K* sk, int64_t n, const double* part, double* S) {
   __shared__ double sh[kSortBlock / 64];
-  double v[kSortItems];
-  const int64_t first = (int64_t)blockIdx.x * kSortTile + (int64_t)threadIdx.x * kSortItems;
-  const double s = load_run(sk, n, first, v);
-  double total;
-  double run = part[blockIdx.x] + block_scan_excl(s, sh, total);
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  double carry = part[blockIdx.x];
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    if (first + j < n) {
-      S[first + j] = run;
-      run += v[j];
-      if (first + j == n - 1) S[n] = run;
-    }
+  for (int k = 0; k < kSortItems; ++k) {
+    const int64_t i = base + (int64_t)k * kSortBlock + threadIdx.x;
+    const double v = i < n ? from_key(sk[i]) : 0.0;
+    double total;
+    const double ex = block_scan_excl(v, sh, total);
+    if (i < n) S[i] = carry + ex;
+    if (i == n - 1) S[n] = carry + ex + v;
+    carry += total;
   }
 }
 
@@ -267,52 +295,117 @@ __device__ double phi_at(const K* sk, const double* S, int64_t n, double t, doub
   return lo * (double)c_lo + hi * (double)(n - c_hi) + (S[c_hi] - S[c_lo]) - t * (double)(c_hi - c_lo);
 }
 
+// Node i of family f: y_i - hi (f = 0, where element i leaves hi) or
+// y_i - lo (f = 1, where it reaches lo).  Along a family phi does not
+// increase with i.
+template <typename K>
+__device__ __forceinline__ double node_t(const K* sk, int64_t i, int f, double lo, double hi) {
+  const double yi = from_key(sk[i]);
+  return f == 0 ? yi - hi : yi - lo;
+}
+
+// Coarse pass: phi at the samples i = j * kCoarseStride (j < ns) of both
+// families.  Per block, the number of samples with phi > vmax and with
+// phi >= vmax, family by family: since phi is monotone along a family,
+// these counts locate the crossing to within one sample interval.  The
+// thread after the last sample stores phi(0).
 template <typename K>
 __global__ void __launch_bounds__(kSortBlock)
-    k_bracket(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax, double* brk, int nb) {
-  double v[2] = {-INFINITY, -INFINITY};  // max node with phi >= vmax; -(min node with phi <= vmax)
-  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock) {
-    const double yi = from_key(sk[i]);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      const double t = s == 0 ? yi - hi : yi - lo;
-      const double f = phi_at(sk, S, n, t, lo, hi);
-      if (f >= vmax) v[0] = fmax(v[0], t);
-      if (f <= vmax) v[1] = fmax(v[1], -t);
+    k_bracket_coarse(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax, int64_t ns,
+                     double* part, int nb, double* phi0) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // family 0: > and >=, family 1: > and >=
+  for (int64_t g = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; g <= 2 * ns;
+       g += (int64_t)gridDim.x * kSortBlock) {
+    if (g == 2 * ns) {
+      *phi0 = phi_at(sk, S, n, 0.0, lo, hi);
+      continue;
+    }
+    const int f = (int)(g & 1);
+    const double ph = phi_at(sk, S, n, node_t(sk, (g >> 1) * kCoarseStride, f, lo, hi), lo, hi);
+    const double gt = ph > vmax ? 1.0 : 0.0, ge = ph >= vmax ? 1.0 : 0.0;
+    if (f == 0) {
+      v[0] += gt;
+      v[1] += ge;
+    } else {
+      v[2] += gt;
+      v[3] += ge;
     }
   }
-  block_reduce<2, 0x3u>(v);
+  block_reduce<4, 0u>(v);
   if (threadIdx.x == 0) {
-    brk[blockIdx.x] = v[0];
-    brk[nb + blockIdx.x] = v[1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) part[(int64_t)k * nb + blockIdx.x] = v[k];
   }
 }
 
+// Fine pass: four blocks, one window of kCoarseStride + 1 nodes each.
+// Block 2 q + f covers family f around its first sample with phi <= vmax
+// (q = 0: the smallest node with phi <= vmax lies there) or its last
+// sample with phi >= vmax (q = 1: the largest node with phi >= vmax).
+// win[4 b ..]: that block's largest node with phi >= vmax and its phi, its
+// smallest node with phi <= vmax and its phi (-inf / +inf when none).
 template <typename K>
-__global__ void __launch_bounds__(kSortBlock)
-    k_lambda(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax, const double* brk, int nb,
-             double* lam_ws, double* lam_out) {
-  double v[2] = {-INFINITY, -INFINITY};
-  for (int b = threadIdx.x; b < nb; b += kSortBlock) {
-    v[0] = fmax(v[0], brk[b]);
-    v[1] = fmax(v[1], brk[nb + b]);
+__global__ void __launch_bounds__(kFineBlock)
+    k_bracket_fine(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax,
+                   const double* part, int nb, double* win) {
+  double c[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += kFineBlock) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] += part[(int64_t)k * nb + b];
   }
+  block_reduce<4, 0u>(c);
+  const int f = blockIdx.x & 1, q = blockIdx.x >> 1;
+  const int64_t cnt = (int64_t)(q == 0 ? (f == 0 ? c[0] : c[2]) : (f == 0 ? c[1] : c[3]));
+  int64_t i0 = (cnt - 1) * kCoarseStride, i1 = cnt * kCoarseStride;
+  if (i0 < 0) i0 = 0;
+  if (i1 > n - 1) i1 = n - 1;
+  const int64_t i = i0 + threadIdx.x;
+  const bool have = i <= i1;
+  double t = 0.0, ph = 0.0;
+  if (have) {
+    t = node_t(sk, i, f, lo, hi);
+    ph = phi_at(sk, S, n, t, lo, hi);
+  }
+  double v[2] = {have && ph >= vmax ? t : -INFINITY, have && ph <= vmax ? -t : -INFINITY};
   block_reduce<2, 0x3u>(v);
-  if (threadIdx.x != 0) return;
-  double lam;
-  if (!isfinite(S[n])) {
-    lam = NAN;                                   // a non-finite y
-  } else if (phi_at(sk, S, n, 0.0, lo, hi) <= vmax) {
-    lam = 0.0;                                   // the clamped point is feasible
-  } else {
-    const double tl = v[0], tu = -v[1];
-    if (!(tl > -INFINITY && tu < INFINITY)) {
-      lam = NAN;                                 // no bracket: vmax < lo * E (checked on the host)
-    } else {
-      const double fl = phi_at(sk, S, n, tl, lo, hi), fu = phi_at(sk, S, n, tu, lo, hi);
-      lam = fl > fu ? tl + (fl - vmax) * (tu - tl) / (fl - fu) : tl;
-      lam = fmin(fmax(lam, tl), tu);
+  // phi at the two extremes (equal nodes give equal phi)
+  double p[2] = {have && ph >= vmax && t == v[0] ? ph : -INFINITY, have && ph <= vmax && -t == v[1] ? ph : -INFINITY};
+  block_reduce<2, 0x3u>(p);
+  if (threadIdx.x == 0) {
+    win[4 * blockIdx.x + 0] = v[0];
+    win[4 * blockIdx.x + 1] = p[0];
+    win[4 * blockIdx.x + 2] = -v[1];
+    win[4 * blockIdx.x + 3] = p[1];
+  }
+}
+
+// lambda from the four windows: 0 when phi(0) <= vmax, else the root on the
+// linear piece between the largest node with phi >= vmax and the smallest
+// with phi <= vmax.
+__global__ void k_lambda(const double* win, const double* phi0, const double* total, double vmax, double* lam_ws,
+                         double* lam_out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double tl = -INFINITY, fl = 0.0, tu = INFINITY, fu = 0.0;
+  for (int b = 0; b < 4; ++b) {
+    if (win[4 * b] > tl) {
+      tl = win[4 * b];
+      fl = win[4 * b + 1];
     }
+    if (win[4 * b + 2] < tu) {
+      tu = win[4 * b + 2];
+      fu = win[4 * b + 3];
+    }
+  }
+  double lam;
+  if (!isfinite(*total)) {
+    lam = NAN;                                   // a non-finite y
+  } else if (*phi0 <= vmax) {
+    lam = 0.0;                                   // the clamped point is feasible
+  } else if (!(tl > -INFINITY && tu < INFINITY)) {
+    lam = NAN;                                   // no bracket: vmax < lo * E (checked on the host)
+  } else {
+    lam = fl > fu ? tl + (fl - vmax) * (tu - tl) / (fl - fu) : tl;
+    lam = fmin(fmax(lam, tl), tu);
   }
   *lam_ws = lam;
   if (lam_out) *lam_out = lam;
@@ -331,7 +424,7 @@ __global__ void __launch_bounds__(kSortBlock)
 size_t sort_ws_layout(int64_t E, SortWs* W) {
   const int64_t ntiles = (E + kSortTile - 1) / kSortTile;
   const size_t sz[7] = {(size_t)E * 8, (size_t)E * 8, (size_t)(E + 1) * 8, (size_t)kRadix * ntiles * 4,
-                        (size_t)kRadix * 4, (size_t)ntiles * 8, (size_t)2 * kBracketBlocks * 8 + 8};
+                        (size_t)kRadix * 4, (size_t)ntiles * 8, (size_t)(4 * kBracketBlocks + 16 + 2) * 8};
   size_t off[7], tot = 0;
   for (int i = 0; i < 7; ++i) {
     off[i] = tot;
@@ -345,8 +438,8 @@ size_t sort_ws_layout(int64_t E, SortWs* W) {
     W->hist = (uint32_t*)(p + off[3]);
     W->tot = (uint32_t*)(p + off[4]);
     W->part = (double*)(p + off[5]);
-    W->brk = (double*)(p + off[6]);
-    W->lam = W->brk + 2 * kBracketBlocks;
+    W->brk = (double*)(p + off[6]);          // [4][kBracketBlocks] coarse counts, then [4][4] windows
+    W->lam = W->brk + 4 * kBracketBlocks + 16;
   }
   return tot;
 }
@@ -376,12 +469,17 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
   hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kSortBlock), 0, st, W.part, ntiles);
   hipLaunchKernelGGL((k_prefix_down<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n,
                      (const double*)W.part, W.S);
-  const int64_t nbr64 = (n + kSortBlock - 1) / kSortBlock;
-  const int nbr = (int)(nbr64 < kBracketBlocks ? nbr64 : kBracketBlocks);
-  hipLaunchKernelGGL((k_bracket<K>), dim3(nbr), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n, lo,
-                     hi, vmax, W.brk, nbr);
-  hipLaunchKernelGGL((k_lambda<K>), dim3(1), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n, lo, hi,
-                     vmax, (const double*)W.brk, nbr, W.lam, lam_out);
+  const int64_t ns = (n + kCoarseStride - 1) / kCoarseStride;  // samples per family
+  const int64_t nbc64 = (2 * ns + 1 + kSortBlock - 1) / kSortBlock;
+  const int nbc = (int)(nbc64 < kBracketBlocks ? nbc64 : kBracketBlocks);
+  double* win = W.brk + 4 * kBracketBlocks;
+  double* phi0 = W.lam + 1;
+  hipLaunchKernelGGL((k_bracket_coarse<K>), dim3(nbc), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n,
+                     lo, hi, vmax, ns, W.brk, nbc, phi0);
+  hipLaunchKernelGGL((k_bracket_fine<K>), dim3(4), dim3(kFineBlock), 0, st, (const K*)a, (const double*)W.S, n, lo,
+                     hi, vmax, (const double*)W.brk, nbc, win);
+  hipLaunchKernelGGL(k_lambda, dim3(1), dim3(64), 0, st, (const double*)win, (const double*)phi0,
+                     (const double*)(W.S + n), vmax, W.lam, lam_out);
   hipLaunchKernelGGL((k_clamp<T>), dim3(nv), dim3(kSortBlock), 0, st, y, x, n, lo, hi, (const double*)W.lam);
   return hipGetLastError();
 }

@@ -19,11 +19,14 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ("paper_2204_06204_amd/csrc/kernels.hip", "paper_2204_06204_amd/csrc/device.h")
+PROJECT_SORT_SOURCES = ("paper_2204_06204_amd/csrc/project_sort.hip", "paper_2204_06204_amd/csrc/device.h")
 
 
-def kernel_hash() -> str:
+def kernel_hash(sources=KERNEL_SOURCES) -> str:
+    """Short hash of the sources that define the profiled kernels (the
+    apply and outer-iteration kernels by default)."""
     h = hashlib.sha256()
-    for s in KERNEL_SOURCES:
+    for s in sources:
         with open(os.path.join(ROOT, s), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

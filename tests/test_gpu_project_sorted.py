@@ -37,6 +37,16 @@ def _phi(y, lam, lo, hi):
     return np.clip(y - lam, lo, hi).sum()
 
 
+def _sum_bound(y, xr, lo, hi):
+    """Bound on the multiplier's FP64 error from the sums (both sides form
+    the volume sum as running or prefix sums of the y values, each with an
+    error of a small multiple of eps * sum |y|).  Divided by the slope at
+    the root (the elements strictly inside the box, at least 1 on a piece
+    next to it), that is the error in lambda and so in x."""
+    n_act = int(((xr > lo) & (xr < hi)).sum())
+    return 16 * EPS[torch.float64] * float(np.abs(y).sum()) / max(1, n_act)
+
+
 # E = 765 (one ragged tile), 6 (a partial wave), 8000 (three tiles and a
 # ragged fourth), 524288 (256 whole tiles), 1 (a single element)
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
@@ -50,19 +60,27 @@ def test_sorted_projection_against_alg4(dtype, shape, kind, seed):
     yd = host(y_t)
     lam = torch.zeros(1, dtype=torch.float64, device=DEV)
     for lo in (0.0, 0.1):
-        for vmax in (p.vmax, lo * p.E + 0.37 * p.E * (1.0 - lo)):
+        s0 = float(np.clip(yd, lo, 1.0).sum())
+        # the workload's bound, a middle one, and crossings near either end
+        # of the node range (just above lo * E; just below sum clamp(y))
+        for vmax in (p.vmax, lo * p.E + 0.37 * p.E * (1.0 - lo), lo * p.E + 1e-3 * p.E * (1.0 - lo),
+                     s0 - 1e-6 * (s0 - lo * p.E)):
             if vmax < lo * p.E:
                 continue
             x = host(g.project_volume(y_t, lo=lo, hi=1.0, vmax=vmax, lam=lam, method="sort"))
             xr, lr = oracle.project_alg4(yd, lo, 1.0, vmax, return_lambda=True)
-            xtol = 1e-12 if dtype == torch.float64 else 2 * EPS[torch.float32]
+            sb = _sum_bound(yd, xr, lo, 1.0)
+            xtol = (1e-12 if dtype == torch.float64 else 2 * EPS[torch.float32]) + sb
             assert np.abs(x - xr).max() <= xtol, (lo, vmax, np.abs(x - xr).max())
             lg = float(lam[0])
-            if kind == "ties":
-                # the root may lie on a flat piece; any root gives the same x
-                assert abs(_phi(yd, lg, lo, 1.0) - _phi(yd, lr, lo, 1.0)) <= 1e-9 * max(1.0, vmax)
+            if lr == 0.0:
+                assert lg == 0.0, lg            # clamp(y) is feasible
+            elif kind in ("ties", "signs"):
+                # gaps wider than hi - lo: the root may lie on a flat piece,
+                # where every root gives the same x
+                assert abs(_phi(yd, lg, lo, 1.0) - vmax) <= 1e-9 * max(1.0, vmax) + p.E * sb
             else:
-                assert abs(lg - lr) <= 1e-10 * max(1.0, abs(lr)), (lg, lr)
+                assert abs(lg - lr) <= 1e-10 * max(1.0, abs(lr)) + sb, (lg, lr)
             if lr > 0:
                 assert abs(x.sum() - vmax) <= 1e-9 * vmax + p.E * xtol
 
