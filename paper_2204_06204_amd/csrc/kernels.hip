@@ -113,6 +113,15 @@ constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
 constexpr int kSinkStride = 16;  // sink entries per thread
 constexpr double kTinyNorm = 1e-30;  // Krylov step: a norm below this is zero (FP32 reciprocals stay finite)
+
+// Bits 3 R + 1 for R < nr: the |r|_inf entries (max-reduced) of the
+// per-RHS triples (sum of squares, |r|_inf, another sum) that the residual
+// and finishing reductions lay out.
+constexpr unsigned rinf_mask(int nr) {
+  unsigned m = 0u;
+  for (int R = 0; R < nr; ++R) m |= 1u << (3 * R + 1);
+  return m;
+}
 static_assert(kApplyMaxThreads * kSinkStride * sizeof(double) <= kSinkBytes, "sink too small");
 
 template <typename T>
@@ -911,7 +920,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       dst[3 * r + 1] = pslot(A.P, P_RIF, rhs0 + r, A.maxp);
       dst[3 * r + 2] = pslot(A.P, P_FN, rhs0 + r, A.maxp);
     }
-    write_parts<3 * NR, 0x92u>(v, dst, lb);
+    write_parts<3 * NR, rinf_mask(NR)>(v, dst, lb);
   }
 }
 
@@ -1583,7 +1592,9 @@ __global__ void __launch_bounds__(1024)
     proj_status = sc->proj_status;
     lam = sc->lam;
   }
-  constexpr unsigned MM = 0x492u | (1u << (3 * NR + 2));
+  // max-reduced entries: |r|_inf of each RHS (3 R + 1, R < NR) and
+  // |dx|_inf (3 NR + 2); the rest are sums
+  constexpr unsigned MM = rinf_mask(NR) | (1u << (3 * NR + 2));
   reduce_parts<3 * NR + 4, MM>(v, src, cnt);
   if (threadIdx.x == 0) {
     double rinf = 0.0, rrel = 0.0, status = 0.0;

@@ -175,6 +175,37 @@ def test_outer_fp32_one_step_against_oracle(inner):
     assert np.abs(u - ur[0]).max() <= 1e-4 * np.abs(ur).max()
 
 
+@pytest.fixture(scope="module")
+def cfg3_oracle_two_steps():
+    """Two FP64 oracle outer iterations of the 128x64x64 workload as the
+    benchmark runs it (projected seeded density, u = 0, 8 PCG steps, r = 2
+    filter, mean projection, the workload's alpha0)."""
+    import json
+    import os
+    p = synth.config("cfg3")
+    a0 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alpha0.json")))["cfg3"]
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs, use_csr=False)
+    xr, ur, rrecs, rxs = run_outer_ref(ctx, p.x0, p.loads, 2, a0, p.inner_steps, 0.0, 1.0, p.vmax)
+    return p, a0, ur, rrecs, rxs
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_outer_workload_128x64x64_against_oracle(cfg3_oracle_two_steps, dtype):
+    """The benchmarked outer iteration at its full size and launch
+    configuration (128x64x64, 1,635,075 DOFs; FP32 with the fused PCG steps
+    and the fused last step + sensitivity, and FP64), two iterations against
+    the FP64 oracle: compliance, design and displacement."""
+    p, a0, ur, rrecs, rxs = cfg3_oracle_two_steps
+    say(f"outer 128x64x64 two steps {dtype}")
+    recs, xs, u = _run_gpu(p, 2, a0, dtype)
+    tol = 1e-9 if dtype == torch.float64 else 2e-5
+    for k in range(2):
+        assert abs(recs[k][0] - rrecs[k].compliance) <= tol * abs(rrecs[k].compliance), (k, recs[k][0])
+        assert np.abs(xs[k] - rxs[k + 1]).max() <= tol, (k, np.abs(xs[k] - rxs[k + 1]).max())
+        assert abs(recs[k][4] - rrecs[k].volume) <= 1e-9 * p.vmax + p.E * (0 if dtype == torch.float64 else 1e-7)
+    assert np.abs(u - ur[0]).max() <= (1e-9 if dtype == torch.float64 else 1e-4) * np.abs(ur).max()
+
+
 def test_outer_multiload_and_springs():
     """Multi-load (summed compliance) and a spring-loaded inverter grid: one
     FP64 outer iteration against the oracle."""

@@ -80,6 +80,27 @@ def test_relaxation_variants(method, omega):
     assert np.abs(host(u_t) - ur).max() <= 1e-12 * np.abs(ur).max()
 
 
+def test_residual_info_per_load_case():
+    """Four load cases (the largest RHS count) on a grid of many blocks:
+    after damped Jacobi steps, whose final norms come from the residual
+    pass, every case's reported ||r||_2, ||r||_inf and ||f||_2 equal those
+    of the oracle's residual (each case's |r|_inf is a max over blocks,
+    not a sum)."""
+    p = synth.multiload_cantilever(24, 12, 12, seed=4)
+    og, g, rho_t, s, K, D = _setup(p, torch.float64, 8, max_rhs=4)
+    F = p.loads
+    U = torch.zeros(4 * p.ndof, dtype=torch.float64, device=DEV)
+    info = torch.zeros(4 * 8, dtype=torch.float64, device=DEV)
+    g.inner_solve(rho_t, dev(F.ravel()), U, 6, method="jacobi", omega=0.6, info=info)
+    Uh = host(U).reshape(4, -1)
+    inf = host(info).reshape(4, 8)
+    for r in range(4):
+        res = F[r] - K @ Uh[r]
+        assert abs(inf[r][0] - np.linalg.norm(res)) <= 1e-12 * np.linalg.norm(F[r]), r
+        assert abs(inf[r][1] - np.abs(res).max()) <= 1e-12 * np.abs(F[r]).max(), r
+        assert abs(inf[r][2] - np.linalg.norm(F[r])) <= 1e-13 * np.linalg.norm(F[r]), r
+
+
 def test_pcg_to_tolerance():
     p = synth.cantilever(16, 8, 8, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=2)
     og, g, rho_t, s, K, D = _setup(p, torch.float64, 2)
