@@ -203,6 +203,10 @@ def test_outer_workload_128x64x64_against_oracle(cfg3_oracle_two_steps, dtype):
         assert abs(recs[k][0] - rrecs[k].compliance) <= tol * abs(rrecs[k].compliance), (k, recs[k][0])
         assert np.abs(xs[k] - rxs[k + 1]).max() <= tol, (k, np.abs(xs[k] - rxs[k + 1]).max())
         assert abs(recs[k][4] - rrecs[k].volume) <= 1e-9 * p.vmax + p.E * (0 if dtype == torch.float64 else 1e-7)
+        assert abs(recs[k][1] - rrecs[k].dx_inf) <= tol, (k, recs[k][1], rrecs[k].dx_inf)
+        assert abs(recs[k][3] - rrecs[k].lam) <= tol * max(1.0, abs(rrecs[k].lam)), (k, recs[k][3], rrecs[k].lam)
+        if dtype == torch.float64:
+            assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-7 * rrecs[k].r_inf, (k, recs[k][2], rrecs[k].r_inf)
     assert np.abs(u - ur[0]).max() <= (1e-9 if dtype == torch.float64 else 1e-4) * np.abs(ur).max()
 
 
@@ -210,6 +214,7 @@ def test_outer_multiload_and_springs():
     """Multi-load (summed compliance) and a spring-loaded inverter grid: one
     FP64 outer iteration against the oracle."""
     for p in (synth.multiload_cantilever(12, 6, 6, seed=2),
+              synth.multiload_cantilever(24, 12, 12, seed=3),   # several blocks per vector kernel
               synth.inverter(24, 8, 8, seed=1)):
         say(f"outer one step {p.name}")
         g = _grid(p, max_rhs=p.nrhs)
@@ -219,6 +224,8 @@ def test_outer_multiload_and_springs():
         for k in range(2):
             assert abs(recs[k][0] - rrecs[k].compliance) <= 1e-9 * abs(rrecs[k].compliance)
             assert np.abs(xs[k] - rxs[k + 1]).max() <= 1e-9
+            assert abs(recs[k][4] - rrecs[k].volume) <= 1e-9 * p.vmax
+            assert abs(recs[k][2] - rrecs[k].r_inf) <= 1e-7 * rrecs[k].r_inf
         assert np.abs(u.reshape(p.nrhs, -1) - ur).max() <= 1e-9 * np.abs(ur).max()
 
 
