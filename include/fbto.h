@@ -226,8 +226,9 @@ fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y
  * fbto_project_volume.  Where the root is not unique (a flat piece at
  * vmax), x is the same for every root; lambda may differ.
  * A non-finite y gives lambda = NaN and x = NaN.
- * The first call on a grid allocates the workspace, about
- * 24 bytes per element + 8 KiB per 2048 elements.  Errors: as
+ * The first call on a grid allocates the workspace: 24 bytes per element
+ * (two key buffers and the prefix sums) + 1 KiB of digit counts per 2048
+ * elements.  Errors: as
  * fbto_project_volume; FBTO_ERR_ARG if E >= 2^31. */
 fbto_status_t fbto_project_volume_sorted(fbto_grid_t g, fbto_prec_t prec, const void* y,
                                          void* x, double lo, double hi, double vmax,
