@@ -23,8 +23,10 @@ from .element import material_lame, element_stiffness, KE_DIAG
 from .grid import Grid
 from .operator import simp_scale, simp_dscale, assemble_K, apply_K, apply_K_rows, jacobi_diag
 from .solve import solve_direct, pcg_ref, pcg_to_tol, krylov_step_ref
-from .sensitivity import element_energy, element_bilinear, compliance_gradient, adjoint_gradient
-from .density_filter import cone_filter_matrix, filter_forward, filter_transpose
+from .sensitivity import (element_energy, element_bilinear, element_bilinear_at, compliance_gradient,
+                          adjoint_gradient)
+from .density_filter import (cone_filter_matrix, filter_forward, filter_transpose, filter_weight_sums_at,
+                             filter_forward_at, filter_transpose_at)
 from .projection import project_alg4, project_bisect, box_clamp
 from .outer import outer_step_ref, run_outer_ref, step_size
 
@@ -32,8 +34,9 @@ __all__ = [
     "material_lame", "element_stiffness", "KE_DIAG", "Grid",
     "simp_scale", "simp_dscale", "assemble_K", "apply_K", "apply_K_rows", "jacobi_diag",
     "solve_direct", "pcg_ref", "pcg_to_tol", "krylov_step_ref",
-    "element_energy", "element_bilinear", "compliance_gradient", "adjoint_gradient",
-    "cone_filter_matrix", "filter_forward", "filter_transpose",
+    "element_energy", "element_bilinear", "element_bilinear_at", "compliance_gradient", "adjoint_gradient",
+    "cone_filter_matrix", "filter_forward", "filter_transpose", "filter_weight_sums_at", "filter_forward_at",
+    "filter_transpose_at",
     "project_alg4", "project_bisect", "box_clamp",
     "outer_step_ref", "run_outer_ref", "step_size",
 ]

@@ -57,3 +57,45 @@ def filter_forward(H, Hs, x):
 def filter_transpose(H, Hs, g):
     """g_x = H^T (g / Hs)."""
     return H.T @ (np.asarray(g, dtype=np.float64) / Hs)
+
+
+def _neighbours(grid: Grid, elems, dx, dy, dz):
+    """Index of element e + (dx, dy, dz) for each e in elems, and whether it
+    lies inside the grid."""
+    ex, ey, ez = grid.elem_coords(np.asarray(elems))
+    jx, jy, jz = ex + dx, ey + dy, ez + dz
+    ok = (jx >= 0) & (jx < grid.nx) & (jy >= 0) & (jy < grid.ny) & (jz >= 0) & (jz < grid.nz)
+    j = np.where(ok, jx + grid.nx * (jy + grid.ny * jz), 0)
+    return j, ok
+
+
+def filter_weight_sums_at(grid: Grid, radius: float, elems):
+    """Hs_e for the given elements, summed over the stencil one offset at a
+    time (for sampled checks on grids too large for the matrix)."""
+    hs = np.zeros(len(elems))
+    for dx, dy, dz, w in stencil_offsets(radius):
+        _, ok = _neighbours(grid, elems, dx, dy, dz)
+        hs += np.where(ok, w, 0.0)
+    return hs
+
+
+def filter_forward_at(grid: Grid, radius: float, x, elems):
+    """rho_e = sum_j H_ej x_j / Hs_e at the given elements."""
+    x = np.asarray(x, dtype=np.float64)
+    acc = np.zeros(len(elems))
+    for dx, dy, dz, w in stencil_offsets(radius):
+        j, ok = _neighbours(grid, elems, dx, dy, dz)
+        acc += np.where(ok, w * x[j], 0.0)
+    return acc / filter_weight_sums_at(grid, radius, elems)
+
+
+def filter_transpose_at(grid: Grid, radius: float, g, elems):
+    """g_x[j] = sum_e H_ej g_e / Hs_e at the given elements j (H is
+    symmetric: the cone weight depends on the distance only)."""
+    g = np.asarray(g, dtype=np.float64)
+    acc = np.zeros(len(elems))
+    for dx, dy, dz, w in stencil_offsets(radius):
+        e, ok = _neighbours(grid, elems, dx, dy, dz)
+        hs = filter_weight_sums_at(grid, radius, e)
+        acc += np.where(ok, w * g[e] / hs, 0.0)
+    return acc

@@ -41,6 +41,19 @@ def element_bilinear(grid: Grid, lam, u, fixed_mask=None, KE=None, chunk=1 << 16
     return out
 
 
+def element_bilinear_at(grid: Grid, lam, u, elems, fixed_mask=None, KE=None):
+    """b_e = lambda_e^T KE u_e at the given elements only (for sampled checks
+    on grids too large for the full pass)."""
+    KE = element_stiffness() if KE is None else KE
+    U = np.atleast_2d(_masked(u, fixed_mask))
+    L = np.atleast_2d(_masked(lam, fixed_mask))
+    edof = grid.elem_dofs(np.asarray(elems))
+    out = np.zeros(len(elems))
+    for r in range(U.shape[0]):
+        out += np.einsum("ei,ij,ej->e", L[r][edof], KE, U[r][edof])
+    return out
+
+
 def element_energy(grid: Grid, u, fixed_mask=None, KE=None):
     """w_e = u_e^T KE u_e."""
     return element_bilinear(grid, u, u, fixed_mask, KE)

@@ -64,6 +64,40 @@ def test_filter(r, dtype):
     assert np.abs(tr - oracle.filter_transpose(H, Hs, x)).max() <= tol * 2
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_filter_and_sensitivity_384x192x192_sampled(dtype):
+    """The filter (forward and transpose) and the sensitivity on the largest
+    workload grid (384x192x192, 14,155,776 elements, its filter radius), at
+    4096 sampled elements plus the eight corners and boundary layers, against
+    the oracle's per-element forms of the same definitions."""
+    say(f"filter + sensitivity 384x192x192 sampled {dtype}")
+    p = synth.config("cfg5")
+    og = OGrid(p.nx, p.ny, p.nz)
+    g = _grid(p)
+    rng = np.random.default_rng(21)
+    corners = [og.nx * (og.ny * k + j) + i for i in (0, og.nx - 1) for j in (0, og.ny - 1) for k in (0, og.nz - 1)]
+    elems = np.unique(np.concatenate([rng.integers(0, p.E, 4096), corners,
+                                      np.arange(0, p.E, p.E // 64)]))
+    x_t = dev(synth.uniform_density(p.E, 5, 0.0, 1.0), dtype)
+    x = host(x_t)
+    fw = host(g.filter(x_t))
+    gr_t = dev(synth.normal_vector(p.E, 6).ravel(), dtype)
+    tr = host(g.filter(gr_t, transpose=True))
+    ftol = 1e-14 if dtype == torch.float64 else 1e-6
+    assert np.abs(fw[elems] - oracle.filter_forward_at(og, p.filter_radius, x, elems)).max() <= ftol
+    ref_t = oracle.filter_transpose_at(og, p.filter_radius, host(gr_t), elems)
+    assert np.abs(tr[elems] - ref_t).max() <= 2 * ftol * max(1.0, np.abs(ref_t).max())
+    del x_t, gr_t
+    rho_t = dev(synth.uniform_density(p.E, 2, 0.05, 1.0), dtype)
+    u_t = dev(synth.normal_vector(p.ndof, 3).ravel(), dtype)
+    d = host(g.sensitivity(rho_t, u_t))
+    rho, u = host(rho_t), host(u_t)
+    ref = -oracle.simp_dscale(rho[elems], p.penal, p.rho_min) * oracle.element_bilinear_at(og, u, u, elems,
+                                                                                            p.fixed_mask)
+    stol = 1e-12 if dtype == torch.float64 else 2e-5
+    assert np.abs(d[elems] - ref).max() <= stol * np.abs(ref).max()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("E_shape,vf,seed", [((17, 9, 5), 0.3, 1), ((128, 64, 64), 0.25, 2),
                                              ((6, 1, 1), 0.5, 3), ((40, 20, 10), 0.01, 4)])

@@ -109,3 +109,19 @@ def test_alg4_kkt_large():
     assert np.array_equal(oracle.project_alg4(y, lo, hi, 0.9 * E), np.clip(y, lo, hi))
     with pytest.raises(ValueError):
         oracle.project_alg4(y, 0.5, 1.0, 0.25 * E)
+
+
+@pytest.mark.parametrize("r", [1.5, 2.0, 3.0])
+def test_sampled_filter_equals_matrix_filter(r):
+    """The per-element filter (forward, transpose, weight sums) used for
+    sampled checks on large grids equals the matrix filter at every element
+    of a small grid, boundary-truncated stencils included."""
+    g = Grid(9, 6, 5)
+    H, Hs = oracle.cone_filter_matrix(g, r)
+    rng = np.random.default_rng(7)
+    x = rng.uniform(0.0, 1.0, g.E)
+    gr = rng.normal(0.0, 1.0, g.E)
+    e = np.arange(g.E)
+    assert np.allclose(oracle.filter_weight_sums_at(g, r, e), Hs, rtol=0, atol=1e-13)
+    assert np.allclose(oracle.filter_forward_at(g, r, x, e), oracle.filter_forward(H, Hs, x), rtol=0, atol=1e-14)
+    assert np.allclose(oracle.filter_transpose_at(g, r, gr, e), oracle.filter_transpose(H, Hs, gr), rtol=0, atol=1e-13)

@@ -71,3 +71,16 @@ def test_sensitivity_sums_over_load_cases():
     total = oracle.element_energy(g, U)
     parts = sum(oracle.element_energy(g, U[r]) for r in range(3))
     assert np.allclose(total, parts, rtol=1e-14, atol=0)
+
+
+def test_sampled_bilinear_equals_full_pass():
+    """The per-element bilinear form used for sampled checks on large grids
+    equals the full pass (two load cases, fixed DOFs masked)."""
+    g = Grid(7, 5, 4)
+    rng = np.random.default_rng(3)
+    u = rng.normal(0.0, 1.0, (2, g.ndof))
+    lam = rng.normal(0.0, 1.0, (2, g.ndof))
+    mask = (rng.uniform(0.0, 1.0, g.ndof) < 0.1).astype(np.uint8)
+    elems = rng.permutation(g.E)[:37]
+    full = oracle.element_bilinear(g, lam, u, mask)
+    assert np.allclose(oracle.element_bilinear_at(g, lam, u, elems, mask), full[elems], rtol=1e-14, atol=1e-13)
