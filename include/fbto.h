@@ -58,7 +58,7 @@ typedef enum fbto_status {
   FBTO_ERR_INFEASIBLE = 4,   /* vmax < lo * E: X is empty                 */
   FBTO_ERR_BREAKDOWN = 5,    /* device: p^T K p <= 0 in CG                 */
   FBTO_ERR_NONFINITE = 6,    /* device: NaN / Inf met                     */
-  FBTO_ERR_UNSUPPORTED = 7   /* valid request this build does not handle  */
+  FBTO_ERR_UNSUPPORTED = 7   /* valid request the library does not handle */
 } fbto_status_t;
 
 typedef enum fbto_prec { FBTO_F64 = 0, FBTO_F32 = 1 } fbto_prec_t;

@@ -10,8 +10,8 @@ Everything here is written for clarity, not speed: NumPy/SciPy in FP64,
 no blocking, no fusion, each function citing the passage of the paper
 (arXiv 2204.06204, "First-Order Bilevel Topology Optimization for Fast
 Mechanical Design") that it follows.  The paper is two-dimensional and
-never fixes an element; the 3D hex8 lifting and every reading of an
-unstated detail is listed in the design doc.
+never fixes an element; here it is lifted to 3D hex8 elements, and each
+function's docstring states the reading it takes of an unstated detail.
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: Gauss quadrature and rigid-body modes for KE, the patch test and a

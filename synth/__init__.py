@@ -231,8 +231,8 @@ CONFIG_NAMES = ("cfg1", "cfg2", "cfg3", "cfg3_inverter", "cfg4", "cfg5")
 
 
 def config(name: str) -> Problem:
-    """The five workload configurations of the benchmark (see the design doc for
-    every reading of an unspecified parameter)."""
+    """The five workload configurations of the benchmark: grid, volume
+    fraction, filter radius, inner steps, load and supports of each."""
     if name == "cfg1":
         return cantilever(16, 8, 8, volfrac=0.3, filter_radius=1.5, outer_iters=50,
                           inner_steps=5, load_node=(16, 4, 0), x0=0.3, name="cfg1",
