@@ -294,6 +294,33 @@ def test_outer_multiload_and_springs():
         assert np.abs(u.reshape(p.nrhs, -1) - ur).max() <= 1e-9 * np.abs(ur).max()
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("method", ["pcg", "krylov"])
+def test_outer_step_with_zero_load(dtype, method):
+    """Degenerate case: f = 0.  The low-level solve stays at u = 0 (zero
+    residual: no 0/0 in the PCG or Krylov coefficients).  Compliance and
+    gradient are 0, so the step leaves x where it was.  x is feasible at
+    vmax, so the projection returns it unchanged, with status 0."""
+    say(f"outer step zero load {method} {dtype}")
+    p = synth.cantilever(20, 10, 8, volfrac=0.3, filter_radius=2.0, outer_iters=2, inner_steps=8, seed=5)
+    g = _grid(p)
+    x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
+    x0 = host(x).copy()
+    u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    f = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    for k in (1, 2):
+        if method == "pcg":
+            g.outer_step(x, u, f, k, 0.002, p.inner_steps, 0.0, p.vmax, info=info)
+        else:
+            g.outer_step(x, u, f, k, 0.002, 20, 0.0, p.vmax, info=info, method="krylov", beta=1.0)
+        inf = host(info)
+        assert np.all(np.isfinite(inf)) and inf[6] == 0, inf
+        assert inf[0] == 0.0 and inf[2] == 0.0
+        assert np.abs(host(x) - x0).max() <= 2 * EPS[dtype], np.abs(host(x) - x0).max()
+    assert np.all(host(u) == 0.0)
+
+
 def test_outer_steps_bitwise_reproducible():
     """Two runs of 10 FP32 outer iterations give bit-identical designs and
     displacements (fixed reduction order, no atomics)."""
