@@ -303,8 +303,8 @@ def projection_timing(torch, reps=20):
     and FP64, from HIP events on the launch stream.  The input is a
     gradient step from a U[0.2, 0.4] density (the multiplier is positive).
     Streaming bytes of the sorted path per element, with b bytes per value:
-    keys 2b; per 8-bit pass histogram b + scatter 2b; prefix sums b + b + 8;
-    bracket b (its searches hit cache); clamp 2b."""
+    per 8-bit pass histogram b + scatter 2b (the first pass reads y itself);
+    prefix sums b + b + 8; bracket b (its searches hit cache); clamp 2b."""
     import numpy as np
     import synth
     from paper_2204_06204_amd.grid import Grid
@@ -332,7 +332,7 @@ def projection_timing(torch, reps=20):
                 torch.cuda.synchronize()
                 rec[f"{method}_us"] = e0.elapsed_time(e1) * 1e3 / reps
             passes = 8 * b // 8
-            nbytes = p.E * (2 * b + passes * 3 * b + 2 * b + 8 + b + 2 * b)
+            nbytes = p.E * (passes * 3 * b + 2 * b + 8 + b + 2 * b)
             rec["sort_bytes"] = nbytes
             rec["sort_hbm_frac"] = nbytes / (rec["sort_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
             lv = lam.cpu().tolist()

@@ -12,22 +12,22 @@
 // c_lo - c_hi).  The largest node with phi >= vmax and the smallest with
 // phi <= vmax bound the linear piece that holds the root, which is then
 // solved exactly.  phi is monotone along each family, so a coarse pass over
-// every 256th node finds the windows that hold these two nodes, and a fine
+// every 255th node finds the windows that hold these two nodes, and a fine
 // pass evaluates the nodes of those windows.
 //
 // Kernels, in launch order:
-//   k_sort_keys      y -> order-preserving unsigned keys
 //   k_radix_hist     per 2048-key tile, counts of the current 8-bit digit
+//                    (the first pass maps y to order-preserving unsigned
+//                    keys as it reads it)
 //   k_radix_scan     per digit, exclusive scan of the tile counts
 //   k_radix_scatter  stable scatter of each tile (wave ballots rank the keys)
 //                    (the three above run 4 times for FP32, 8 for FP64)
 //   k_prefix_part    FP64 sum of each tile of sorted values
 //   k_prefix_top     exclusive scan of the tile sums (one block)
 //   k_prefix_down    S[i] for every i, S[E] = the total
-//   k_bracket_coarse phi at every 256th node of each family, and phi(0)
-//   k_bracket_fine   phi at every node of the four windows that hold the
-//                    crossing of vmax
-//   k_lambda         one thread: lambda
+//   k_bracket_coarse phi at every 255th node of each family, and phi(0)
+//   k_bracket_lambda one block: phi at every node of the four windows that
+//                    hold the crossing of vmax, then lambda
 //   k_clamp          x = clamp(y - lambda, lo, hi)
 #include "device.h"
 
@@ -40,9 +40,10 @@ constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kRadix = 256;
 constexpr int kRadixBits = 8;
 constexpr int kBracketBlocks = kSortBracketBlocks;
-constexpr int kCoarseStride = 256;  // nodes between the coarse samples of a family
-constexpr int kFineBlock = 320;     // threads of a fine window: kCoarseStride + 1 nodes
-static_assert(kFineBlock >= kCoarseStride + 1 && kFineBlock % 64 == 0, "fine window");
+constexpr int kCoarseStride = 255;            // nodes between the coarse samples of a family
+constexpr int kWindow = kCoarseStride + 1;     // nodes of a fine window
+constexpr int kFineBlock = 4 * kWindow;        // one block: the four windows, a node per thread
+static_assert(kFineBlock % 64 == 0 && kFineBlock <= 1024, "fine block");
 
 template <typename T> struct KeyOf;
 template <> struct KeyOf<float> { using type = uint32_t; };
@@ -106,15 +107,16 @@ __device__ __forceinline__ V block_scan_excl(V v, V* sh, V& total) {
   return off + incl - v;
 }
 
-template <typename T, typename K>
-__global__ void __launch_bounds__(kSortBlock) k_sort_keys(const T* y, K* keys, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock)
-    keys[i] = to_key(y[i]);
+// Key i of a pass: from y itself on the first pass (y != NULL), otherwise
+// from the previous pass's output.
+template <typename K, typename T>
+__device__ __forceinline__ K load_key(const K* keys, const T* y, int64_t i) {
+  return y ? to_key(y[i]) : keys[i];
 }
 
-template <typename K>
+template <typename K, typename T>
 __global__ void __launch_bounds__(kSortBlock)
-    k_radix_hist(const K* keys, int64_t n, int shift, uint32_t* hist, int ntiles) {
+    k_radix_hist(const K* keys, const T* y, int64_t n, int shift, uint32_t* hist, int ntiles) {
   __shared__ uint32_t h[kRadix];
   const int tid = threadIdx.x;
   h[tid] = 0u;
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(kSortBlock)
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t i = base + k * kSortBlock + tid;
-    if (i < n) atomicAdd(&h[(uint32_t)(keys[i] >> shift) & (kRadix - 1)], 1u);
+    if (i < n) atomicAdd(&h[(uint32_t)(load_key(keys, y, i) >> shift) & (kRadix - 1)], 1u);
   }
   __syncthreads();
   hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
@@ -158,10 +160,10 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scan(uint32_t* hist, int n
 //  3. LDS entry j goes to the digit's global start for this tile plus its
 //     offset in the digit's run, so consecutive threads write consecutive
 //     addresses within each run.
-template <typename K>
+template <typename K, typename T>
 __global__ void __launch_bounds__(kSortBlock)
-    k_radix_scatter(const K* in, K* out, int64_t n, int shift, const uint32_t* hist, const uint32_t* tot,
-                    int ntiles) {
+    k_radix_scatter(const K* in, const T* y, K* out, int64_t n, int shift, const uint32_t* hist,
+                    const uint32_t* tot, int ntiles) {
   __shared__ K stage[kSortTile];
   __shared__ uint32_t cnt[kRadix];                 // keys of each digit ranked so far
   __shared__ uint32_t wcnt[kSortBlock / 64][kRadix];
@@ -180,7 +182,7 @@ __global__ void __launch_bounds__(kSortBlock)
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const bool valid = base + (int64_t)k * kSortBlock + tid < n;
-    key[k] = valid ? in[base + (int64_t)k * kSortBlock + tid] : (K)0;
+    key[k] = valid ? load_key(in, y, base + (int64_t)k * kSortBlock + tid) : (K)0;
     const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
     uint64_t same = __ballot(valid);
 #pragma unroll
@@ -338,28 +340,30 @@ __global__ void __launch_bounds__(kSortBlock)
   }
 }
 
-// Fine pass: four blocks, one window of kCoarseStride + 1 nodes each.
-// Block 2 q + f covers family f around its first sample with phi <= vmax
-// (q = 0: the smallest node with phi <= vmax lies there) or its last
-// sample with phi >= vmax (q = 1: the largest node with phi >= vmax).
-// win[4 b ..]: that block's largest node with phi >= vmax and its phi, its
-// smallest node with phi <= vmax and its phi (-inf / +inf when none).
+// Fine pass and lambda, in one block: four windows of kWindow nodes, a node
+// per thread.  Window 2 q + f covers family f around its first sample with
+// phi <= vmax (q = 0: the smallest node with phi <= vmax lies there) or its
+// last sample with phi >= vmax (q = 1: the largest node with phi >= vmax).
+// Over all four windows, the largest node with phi >= vmax and the
+// smallest with phi <= vmax bound the linear piece of the root.  lambda is
+// 0 when phi(0) <= vmax, else the root on that piece.
 template <typename K>
 __global__ void __launch_bounds__(kFineBlock)
-    k_bracket_fine(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax,
-                   const double* part, int nb, double* win) {
+    k_bracket_lambda(const K* sk, const double* S, int64_t n, double lo, double hi, double vmax,
+                     const double* part, int nb, const double* phi0, double* lam_ws, double* lam_out) {
   double c[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += kFineBlock) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) c[k] += part[(int64_t)k * nb + b];
   }
   block_reduce<4, 0u>(c);
-  const int f = blockIdx.x & 1, q = blockIdx.x >> 1;
+  const int wdw = threadIdx.x / kWindow;
+  const int f = wdw & 1, q = wdw >> 1;
   const int64_t cnt = (int64_t)(q == 0 ? (f == 0 ? c[0] : c[2]) : (f == 0 ? c[1] : c[3]));
   int64_t i0 = (cnt - 1) * kCoarseStride, i1 = cnt * kCoarseStride;
   if (i0 < 0) i0 = 0;
   if (i1 > n - 1) i1 = n - 1;
-  const int64_t i = i0 + threadIdx.x;
+  const int64_t i = i0 + threadIdx.x % kWindow;
   const bool have = i <= i1;
   double t = 0.0, ph = 0.0;
   if (have) {
@@ -371,33 +375,10 @@ __global__ void __launch_bounds__(kFineBlock)
   // phi at the two extremes (equal nodes give equal phi)
   double p[2] = {have && ph >= vmax && t == v[0] ? ph : -INFINITY, have && ph <= vmax && -t == v[1] ? ph : -INFINITY};
   block_reduce<2, 0x3u>(p);
-  if (threadIdx.x == 0) {
-    win[4 * blockIdx.x + 0] = v[0];
-    win[4 * blockIdx.x + 1] = p[0];
-    win[4 * blockIdx.x + 2] = -v[1];
-    win[4 * blockIdx.x + 3] = p[1];
-  }
-}
-
-// lambda from the four windows: 0 when phi(0) <= vmax, else the root on the
-// linear piece between the largest node with phi >= vmax and the smallest
-// with phi <= vmax.
-__global__ void k_lambda(const double* win, const double* phi0, const double* total, double vmax, double* lam_ws,
-                         double* lam_out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double tl = -INFINITY, fl = 0.0, tu = INFINITY, fu = 0.0;
-  for (int b = 0; b < 4; ++b) {
-    if (win[4 * b] > tl) {
-      tl = win[4 * b];
-      fl = win[4 * b + 1];
-    }
-    if (win[4 * b + 2] < tu) {
-      tu = win[4 * b + 2];
-      fu = win[4 * b + 3];
-    }
-  }
+  if (threadIdx.x != 0) return;
+  const double tl = v[0], fl = p[0], tu = -v[1], fu = p[1];
   double lam;
-  if (!isfinite(*total)) {
+  if (!isfinite(S[n])) {
     lam = NAN;                                   // a non-finite y
   } else if (*phi0 <= vmax) {
     lam = 0.0;                                   // the clamped point is feasible
@@ -451,20 +432,24 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
   const SortWs& W = g->sort;
   const int64_t n = g->geo.E;
   const int ntiles = (int)((n + kSortTile - 1) / kSortTile);
-  K* a = (K*)W.keys[0];
-  K* b = (K*)W.keys[1];
+  // the first pass reads y (src = NULL); later passes alternate between
+  // the two key buffers
+  K* src = nullptr;
+  K* dst = (K*)W.keys[0];
+  K* spare = (K*)W.keys[1];
   const int nv = vec_blocks(n);
-  hipLaunchKernelGGL((k_sort_keys<T, K>), dim3(nv), dim3(kSortBlock), 0, st, y, a, n);
   for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += kRadixBits) {
-    hipLaunchKernelGGL((k_radix_hist<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n, shift, W.hist,
-                       ntiles);
+    const T* yk = shift == 0 ? y : nullptr;
+    hipLaunchKernelGGL((k_radix_hist<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, n, shift,
+                       W.hist, ntiles);
     hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kSortBlock), 0, st, W.hist, ntiles, W.tot);
-    hipLaunchKernelGGL((k_radix_scatter<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, b, n, shift,
-                       (const uint32_t*)W.hist, (const uint32_t*)W.tot, ntiles);
-    K* t = a;
-    a = b;
-    b = t;
+    hipLaunchKernelGGL((k_radix_scatter<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, dst, n,
+                       shift, (const uint32_t*)W.hist, (const uint32_t*)W.tot, ntiles);
+    K* nxt = src ? src : spare;
+    src = dst;
+    dst = nxt;
   }
+  K* a = src;  // the sorted keys
   hipLaunchKernelGGL((k_prefix_part<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n, W.part);
   hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kSortBlock), 0, st, W.part, ntiles);
   hipLaunchKernelGGL((k_prefix_down<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n,
@@ -472,14 +457,11 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
   const int64_t ns = (n + kCoarseStride - 1) / kCoarseStride;  // samples per family
   const int64_t nbc64 = (2 * ns + 1 + kSortBlock - 1) / kSortBlock;
   const int nbc = (int)(nbc64 < kBracketBlocks ? nbc64 : kBracketBlocks);
-  double* win = W.brk + 4 * kBracketBlocks;
   double* phi0 = W.lam + 1;
   hipLaunchKernelGGL((k_bracket_coarse<K>), dim3(nbc), dim3(kSortBlock), 0, st, (const K*)a, (const double*)W.S, n,
                      lo, hi, vmax, ns, W.brk, nbc, phi0);
-  hipLaunchKernelGGL((k_bracket_fine<K>), dim3(4), dim3(kFineBlock), 0, st, (const K*)a, (const double*)W.S, n, lo,
-                     hi, vmax, (const double*)W.brk, nbc, win);
-  hipLaunchKernelGGL(k_lambda, dim3(1), dim3(64), 0, st, (const double*)win, (const double*)phi0,
-                     (const double*)(W.S + n), vmax, W.lam, lam_out);
+  hipLaunchKernelGGL((k_bracket_lambda<K>), dim3(1), dim3(kFineBlock), 0, st, (const K*)a, (const double*)W.S, n,
+                     lo, hi, vmax, (const double*)W.brk, nbc, (const double*)phi0, W.lam, lam_out);
   hipLaunchKernelGGL((k_clamp<T>), dim3(nv), dim3(kSortBlock), 0, st, y, x, n, lo, hi, (const double*)W.lam);
   return hipGetLastError();
 }
