@@ -17,6 +17,8 @@
 //
 // Kernels, in launch order:
 //   k_radix_hist     per 2048-key tile, counts of the current 8-bit digit
+//                    (on the top digit, equal digits of a wave are added
+//                    up before the LDS atomic)
 //                    (the first pass maps y to order-preserving unsigned
 //                    keys as it reads it)
 //   k_radix_scan     per digit, exclusive scan of the tile counts
@@ -114,18 +116,44 @@ __device__ __forceinline__ K load_key(const K* keys, const T* y, int64_t i) {
   return y ? to_key(y[i]) : keys[i];
 }
 
+// Lanes of the wave holding the same digit d as this lane (eight ballots,
+// one per digit bit), among the lanes in `valid`.
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t valid) {
+  uint64_t same = valid;
+#pragma unroll
+  for (int b = 0; b < kRadixBits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t m = __ballot(bit);
+    same &= bit ? m : ~m;
+  }
+  return same;
+}
+
+// Digit counts of one tile.  `aggregate` (the top digit, which takes few
+// values here, so that one LDS atomic per key piles up on one bin): the
+// lanes of a wave with the same digit add their count once, from the lowest
+// of them.  The eight ballots this costs are slower than plain atomics on
+// the other digits.
 template <typename K, typename T>
 __global__ void __launch_bounds__(kSortBlock)
-    k_radix_hist(const K* keys, const T* y, int64_t n, int shift, uint32_t* hist, int ntiles) {
+    k_radix_hist(const K* keys, const T* y, int64_t n, int shift, int aggregate, uint32_t* hist, int ntiles) {
   __shared__ uint32_t h[kRadix];
   const int tid = threadIdx.x;
+  const uint64_t earlier = (1ull << __lane_id()) - 1ull;
   h[tid] = 0u;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
     const int64_t i = base + k * kSortBlock + tid;
-    if (i < n) atomicAdd(&h[(uint32_t)(load_key(keys, y, i) >> shift) & (kRadix - 1)], 1u);
+    const bool valid = i < n;
+    const uint32_t d = valid ? (uint32_t)(load_key(keys, y, i) >> shift) & (kRadix - 1) : 0u;
+    if (aggregate) {
+      const uint64_t same = same_digit_lanes(d, __ballot(valid));
+      if (valid && (same & earlier) == 0ull) atomicAdd(&h[d], (uint32_t)__popcll(same));
+    } else if (valid) {
+      atomicAdd(&h[d], 1u);
+    }
   }
   __syncthreads();
   hist[(int64_t)tid * ntiles + blockIdx.x] = h[tid];
@@ -184,13 +212,7 @@ __global__ void __launch_bounds__(kSortBlock)
     const bool valid = base + (int64_t)k * kSortBlock + tid < n;
     key[k] = valid ? load_key(in, y, base + (int64_t)k * kSortBlock + tid) : (K)0;
     const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-    uint64_t same = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      same &= bit ? m : ~m;
-    }
+    const uint64_t same = same_digit_lanes(d, __ballot(valid));
     const uint32_t before = (uint32_t)__popcll(same & earlier);
     if (valid && before == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
     __syncthreads();
@@ -440,8 +462,9 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
   const int nv = vec_blocks(n);
   for (int shift = 0; shift < (int)(8 * sizeof(K)); shift += kRadixBits) {
     const T* yk = shift == 0 ? y : nullptr;
+    const int top = shift + kRadixBits == (int)(8 * sizeof(K));
     hipLaunchKernelGGL((k_radix_hist<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, n, shift,
-                       W.hist, ntiles);
+                       top, W.hist, ntiles);
     hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kSortBlock), 0, st, W.hist, ntiles, W.tot);
     hipLaunchKernelGGL((k_radix_scatter<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, dst, n,
                        shift, (const uint32_t*)W.hist, (const uint32_t*)W.tot, ntiles);
