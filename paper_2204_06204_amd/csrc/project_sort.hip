@@ -177,13 +177,15 @@ __global__ void __launch_bounds__(kSortBlock) k_radix_scan(uint32_t* hist, int n
 }
 
 // Stable scatter of one tile by the current digit.
-//  1. Rank: the tile is read in kSortItems rounds of kSortBlock consecutive
-//     keys, so round, wave and lane order are the key order.  In a round the
-//     lanes of a wave that hold the same digit are found with eight ballots
-//     (one per digit bit).  A key's rank within its digit in the tile is the
-//     digit's count in earlier rounds plus the same-digit keys of earlier
-//     waves and lanes.
-//  2. The keys are placed in LDS in digit order (the tile's digit starts are
+//  1. Rank, wave by wave with no block barrier: wave w takes the kWaveKeys
+//     consecutive keys from w * kWaveKeys, in kSortItems rounds of 64, so
+//     wave, round and lane order are the key order.  In a round the lanes
+//     holding the same digit are found with eight ballots (one per digit
+//     bit).  A key's rank within its digit among its wave's keys is the
+//     wave's running count of that digit plus the same-digit lanes before
+//     it; the lowest of those lanes then advances the count.
+//  2. Per digit, the counts of earlier waves are added (one barrier), and
+//     the keys are placed in LDS in digit order (the tile's digit starts are
 //     a scan of its digit counts).
 //  3. LDS entry j goes to the digit's global start for this tile plus its
 //     offset in the digit's run, so consecutive threads write consecutive
@@ -192,59 +194,60 @@ template <typename K, typename T>
 __global__ void __launch_bounds__(kSortBlock)
     k_radix_scatter(const K* in, const T* y, K* out, int64_t n, int shift, const uint32_t* hist,
                     const uint32_t* tot, int ntiles) {
+  constexpr int kWaves = kSortBlock / 64;
+  constexpr int kWaveKeys = 64 * kSortItems;
   __shared__ K stage[kSortTile];
-  __shared__ uint32_t cnt[kRadix];                 // keys of each digit ranked so far
-  __shared__ uint32_t wcnt[kSortBlock / 64][kRadix];
-  __shared__ uint32_t tstart[kRadix];              // tile-local start of each digit
-  __shared__ uint32_t gbase[kRadix];               // global position minus tile-local start (mod 2^32)
-  __shared__ uint32_t sh[kSortBlock / 64];
+  __shared__ uint32_t wcnt[kWaves][kRadix];   // per-wave digit counts, then the counts of earlier waves
+  __shared__ uint32_t tstart[kRadix];          // tile-local start of each digit
+  __shared__ uint32_t gbase[kRadix];           // global position minus tile-local start (mod 2^32)
+  __shared__ uint32_t sh[kWaves];
   const int tid = threadIdx.x, lane = __lane_id(), w = tid >> 6;
-  cnt[tid] = 0u;
 #pragma unroll
-  for (int q = 0; q < kSortBlock / 64; ++q) wcnt[q][tid] = 0u;
+  for (int q = 0; q < kWaves; ++q) wcnt[q][tid] = 0u;
   __syncthreads();
   const uint64_t earlier = (1ull << lane) - 1ull;
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + (int64_t)w * kWaveKeys + lane;
   K key[kSortItems];
   uint32_t rank[kSortItems];
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    const bool valid = base + (int64_t)k * kSortBlock + tid < n;
-    key[k] = valid ? load_key(in, y, base + (int64_t)k * kSortBlock + tid) : (K)0;
+    const int64_t i = base + (int64_t)k * 64;
+    const bool valid = i < n;
+    key[k] = valid ? load_key(in, y, i) : (K)0;
     const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
     const uint64_t same = same_digit_lanes(d, __ballot(valid));
     const uint32_t before = (uint32_t)__popcll(same & earlier);
-    if (valid && before == 0u) wcnt[w][d] = (uint32_t)__popcll(same);
-    __syncthreads();
-    uint32_t r = cnt[d] + before;
-    for (int q = 0; q < w; ++q) r += wcnt[q][d];
+    const uint32_t r = wcnt[w][d] + before;
     rank[k] = r;
-    __syncthreads();
-    uint32_t adv = 0u;
+    // the lowest same-digit lane advances the wave's count; a wave's LDS
+    // accesses complete in program order, so the next round reads it
+    if (valid && before == 0u) wcnt[w][d] = r + (uint32_t)__popcll(same);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  uint32_t c = 0u;
 #pragma unroll
-    for (int q = 0; q < kSortBlock / 64; ++q) {
-      adv += wcnt[q][tid];
-      wcnt[q][tid] = 0u;
-    }
-    cnt[tid] += adv;
-    __syncthreads();
+  for (int q = 0; q < kWaves; ++q) {
+    const uint32_t v = wcnt[q][tid];
+    wcnt[q][tid] = c;  // keys of this digit in earlier waves
+    c += v;
   }
   uint32_t total;
-  const uint32_t ts = block_scan_excl(cnt[tid], sh, total);
+  const uint32_t ts = block_scan_excl(c, sh, total);
   const uint32_t ds = block_scan_excl(tot[tid], sh, total);
   tstart[tid] = ts;
   gbase[tid] = ds + hist[(int64_t)tid * ntiles + blockIdx.x] - ts;
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSortItems; ++k) {
-    if (base + (int64_t)k * kSortBlock + tid < n) {
+    if (base + (int64_t)k * 64 < n) {
       const uint32_t d = (uint32_t)(key[k] >> shift) & (kRadix - 1);
-      const uint32_t j = tstart[d] + rank[k];
+      const uint32_t j = tstart[d] + wcnt[w][d] + rank[k];
       if (j < (uint32_t)kSortTile) stage[j] = key[k];  // always true when the counts are consistent
     }
   }
   __syncthreads();
-  const int64_t left = n - base;
+  const int64_t left = n - (int64_t)blockIdx.x * kSortTile;
   const int tile_n = left < kSortTile ? (int)left : kSortTile;
   for (int j = tid; j < tile_n; j += kSortBlock) {
     const K kk = stage[j];
