@@ -40,6 +40,7 @@ constexpr int kSortBlock = 256;  // four waves; every kernel here assumes it
 constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortBlock * kSortItems;
 constexpr int kRadix = 256;
+constexpr int kScanBlock = 1024;  // the single-block scans over tile counts and tile sums
 constexpr int kRadixBits = 8;
 constexpr int kBracketBlocks = kSortBracketBlocks;
 constexpr int kCoarseStride = 255;            // nodes between the coarse samples of a family
@@ -90,9 +91,10 @@ __device__ __forceinline__ double wave_scan_incl(double v) {
   return v;
 }
 
-// Exclusive scan over the block of kSortBlock threads; `total` receives the
-// block's sum.  Every thread must call it (it synchronises twice).
-template <typename V>
+// Exclusive scan over a block of NT threads (sh: NT / 64 entries); `total`
+// receives the block's sum.  Every thread must call it (it synchronises
+// twice).
+template <int NT = kSortBlock, typename V>
 __device__ __forceinline__ V block_scan_excl(V v, V* sh, V& total) {
   const int w = threadIdx.x >> 6;
   const V incl = wave_scan_incl(v);
@@ -100,7 +102,7 @@ __device__ __forceinline__ V block_scan_excl(V v, V* sh, V& total) {
   __syncthreads();
   V off = V(0), tot = V(0);
 #pragma unroll
-  for (int k = 0; k < kSortBlock / 64; ++k) {
+  for (int k = 0; k < NT / 64; ++k) {
     if (k < w) off += sh[k];
     tot += sh[k];
   }
@@ -161,15 +163,15 @@ __global__ void __launch_bounds__(kSortBlock)
 
 // One block per digit: the tile counts of the digit become the number of
 // keys with that digit in earlier tiles; tot[digit] the digit's total.
-__global__ void __launch_bounds__(kSortBlock) k_radix_scan(uint32_t* hist, int ntiles, uint32_t* tot) {
-  __shared__ uint32_t sh[kSortBlock / 64];
+__global__ void __launch_bounds__(kScanBlock) k_radix_scan(uint32_t* hist, int ntiles, uint32_t* tot) {
+  __shared__ uint32_t sh[kScanBlock / 64];
   uint32_t* row = hist + (int64_t)blockIdx.x * ntiles;
   uint32_t carry = 0u;
-  for (int c = 0; c < ntiles; c += kSortBlock) {
+  for (int c = 0; c < ntiles; c += kScanBlock) {
     const int j = c + threadIdx.x;
     const uint32_t v = j < ntiles ? row[j] : 0u;
     uint32_t total;
-    const uint32_t ex = block_scan_excl(v, sh, total);
+    const uint32_t ex = block_scan_excl<kScanBlock>(v, sh, total);
     if (j < ntiles) row[j] = carry + ex;
     carry += total;
   }
@@ -271,14 +273,14 @@ __global__ void __launch_bounds__(kSortBlock) k_prefix_part(const K* sk, int64_t
   if (threadIdx.x == 0) part[blockIdx.x] = v[0];
 }
 
-__global__ void __launch_bounds__(kSortBlock) k_prefix_top(double* part, int nb) {
-  __shared__ double sh[kSortBlock / 64];
+__global__ void __launch_bounds__(kScanBlock) k_prefix_top(double* part, int nb) {
+  __shared__ double sh[kScanBlock / 64];
   double carry = 0.0;
-  for (int c = 0; c < nb; c += kSortBlock) {
+  for (int c = 0; c < nb; c += kScanBlock) {
     const int j = c + threadIdx.x;
     const double v = j < nb ? part[j] : 0.0;
     double total;
-    const double ex = block_scan_excl(v, sh, total);
+    const double ex = block_scan_excl<kScanBlock>(v, sh, total);
     if (j < nb) part[j] = carry + ex;
     carry += total;
   }
@@ -468,7 +470,7 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
     const int top = shift + kRadixBits == (int)(8 * sizeof(K));
     hipLaunchKernelGGL((k_radix_hist<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, n, shift,
                        top, W.hist, ntiles);
-    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kSortBlock), 0, st, W.hist, ntiles, W.tot);
+    hipLaunchKernelGGL(k_radix_scan, dim3(kRadix), dim3(kScanBlock), 0, st, W.hist, ntiles, W.tot);
     hipLaunchKernelGGL((k_radix_scatter<K, T>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)src, yk, dst, n,
                        shift, (const uint32_t*)W.hist, (const uint32_t*)W.tot, ntiles);
     K* nxt = src ? src : spare;
@@ -477,7 +479,7 @@ hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, do
   }
   K* a = src;  // the sorted keys
   hipLaunchKernelGGL((k_prefix_part<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n, W.part);
-  hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kSortBlock), 0, st, W.part, ntiles);
+  hipLaunchKernelGGL(k_prefix_top, dim3(1), dim3(kScanBlock), 0, st, W.part, ntiles);
   hipLaunchKernelGGL((k_prefix_down<K>), dim3(ntiles), dim3(kSortBlock), 0, st, (const K*)a, n,
                      (const double*)W.part, W.S);
   const int64_t ns = (n + kCoarseStride - 1) / kCoarseStride;  // samples per family
