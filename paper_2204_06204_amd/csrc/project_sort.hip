@@ -419,12 +419,21 @@ __global__ void __launch_bounds__(kFineBlock)
   if (lam_out) *lam_out = lam;
 }
 
+// x = clamp(y - lambda, lo, hi); four independent elements per thread and
+// iteration (the grid stride apart) keep more loads in flight.
 template <typename T>
 __global__ void __launch_bounds__(kSortBlock)
     k_clamp(const T* y, T* x, int64_t n, double lo, double hi, const double* lam_ws) {
   const double lam = *lam_ws;
-  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kSortBlock)
-    x[i] = isnan(lam) ? (T)NAN : (T)fmin(fmax((double)y[i] - lam, lo), hi);
+  const int64_t stride = (int64_t)gridDim.x * kSortBlock;
+  for (int64_t i = (int64_t)blockIdx.x * kSortBlock + threadIdx.x; i < n; i += 4 * stride) {
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = i + u * stride < n ? y[i + u * stride] : (T)0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * stride < n) x[i + u * stride] = isnan(lam) ? (T)NAN : (T)fmin(fmax((double)v[u] - lam, lo), hi);
+  }
 }
 
 }  // namespace
