@@ -255,6 +255,34 @@ def test_krylov_step_cfg3_residual_decreases():
         prev = rn
 
 
+def test_krylov_step_384x192x192_fp32_against_fp64():
+    """The largest workload grid (43M DOFs), degree 20 from u = 0.  The step
+    minimises the residual over a space that holds f, so ||r|| <= ||f||.
+    The reported norm equals f - K u by the apply.  The FP32 step (fused
+    Lanczos passes) agrees with the FP64 one: residual norm to 1e-3 and u
+    to 1e-3 of its largest entry."""
+    say("krylov 384x192x192 fp32 vs fp64")
+    p = synth.config("cfg5")
+    from paper_2204_06204_amd.grid import Grid
+    g = Grid.from_problem(p)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    out = {}
+    for dtype in (torch.float32, torch.float64):
+        rho = dev(p.x0, dtype)
+        f = dev(p.loads[0], dtype)
+        u = torch.zeros_like(f)
+        g.inner_solve(rho, f, u, 20, method="krylov", omega=1.0, info=info)
+        inf = host(info)
+        rn = float(torch.linalg.norm((f - g.apply_K(rho, u)).double()))
+        fn = float(torch.linalg.norm(f.double()))
+        assert inf[4] == 0 and abs(inf[0] - rn) <= 1e-3 * rn and rn < fn, (dtype, inf[0], rn, fn)
+        out[dtype] = (rn, host(u))
+        del rho, f, u
+    (r32, u32), (r64, u64) = out[torch.float32], out[torch.float64]
+    assert abs(r32 - r64) <= 1e-3 * r64, (r32, r64)
+    assert np.abs(u32 - u64).max() <= 1e-3 * np.abs(u64).max()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_krylov_step_at_the_solution_is_a_fixed_point(dtype):
     """Degenerate case: from the exact solution the residual is zero, every
