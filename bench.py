@@ -352,7 +352,7 @@ def cpu_baseline(p, seconds):
     import oracle
     from oracle.outer import OuterContext, outer_step_ref
     ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs, use_csr=False)
-    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    x = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
     u = np.zeros_like(p.loads)
     n, k = 0, 1
     t0 = time.perf_counter()

@@ -58,7 +58,10 @@ typedef enum fbto_status {
   FBTO_ERR_INFEASIBLE = 4,   /* vmax < lo * E: X is empty                 */
   FBTO_ERR_BREAKDOWN = 5,    /* device: p^T K p <= 0 in CG                 */
   FBTO_ERR_NONFINITE = 6,    /* device: NaN / Inf met                     */
-  FBTO_ERR_UNSUPPORTED = 7   /* valid request the library does not handle */
+  FBTO_ERR_UNSUPPORTED = 7,  /* valid request the library does not handle */
+  FBTO_INEXACT = 8           /* device: the volume projection used up its   */
+                             /* pass budget; x is feasible (sum x <= vmax)  */
+                             /* but not the exact projection               */
 } fbto_status_t;
 
 typedef enum fbto_prec { FBTO_F64 = 0, FBTO_F32 = 1 } fbto_prec_t;
@@ -203,13 +206,30 @@ fbto_status_t fbto_filter(fbto_grid_t g, fbto_prec_t prec, int32_t transpose,
  * Eq. piecewiseLinearEQ; Alg. 4 computes the same point by sorting).
  * x = clamp(y - lambda, lo, hi) with lambda = 0 if clamp(y) is feasible,
  * else the root of sum clamp(y - lambda, lo, hi) = vmax found on the device
- * in FP64 (Newton steps on the piecewise-linear sum, safeguarded by
- * bisection, finished by the exact solve on the final linear piece).
- * y, x: [E] (may alias).  lambda (device FP64, may be NULL) receives lambda.
- * Errors: FBTO_ERR_INFEASIBLE if vmax < lo * E. */
+ * in FP64 by passes over y: each pass evaluates the sum and the linear
+ * piece on either side of the current lambda; the next pass solves that
+ * piece exactly, which ends the search when the root lies on it, and
+ * otherwise takes a Newton step safeguarded by bisection of the bracket.
+ *   max_passes  pass budget, 1 .. 64; 0 selects 8.  Each pass is one launch
+ *               that streams y once; passes after the search has ended
+ *               return at once.  Seeded U[0.2, 0.4] densities after a
+ *               gradient step need 3-4 passes; values spread over many
+ *               decades (lognormal, Pareto), or spread far wider than
+ *               hi - lo, can need 20-45.
+ *   lambda      device FP64 scalar, may be NULL: the multiplier.
+ *   status      device FP64 scalar, may be NULL: 0; FBTO_INEXACT when the
+ *               budget ran out before the root's piece was found (x is then
+ *               clamp(y - b, lo, hi) for the feasible end b of the last
+ *               bracket: sum x <= vmax, but not the projection;
+ *               fbto_project_volume_sorted is exact for any input); or
+ *               FBTO_ERR_NONFINITE for non-finite y.
+ * y, x: [E] (may alias).  Asynchronous (no host synchronisation).
+ * Errors: FBTO_ERR_INFEASIBLE if vmax < lo * E; FBTO_ERR_ARG for a budget
+ * outside 0 .. 64. */
 fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y,
                                   void* x, double lo, double hi, double vmax,
-                                  double* lambda, void* stream);
+                                  int32_t max_passes, double* lambda, double* status,
+                                  void* stream);
 
 /* The same projection computed the way Alg. 4 does it, in its GPU form
  * (Sec. 4.3: a radix sort and parallel scans), as a cross-check of
@@ -266,6 +286,30 @@ fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, v
                                      const void* f, int32_t nrhs, int32_t k, double alpha0,
                                      int32_t degree, double beta, int32_t mean_project,
                                      double lo, double vmax, double* info, void* stream);
+
+/* Tuning options of a grid handle (fbto_set_option).  They change how the
+ * work is laid out or how long a search may run, not what is computed.
+ *   FBTO_OPT_PROJ_PASSES  pass budget of the volume projection inside
+ *                         fbto_outer_step / _krylov / _exact, 1 .. 64
+ *                         (default 4).  These projections start from the
+ *                         previous multiplier and need 1-2 passes on the
+ *                         workloads measured; FBTO_INEXACT in the info
+ *                         record's status says the budget ran out.
+ *   FBTO_OPT_APPLY_TILE   tile of the z-marching K(rho)u kernels (apply,
+ *   FBTO_OPT_CGF_TILE     residual and CG products; the fused CG step):
+ *                         bx | by << 8 | dz << 16 (threads per tile row and
+ *                         column, 8 <= bx <= 64, 4 <= by <= 64,
+ *                         128 <= bx * by <= 256, slab depth dz 1 .. 64; a
+ *                         zero field is chosen by the cost model), or 0 for
+ *                         the cost model alone.  A shape the kernel cannot
+ *                         run makes the next launch fail (FBTO_ERR_HIP).
+ * Errors: FBTO_ERR_ARG for an unknown option or a value out of range. */
+typedef enum fbto_option {
+  FBTO_OPT_PROJ_PASSES = 0,
+  FBTO_OPT_APPLY_TILE = 1,
+  FBTO_OPT_CGF_TILE = 2
+} fbto_option_t;
+fbto_status_t fbto_set_option(fbto_grid_t g, fbto_option_t option, int64_t value);
 
 /* Message of the last error on this thread ("" if none). */
 const char* fbto_last_error(void);

@@ -27,7 +27,7 @@ from .sensitivity import (element_energy, element_bilinear, element_bilinear_at,
                           adjoint_gradient)
 from .density_filter import (cone_filter_matrix, filter_forward, filter_transpose, filter_weight_sums_at,
                              filter_forward_at, filter_transpose_at)
-from .projection import project_alg4, project_bisect, box_clamp
+from .projection import project_volume_ref, project_bisect, box_clamp
 from .outer import outer_step_ref, run_outer_ref, step_size
 
 __all__ = [
@@ -37,6 +37,6 @@ __all__ = [
     "element_energy", "element_bilinear", "element_bilinear_at", "compliance_gradient", "adjoint_gradient",
     "cone_filter_matrix", "filter_forward", "filter_transpose", "filter_weight_sums_at", "filter_forward_at",
     "filter_transpose_at",
-    "project_alg4", "project_bisect", "box_clamp",
+    "project_volume_ref", "project_bisect", "box_clamp",
     "outer_step_ref", "run_outer_ref", "step_size",
 ]

@@ -14,7 +14,7 @@ step for the sensitivity):
   6. g_x <- g_x - mean(g_x)           mean-projected gradient (Sec. 4.2)
   7. y = x - alpha_k * g_x / 2,  alpha_k = alpha0 k^(-3/4)   (Sec. 5)
      (the paper's objective is l = c/2, so its gradient is g_x / 2)
-  8. x <- Proj_X(y)                   Alg. 4
+  8. x <- Proj_X(y)                   Sec. 4.2, Eq. piecewiseLinearEQ
   9. metrics ||x_new - x||_inf, ||r||_inf (recursive residual), c (Sec. 5)
 """
 from __future__ import annotations
@@ -27,7 +27,7 @@ from .density_filter import cone_filter_matrix, filter_forward, filter_transpose
 from .element import element_stiffness
 from .grid import Grid
 from .operator import apply_K, assemble_K, jacobi_diag, simp_dscale, simp_scale
-from .projection import project_alg4
+from .projection import project_volume_ref
 from .sensitivity import element_energy
 from .solve import krylov_step_ref, pcg_ref, solve_direct
 
@@ -102,7 +102,7 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
     if mean_project:
         g_x = g_x - g_x.mean()
     y = x - step_size(alpha0, k) * 0.5 * g_x
-    x_new, lam = project_alg4(y, lo, hi, vmax, return_lambda=True)
+    x_new, lam = project_volume_ref(y, lo, hi, vmax, return_lambda=True)
     rec = OuterRecord(k=k, compliance=c, dx_inf=float(np.abs(x_new - x).max()),
                       r_inf=r_inf, lam=float(lam), volume=float(x_new.sum()))
     return x_new, (U if np.ndim(u) == 2 else U[0]), rec, g_x
@@ -111,7 +111,7 @@ def outer_step_ref(ctx: OuterContext, x, u, f, k, alpha0, inner_steps, lo, hi, v
 def run_outer_ref(ctx: OuterContext, x_init, f, iters, alpha0, inner_steps, lo, hi, vmax,
                   mean_project=True, u0=None, low_level=None):
     """x_0 = Proj_X(x_init), u_0 = 0 (or u0); then `iters` outer steps."""
-    x = project_alg4(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
+    x = project_volume_ref(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
     F = np.atleast_2d(f)
     u = np.zeros_like(F) if u0 is None else np.array(u0, dtype=np.float64)
     recs, xs = [], [x.copy()]
@@ -127,7 +127,7 @@ def default_alpha0(ctx: OuterContext, x_init, f, inner_steps, lo, hi, vmax,
                    max_move=0.2, mean_project=True):
     """Step-size reading: alpha0 such that the first step moves no density
     by more than `max_move`:  alpha0 = max_move / max|g_P(x_1) / 2|."""
-    x = project_alg4(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
+    x = project_volume_ref(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
     F = np.atleast_2d(f)
     _, _, _, g_x = outer_step_ref(ctx, x, np.zeros_like(F), F, 1, 0.0, inner_steps, lo, hi,
                                   vmax, mean_project)

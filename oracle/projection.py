@@ -1,14 +1,17 @@
 """Euclidean projection onto X = {lo <= v <= hi, 1^T v <= vmax} (oracle, FP64).
 
-Sec. 4.2 (Efficient Implementation) and Alg. 4.  If clamping to the box
-already satisfies the sum constraint the clamp is the projection.
-Otherwise the KKT conditions give v = clamp(y - lambda 1, lo, hi) with
-lambda solving the piecewise-linear equation (Eq. piecewiseLinearEQ)
-    vmax = sum_e clamp(y_e - lambda, lo, hi),
-whose 2E breakpoints are y_e - lo and y_e - hi.  Alg. 4 sorts them and
-sweeps with a running slope and right-hand side, then solves on the linear
-piece that crosses vmax.  The paper writes the upper bound as 1; it is a
-parameter `hi` here.
+Sec. 4.2 (Efficient Implementation), Eq. piecewiseLinearEQ.  The projection
+of y is the minimiser of |v - y|^2 over X.  If clamping y to the box already
+satisfies the sum constraint the clamp is the projection.  Otherwise the
+KKT conditions give v = clamp(y - lambda, lo, hi) with lambda > 0 solving
+    phi(lambda) = vmax,   phi(t) = sum_e clamp(y_e - t, lo, hi),
+a continuous, non-increasing function that is linear between consecutive
+breakpoints of {y_e - lo} and {y_e - hi}.  The paper's Alg. 4 finds the
+crossing by sorting those breakpoints and sweeping; here the crossing piece
+is located by a binary search over the sorted breakpoints with phi
+evaluated directly from its definition at each probe, and lambda is the
+linear interpolation on that piece.  The paper writes the upper bound as 1;
+it is a parameter `hi` here.
 """
 from __future__ import annotations
 
@@ -19,8 +22,15 @@ def box_clamp(y, lo, hi):
     return np.clip(np.asarray(y, dtype=np.float64), lo, hi)
 
 
-def project_alg4(y, lo, hi, vmax, return_lambda=False):
-    """Projection by sorting the breakpoints (Alg. 4)."""
+def volume_sum(y, t, lo, hi):
+    """phi(t) = sum_e clamp(y_e - t, lo, hi), summed directly."""
+    return float(box_clamp(y - t, lo, hi).sum())
+
+
+def project_volume_ref(y, lo, hi, vmax, return_lambda=False):
+    """The projection onto X from Eq. piecewiseLinearEQ.  Where phi is flat
+    at vmax every point of the flat piece is a root; the smallest is
+    returned (x is the same for all of them)."""
     y = np.asarray(y, dtype=np.float64)
     E = y.size
     if vmax < E * lo:
@@ -28,29 +38,22 @@ def project_alg4(y, lo, hi, vmax, return_lambda=False):
     x = box_clamp(y, lo, hi)
     if x.sum() <= vmax:
         return (x, 0.0) if return_lambda else x
-    # breakpoints: kind +1 at y_e - lo (element reaches lo, slope back up),
-    #              kind -1 at y_e - hi (element leaves hi, slope down)
-    pts = np.concatenate([y - lo, y - hi])
-    kind = np.concatenate([np.ones(E), -np.ones(E)])
-    order = np.argsort(pts, kind="stable")
-    pts, kind = pts[order], kind[order]
-    slope, rhs, lam_last = 0.0, E * hi, 0.0
-    node_lam, node_rhs = [], []
-    for lam_star, kd in zip(pts, kind):
-        rhs = rhs + slope * (lam_star - lam_last)
-        slope += kd
-        node_lam.append(lam_star)
-        node_rhs.append(rhs)
-        lam_last = lam_star
-    lam = None
-    for a in range(len(node_lam) - 1):
-        ra, rb = node_rhs[a], node_rhs[a + 1]
-        if ra >= vmax >= rb:
-            la, lb = node_lam[a], node_lam[a + 1]
-            lam = la if ra == rb else la + (ra - vmax) * (lb - la) / (ra - rb)
-            break
-    if lam is None:                     # vmax == E*lo exactly: past the last node
-        lam = node_lam[-1]
+    # phi(t) = E hi at the smallest breakpoint, E lo <= vmax at the largest
+    t = np.unique(np.concatenate([y - lo, y - hi]))
+    a, b = 0, t.size - 1            # phi(t[a]) > vmax >= phi(t[b])
+    if volume_sum(y, t[b], lo, hi) > vmax:   # only when vmax < E lo, excluded above
+        raise ValueError("no root of the volume equation")
+    while b - a > 1:
+        m = (a + b) // 2
+        if volume_sum(y, t[m], lo, hi) > vmax:
+            a = m
+        else:
+            b = m
+    fa, fb = volume_sum(y, t[a], lo, hi), volume_sum(y, t[b], lo, hi)
+    if fb == vmax:
+        lam = float(t[b])
+    else:                           # phi is linear on [t[a], t[b]]
+        lam = float(t[a] + (fa - vmax) * (t[b] - t[a]) / (fa - fb))
     x = box_clamp(y - lam, lo, hi)
     return (x, lam) if return_lambda else x
 

@@ -13,6 +13,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libfbto.so"
 
 FBTO_OK, FBTO_ERR_ARG, FBTO_ERR_ALLOC, FBTO_ERR_HIP = 0, 1, 2, 3
 FBTO_ERR_INFEASIBLE, FBTO_ERR_BREAKDOWN, FBTO_ERR_NONFINITE, FBTO_ERR_UNSUPPORTED = 4, 5, 6, 7
+FBTO_INEXACT = 8
+FBTO_OPT_PROJ_PASSES, FBTO_OPT_APPLY_TILE, FBTO_OPT_CGF_TILE = 0, 1, 2
 FBTO_F64, FBTO_F32 = 0, 1
 FBTO_PCG_JACOBI, FBTO_RICHARDSON, FBTO_DAMPED_JACOBI, FBTO_KRYLOV = 0, 1, 2, 3
 FBTO_SOLVE_INFO = 8
@@ -40,7 +42,7 @@ _SIGS = {
     "fbto_sensitivity": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, _VP, C.c_int32, _VP, _VP, _VP]),
     "fbto_filter": (C.c_int, [_VP, C.c_int, C.c_int32, _VP, _VP, _VP]),
     "fbto_project_volume": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_double, C.c_double,
-                                      _VP, _VP]),
+                                      C.c_int32, _VP, _VP, _VP]),
     "fbto_project_volume_sorted": (C.c_int, [_VP, C.c_int, _VP, _VP, C.c_double, C.c_double, C.c_double,
                                              _VP, _VP]),
     "fbto_outer_step": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
@@ -49,6 +51,7 @@ _SIGS = {
                                         C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_krylov": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                          C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
+    "fbto_set_option": (C.c_int, [_VP, C.c_int, C.c_int64]),
     "fbto_last_error": (C.c_char_p, []),
     "fbto_version": (C.c_char_p, []),
 }

@@ -93,6 +93,8 @@ void modal_coefficients(double young, double poisson, Modal<double>& km, double&
   ke_diag = (lam + 4.0 * mu) / 9.0;
 }
 
+ProjWs proj_ws(fbto_grid_s* g) { return ProjWs{g->partials, g->max_partials, g->sc}; }
+
 fbto_status_t check_grid(fbto_grid_t g) {
   if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
   return FBTO_OK;
@@ -195,27 +197,6 @@ struct CgCounts {
   int dot;  // partials of f . x (final vector step, or the dot kernel)
 };
 
-// Diagnostics: FBTO_CG_TRACE=1 prints the reduced partial set of parity
-// `par` (r.z, w.z, r.r over n blocks) and the step coefficients after each
-// CG kernel (synchronises the stream).
-static void cg_trace(fbto_grid_s* g, hipStream_t st, const char* what, int k, int par, int n) {
-  static const bool on = getenv("FBTO_CG_TRACE") != nullptr;
-  if (!on) return;
-  (void)hipStreamSynchronize(st);
-  std::vector<double> h((size_t)P_COUNT * 4 * g->max_partials);
-  (void)hipMemcpy(h.data(), g->partials, h.size() * sizeof(double), hipMemcpyDeviceToHost);
-  Scalars sc;
-  (void)hipMemcpy(&sc, g->sc, sizeof(Scalars), hipMemcpyDeviceToHost);
-  auto sum = [&](int slot) {
-    double a = 0.0;
-    for (int i = 0; i < n; ++i) a += h[((size_t)slot * 4) * g->max_partials + i];
-    return a;
-  };
-  fprintf(stderr, "cg %s k=%d set %d (n=%d): rz %.17g wz %.17g rr %.17g | alpha %.17g beta %.17g done %g st %g\n",
-          what, k, par, n, sum(P_RZ0 + par), sum(P_PQ0 + par), sum(P_RN0 + par), sc.alpha[0], sc.beta[0],
-          sc.done[0], sc.status[0]);
-}
-
 template <typename T>
 fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, int steps,
                       double rtol, hipStream_t st, bool f_dot, CgCounts* cn_out, T* sens = nullptr,
@@ -243,14 +224,12 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   };
   // step 0's product w = K z from the residual's z
   HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
-  cg_trace(g, st, "apply", 0, 0, nb_a);
   int k = 0;
   if constexpr (sizeof(T) == 4) {
     // fused steps: the update of step k and the product of step k + 1 in one pass
     for (; k + 1 < steps; ++k) {
       HIP_TRY(launch_cg_fused<T>(g, rho, set[k & 1], set[(k + 1) & 1], invD, nrhs, k, nb_a, cn.fn, rtol, st,
                                  &nb_a));
-      cg_trace(g, st, "fused", k, (k + 1) & 1, nb_a);
       if (rtol > 0.0 && (k + 2) % 64 == 0 && k + 2 < steps) {
         bool done = false;
         if (fbto_status_t e = all_done(done)) return e;
@@ -267,7 +246,6 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
       HIP_TRY(launch_cg_step<T>(g, x, x, set[0].r, z, z, set[0].w, set[0].p, set[0].s, invD, nullptr, nrhs, nb_a,
                                 cn.fn, k, rtol, st, &nb_v));
       HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, k + 1, st, &nb_a));
-      cg_trace(g, st, "step+apply", k, (k + 1) & 1, nb_a);
       if (rtol > 0.0 && (k + 2) % 64 == 0 && k + 2 < steps) {
         bool done = false;
         if (fbto_status_t e = all_done(done)) return e;
@@ -427,7 +405,8 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 1, st));
   const double alpha_k = alpha0 * std::pow((double)k, -0.75);
   HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
-  HIP_TRY(launch_project<T>(g, (const T*)V.y, x, lo, 1.0, vmax, 1, x, nullptr, st));
+  HIP_TRY(launch_project<T>(proj_ws(g), g->geo.E, (const T*)V.y, x, lo, 1.0, vmax, 1, g->proj_passes_warm, x,
+                            nullptr, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
   HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
   return FBTO_OK;
@@ -585,6 +564,30 @@ fbto_status_t fbto_destroy_grid(fbto_grid_t g) {
   drop_extra(g);
   delete g;
   return ok();
+}
+
+fbto_status_t fbto_set_option(fbto_grid_t g, fbto_option_t option, int64_t value) {
+  if (check_grid(g)) return FBTO_ERR_ARG;
+  switch (option) {
+    case FBTO_OPT_PROJ_PASSES:
+      if (value < 1 || value > kProjMaxPasses)
+        return fail(FBTO_ERR_ARG, "projection passes %lld outside [1, %d]", (long long)value, kProjMaxPasses);
+      g->proj_passes_warm = (int)value;
+      return ok();
+    case FBTO_OPT_APPLY_TILE:
+    case FBTO_OPT_CGF_TILE: {
+      if (value < 0 || value >= ((int64_t)1 << 24)) return fail(FBTO_ERR_ARG, "tile value %lld out of range", (long long)value);
+      const int bx = (int)(value & 0xff), by = (int)((value >> 8) & 0xff), dz = (int)((value >> 16) & 0xff);
+      if ((bx && (bx < 8 || bx > 64)) || (by && (by < 4 || by > 64)) || dz > 64 || (bx && by && (bx * by < 128 || bx * by > 256)))
+        return fail(FBTO_ERR_ARG, "tile %d x %d x %d outside the kernel's limits", bx, by, dz);
+      g->tile_override[option == FBTO_OPT_CGF_TILE ? 1 : 0] = (int)value;
+      for (auto& a : g->tiles)  // chosen again on the next launch
+        for (auto& b : a)
+          for (auto& t : b) t = TileChoice{};
+      return ok();
+    }
+  }
+  return fail(FBTO_ERR_ARG, "unknown option %d", (int)option);
 }
 
 fbto_status_t fbto_grid_sizes(fbto_grid_t g, int64_t* n_elem, int64_t* n_node, int64_t* n_dof) {
@@ -759,19 +762,25 @@ fbto_status_t fbto_filter(fbto_grid_t g, fbto_prec_t prec, int32_t transpose, co
 }
 
 fbto_status_t fbto_project_volume(fbto_grid_t g, fbto_prec_t prec, const void* y, void* x, double lo,
-                                  double hi, double vmax, double* lambda, void* stream) {
+                                  double hi, double vmax, int32_t max_passes, double* lambda, double* status,
+                                  void* stream) {
   if (check_grid(g) || check_prec(prec)) return FBTO_ERR_ARG;
   if (!y || !x) return fail(FBTO_ERR_ARG, "y and x must be non-NULL");
   if (!(std::isfinite(lo) && std::isfinite(hi) && lo <= hi)) return fail(FBTO_ERR_ARG, "need finite lo <= hi");
   if (!std::isfinite(vmax)) return fail(FBTO_ERR_ARG, "vmax must be finite");
+  if (max_passes < 0 || max_passes > kProjMaxPasses)
+    return fail(FBTO_ERR_ARG, "max_passes = %d outside [0, %d]", (int)max_passes, kProjMaxPasses);
   if (vmax < lo * (double)g->geo.E)
     return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g: the feasible set is empty", vmax,
                 lo * (double)g->geo.E);
+  const int passes = max_passes == 0 ? 8 : max_passes;
   hipStream_t st = (hipStream_t)stream;
   if (prec == FBTO_F64)
-    HIP_TRY(launch_project<double>(g, (const double*)y, (double*)x, lo, hi, vmax, 0, nullptr, lambda, st));
+    HIP_TRY(launch_project<double>(proj_ws(g), g->geo.E, (const double*)y, (double*)x, lo, hi, vmax, 0, passes,
+                                   nullptr, lambda, status, st));
   else
-    HIP_TRY(launch_project<float>(g, (const float*)y, (float*)x, lo, hi, vmax, 0, nullptr, lambda, st));
+    HIP_TRY(launch_project<float>(proj_ws(g), g->geo.E, (const float*)y, (float*)x, lo, hi, vmax, 0, passes,
+                                  nullptr, lambda, status, st));
   return ok();
 }
 

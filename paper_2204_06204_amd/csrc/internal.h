@@ -92,13 +92,15 @@ enum PartSlot {
   P_DOT,               // sum_r f_r . u_r
   P_GSUM,              // sum of the filtered gradient
   P_S0, P_YMAX, P_NACT,  // projection seed: sum clamp(y), max y, #interior
-  P_E0,                // projection pass: 11 consecutive slots P_E0 .. P_E0+10
-  P_VOL = P_E0 + 11,   // sum x_new
+  P_E0,                // projection pass: two sets of 11 slots, P_E0 + 11 q .. P_E0 + 11 q + 10;
+                       // pass t reads set t & 1 (written by pass t - 1) and writes set (t + 1) & 1
+  P_VOL = P_E0 + 22,   // sum x_new
   P_DX,                // max |x_new - x_old|
   P_KRN0, P_KRN1,      // Krylov step: ||y||^2 of the new Lanczos vector, by iteration parity
   P_COUNT
 };
 constexpr int kMaxVecBlocks = 1024;
+constexpr int kProjMaxPasses = 64;   // pass budget limit of the volume projection
 constexpr size_t kSinkBytes = 64 * 1024;  // scratch for stores of threads that own no output
 
 // Workspace vectors of one precision.  The CG vectors come in two sets:
@@ -183,6 +185,8 @@ struct fbto_grid_s {
   int n_cu = 256;
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
   fbto::TileChoice tiles[2][2][6] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
+  int tile_override[2] = {0, 0};         // FBTO_OPT_APPLY_TILE, FBTO_OPT_CGF_TILE (0: cost model)
+  int proj_passes_warm = 4;              // FBTO_OPT_PROJ_PASSES: projection passes of the outer steps
   fbto::SortWs sort;                     // sort-based projection
 };
 
@@ -254,9 +258,19 @@ size_t sort_ws_layout(int64_t E, SortWs* W);
 template <typename T>
 hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, double hi, double vmax,
                                  double* lam_out, hipStream_t st);
+// Workspace of the volume projection: per-block partial slots (P_COUNT x 4 x
+// maxp doubles) and the search state in a Scalars record.
+struct ProjWs {
+  double* P;
+  int maxp;
+  Scalars* sc;
+};
+// Projection of y onto {lo <= x <= hi, sum x <= vmax} with `passes` search
+// passes.  seeded: the seed partials (P_S0, P_YMAX, P_NACT) were left by
+// k_step.  lam_out, status_out: device FP64 scalars, may be NULL.
 template <typename T>
-hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi,
-                          double vmax, int seeded, const T* x_old, double* lam_out,
+hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
+                          int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_convert(const void* in, void* out, int64_t n, int to_double, hipStream_t st);

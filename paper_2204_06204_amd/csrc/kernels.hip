@@ -1157,10 +1157,10 @@ static size_t apply_lds_bytes(int bx, int by) {
 // prologue)), with a floor of kMinWaves resident waves per round below which
 // latency, not issue, sets the time.
 template <typename T, int NR, int MODE>
-static TileChoice choose_tile(const Geo& G, int n_cu) {
-  const char* env = getenv(MODE == MODE_CGF ? "FBTO_CGF_TILE" : "FBTO_APPLY_TILE");
-  int want_bx = 0, want_by = 0, want_dz = 0;
-  if (env) sscanf(env, "%dx%dx%d", &want_bx, &want_by, &want_dz);
+static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
+  // fixed fields of a caller's override (FBTO_OPT_APPLY_TILE / _CGF_TILE)
+  const int want_bx = override_shape & 0xff, want_by = (override_shape >> 8) & 0xff,
+            want_dz = (override_shape >> 16) & 0xff;
   constexpr double kMinWaves = 8.0;
   TileChoice best{};
   double best_cost = 1e300;
@@ -1205,9 +1205,6 @@ static TileChoice choose_tile(const Geo& G, int n_cu) {
       }
     }
   }
-  if (getenv("FBTO_APPLY_VERBOSE"))
-    fprintf(stderr, "fbto apply<%s, NR=%d, mode=%d>: tile %dx%d, dz %d, %d blocks\n",
-            sizeof(T) == 8 ? "f64" : "f32", NR, MODE, best.bx, best.by, best.dz, best.nblocks);
   return best;
 }
 
@@ -1216,7 +1213,7 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
                                  int* nb_out) {
   TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][NR - 1][MODE];
   if (t.nblocks == 0) {
-    t = choose_tile<T, NR, MODE>(g->geo, g->n_cu);
+    t = choose_tile<T, NR, MODE>(g->geo, g->n_cu, g->tile_override[MODE == MODE_CGF ? 1 : 0]);
     if (t.nblocks == 0) return hipErrorInvalidConfiguration;
   }
   if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
@@ -1313,7 +1310,7 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
                           int* nb_out) {
   TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][0][MODE_SENSF];
   if (t.nblocks == 0) {
-    t = choose_tile<T, 1, MODE_SENSF>(g->geo, g->n_cu);
+    t = choose_tile<T, 1, MODE_SENSF>(g->geo, g->n_cu, g->tile_override[0]);
     if (t.nblocks == 0) return hipErrorInvalidConfiguration;
   }
   if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
@@ -1614,7 +1611,9 @@ __global__ void __launch_bounds__(1024)
       if (stR != 0.0) status = stR;
     }
     if (info) {
-      if (proj_status > 0.0) status = proj_status;
+      // the projection's status: non-finite values take precedence, an
+      // inexact projection (FBTO_INEXACT) only reports when the solve had none
+      if (proj_status > 0.0 && (status == 0.0 || proj_status == (double)FBTO_ERR_NONFINITE)) status = proj_status;
       sc->dot[0] = v[3 * NR];
       info[FBTO_OI_COMPLIANCE] = v[3 * NR];
       info[FBTO_OI_DX_INF] = v[3 * NR + 2];
@@ -2177,10 +2176,15 @@ struct ProjDecision {
   bool bad;
 };
 
+// First slot of the evaluation set q of the projection passes.
+__host__ __device__ constexpr int proj_set(int q) { return P_E0 + 11 * (q & 1); }
+// pass t reads set t and writes set t + 1: two disjoint runs of 11 slots
+static_assert(proj_set(0) + 11 <= proj_set(1) && proj_set(1) + 11 <= P_VOL, "projection slot sets overlap");
+
 // The search state after a pass (identical in every block).  `first`: the
 // partials are the seed (sum clamp(y), max y, #interior); otherwise the
-// evaluation at sc->lam.
-__device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool first, double lo, double hi,
+// evaluation at `lam` left in the slots of set `set`.
+__device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool first, int set, double lo, double hi,
                                     double vmax, double lam_prev, double lam, double a, double b) {
   ProjDecision d{};
   if (first) {
@@ -2215,7 +2219,7 @@ __device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool firs
   int cnt[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
-    src[i] = pslot(P, P_E0 + i, 0, maxp);
+    src[i] = pslot(P, proj_set(set) + i, 0, maxp);
     cnt[i] = nb;
   }
   reduce_parts<11, 0x600u>(v, src, cnt);
@@ -2266,6 +2270,10 @@ __device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool firs
   return d;
 }
 
+// Pass t of the search: decides from the seed (t = 0) or from pass t - 1's
+// evaluation (set t & 1), then evaluates at the new multiplier into set
+// (t + 1) & 1.  The two sets keep a block that starts late from reading
+// partials that blocks of the same pass have already overwritten.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
     k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, double* P, int maxp,
@@ -2277,7 +2285,8 @@ __global__ void __launch_bounds__(kVecBlock)
       for (int i = 0; i < 4; ++i) out[i] = in[i];
     return;
   }
-  const ProjDecision d = proj_decide(P, maxp, nb, pass == 0, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+  const ProjDecision d =
+      proj_decide(P, maxp, nb, pass == 0, pass, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     out[0] = d.lam;
     out[1] = d.a;
@@ -2310,29 +2319,38 @@ __global__ void __launch_bounds__(kVecBlock)
   }
   double* dst[11];
 #pragma unroll
-  for (int i = 0; i < 11; ++i) dst[i] = pslot(P, P_E0 + i, 0, maxp);
+  for (int i = 0; i < 11; ++i) dst[i] = pslot(P, proj_set(pass + 1) + i, 0, maxp);
   write_parts<11, 0x600u>(v, dst, blockIdx.x);
 }
 
+// x = clamp(y - lambda, lo, hi) after `passes` passes.  A search still open
+// then decides once more from the last evaluation (set passes & 1); if that
+// does not land on the root's piece either, x takes the feasible end of the
+// bracket and the status says FBTO_INEXACT.  The lead thread records the
+// status (also into *status_out) and lambda.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
     k_proj_final(int64_t E, const T* y, T* x, double lo, double hi, double vmax, const T* x_old, double* P,
-                 int maxp, int nb, int passes, Scalars* sc, double* lam_out) {
+                 int maxp, int nb, int passes, Scalars* sc, double* lam_out, double* status_out) {
   const double* in = sc->ps[passes & 1];
   double lam = in[0];
   bool bad = false, unfinished = false;
   if (in[3] == 0.0) {  // pass budget spent: decide from the last evaluation
-    const ProjDecision d = proj_decide(P, maxp, nb, false, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+    const ProjDecision d =
+        proj_decide(P, maxp, nb, false, passes, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
     lam = d.done ? d.lam : d.b;
     bad = d.bad;
     unfinished = !d.done;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (unfinished) sc->proj_status = -1.0;   // finished on the feasible end of the bracket
-    if (bad) sc->proj_status = (double)FBTO_ERR_NONFINITE;
+    double status = sc->proj_status;  // 0, or FBTO_ERR_NONFINITE from a pass
+    if (bad) status = (double)FBTO_ERR_NONFINITE;
+    else if (unfinished && status == 0.0) status = (double)FBTO_INEXACT;
+    sc->proj_status = status;
     sc->lam = lam;
     sc->lam_prev = lam;   // warm start of the next projection (no block here reads it)
     if (lam_out) *lam_out = lam;
+    if (status_out) *status_out = status;
   }
   double v[2] = {0.0, 0.0};
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
@@ -2346,17 +2364,6 @@ __global__ void __launch_bounds__(kVecBlock)
   write_parts<2, 0x2u>(v, dst, blockIdx.x);
 }
 
-// Pass budget of the projection.  From a cold start the search takes up to
-// six passes on the workloads here; warm-started from the previous
-// multiplier (the outer loop) it takes one or two, so four leave margin.  A
-// search that runs out of passes ends on the feasible end of its bracket and
-// says so in the status.
-static int proj_passes(bool seeded) {
-  const char* env = getenv("FBTO_PROJ_PASSES");
-  int p = env ? atoi(env) : (seeded ? 4 : 8);
-  return p < 1 ? 1 : (p > 64 ? 64 : p);
-}
-
 template <typename T>
 hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
                        int mean_project, double lo, double hi, hipStream_t st) {
@@ -2367,21 +2374,20 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
 }
 
 template <typename T>
-hipError_t launch_project(fbto_grid_s* g, const T* y, T* x, double lo, double hi, double vmax,
-                          int seeded, const T* x_old, double* lam_out, hipStream_t st) {
-  const int64_t E = g->geo.E;
+hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
+                          int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
+                          hipStream_t st) {
   const int nb = vec_blocks(E);
+  if (nb > W.maxp) return hipErrorInvalidValue;
   if (!seeded) {
-    hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, g->partials,
-                       g->max_partials);
+    hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, W.P, W.maxp);
   }
-  const int passes = proj_passes(seeded != 0);
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p,
-                       g->partials, g->max_partials, nb, g->sc);
+    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W.P, W.maxp,
+                       nb, W.sc);
   }
-  hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old,
-                     g->partials, g->max_partials, nb, passes, g->sc, lam_out);
+  hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W.P,
+                     W.maxp, nb, passes, W.sc, lam_out, status_out);
   return hipGetLastError();
 }
 
@@ -2479,8 +2485,8 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   template hipError_t launch_filter<T>(fbto_grid_s*, int, const T*, T*, int, hipStream_t);             \
   template hipError_t launch_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, double,       \
                                      double, hipStream_t);                                             \
-  template hipError_t launch_project<T>(fbto_grid_s*, const T*, T*, double, double, double, int,       \
-                                        const T*, double*, hipStream_t);
+  template hipError_t launch_project<T>(const ProjWs&, int64_t, const T*, T*, double, double, double, int, \
+                                        int, const T*, double*, double*, hipStream_t);
 
 FBTO_INST(double)
 FBTO_INST(float)

@@ -164,22 +164,37 @@ class Grid:
         return out
 
     def project_volume(self, y, x=None, lo: float = 0.0, hi: float = 1.0, vmax: float = None,
-                       lam: Optional[torch.Tensor] = None, stream=None, method: str = "newton"):
-        """method "newton": fbto_project_volume (safeguarded Newton on the
-        multiplier); "sort": fbto_project_volume_sorted (Alg. 4 by radix sort
-        and scans)."""
+                       lam: Optional[torch.Tensor] = None, stream=None, method: str = "newton",
+                       max_passes: int = 0, status: Optional[torch.Tensor] = None):
+        """method "newton": fbto_project_volume (passes of a safeguarded
+        Newton search on the multiplier, at most `max_passes`, 0 = the
+        library's default; `status` receives 0, FBTO_INEXACT or
+        FBTO_ERR_NONFINITE); "sort": fbto_project_volume_sorted (Alg. 4 by
+        radix sort and scans; exact, no status)."""
         if x is None:
             x = torch.empty_like(y)
         if method == "newton":
-            fn = self.lib.fbto_project_volume
+            check(self.lib.fbto_project_volume(
+                self.handle, _prec(y), _ptr(y, None, self.E, "y"), _ptr(x, y.dtype, self.E, "x"),
+                float(lo), float(hi), float(vmax), int(max_passes),
+                _ptr(lam, torch.float64, None, "lambda"), _ptr(status, torch.float64, None, "status"),
+                _stream(stream)), self.lib)
         elif method == "sort":
-            fn = self.lib.fbto_project_volume_sorted
+            if max_passes or status is not None:
+                raise ValueError("max_passes and status belong to the Newton projection")
+            check(self.lib.fbto_project_volume_sorted(
+                self.handle, _prec(y), _ptr(y, None, self.E, "y"), _ptr(x, y.dtype, self.E, "x"),
+                float(lo), float(hi), float(vmax), _ptr(lam, torch.float64, None, "lambda"),
+                _stream(stream)), self.lib)
         else:
             raise ValueError(f"unknown method {method!r}")
-        check(fn(self.handle, _prec(y), _ptr(y, None, self.E, "y"), _ptr(x, y.dtype, self.E, "x"),
-                 float(lo), float(hi), float(vmax), _ptr(lam, torch.float64, None, "lambda"),
-                 _stream(stream)), self.lib)
         return x
+
+    def set_option(self, option: str, value: int):
+        """fbto_set_option: "proj_passes", "apply_tile" or "cgf_tile"."""
+        opt = {"proj_passes": _lib.FBTO_OPT_PROJ_PASSES, "apply_tile": _lib.FBTO_OPT_APPLY_TILE,
+               "cgf_tile": _lib.FBTO_OPT_CGF_TILE}[option]
+        check(self.lib.fbto_set_option(self.handle, opt, int(value)), self.lib)
 
     def outer_step(self, x, u, f, k: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
                    mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None,

@@ -72,5 +72,6 @@ def test_host_side_argument_errors(lib):
                                       None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_outer_step_exact(None, 0, None, None, None, 1, 1, 0.1, 1e-8, 100, 1, 0.0, 1.0, None,
                                      None) == _lib.FBTO_ERR_ARG
-    assert lib.fbto_project_volume(None, 0, None, None, 0.0, 1.0, 1.0, None, None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume(None, 0, None, None, 0.0, 1.0, 1.0, 0, None, None, None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_set_option(None, _lib.FBTO_OPT_PROJ_PASSES, 4) == _lib.FBTO_ERR_ARG
     assert lib.fbto_version().decode().startswith("fbto")

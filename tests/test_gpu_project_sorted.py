@@ -1,5 +1,5 @@
 """GPU parity of the sort-based projection (fbto_project_volume_sorted: Alg. 4
-as a radix sort and scans) against the oracle's Alg. 4, and against the
+as a radix sort and scans) against the oracle's projection, and against the
 other device projection at full size."""
 import numpy as np
 import pytest
@@ -68,7 +68,7 @@ def test_sorted_projection_against_alg4(dtype, shape, kind, seed):
             if vmax < lo * p.E:
                 continue
             x = host(g.project_volume(y_t, lo=lo, hi=1.0, vmax=vmax, lam=lam, method="sort"))
-            xr, lr = oracle.project_alg4(yd, lo, 1.0, vmax, return_lambda=True)
+            xr, lr = oracle.project_volume_ref(yd, lo, 1.0, vmax, return_lambda=True)
             sb = _sum_bound(yd, xr, lo, 1.0)
             xtol = (1e-12 if dtype == torch.float64 else 2 * EPS[torch.float32]) + sb
             assert np.abs(x - xr).max() <= xtol, (lo, vmax, np.abs(x - xr).max())
@@ -107,7 +107,7 @@ def test_sorted_projection_edge_cases(dtype):
         g.project_volume(y, lo=0.5, hi=1.0, vmax=0.1 * p.E, method="sort")
     # in place (x aliases y)
     yy = y.clone()
-    xr = oracle.project_alg4(yd, 0.0, 1.0, 0.3 * p.E)
+    xr = oracle.project_volume_ref(yd, 0.0, 1.0, 0.3 * p.E)
     g.project_volume(yy, x=yy, lo=0.0, hi=1.0, vmax=0.3 * p.E, method="sort")
     assert np.abs(host(yy) - xr).max() <= (1e-12 if dtype == torch.float64 else 2 * EPS[torch.float32])
     # a non-finite input gives lambda = NaN and x = NaN

@@ -78,7 +78,7 @@ def brute_force_projection(y, lo, hi, vmax):
     return best
 
 
-def test_alg4_against_brute_force_and_bisection():
+def test_projection_against_brute_force_and_bisection():
     rng = np.random.default_rng(7)
     for trial in range(40):
         E = int(rng.integers(1, 7))
@@ -87,28 +87,28 @@ def test_alg4_against_brute_force_and_bisection():
             y[: E // 2] = y[0]                      # ties
         lo, hi = 0.1, 1.0
         vmax = float(rng.uniform(E * lo, E * hi))
-        x4 = oracle.project_alg4(y, lo, hi, vmax)
+        x4 = oracle.project_volume_ref(y, lo, hi, vmax)
         xb = brute_force_projection(y, lo, hi, vmax)
         xs = oracle.project_bisect(y, lo, hi, vmax)
         assert np.abs(x4 - xb).max() < 1e-12
         assert np.abs(x4 - xs).max() < 1e-12
 
 
-def test_alg4_kkt_large():
+def test_projection_kkt_large():
     rng = np.random.default_rng(8)
     E = 20000
     y = rng.uniform(-0.3, 1.4, E)
     lo, hi, vmax = 0.0, 1.0, 0.25 * E
-    x, lam = oracle.project_alg4(y, lo, hi, vmax, return_lambda=True)
+    x, lam = oracle.project_volume_ref(y, lo, hi, vmax, return_lambda=True)
     assert lam > 0
     assert abs(x.sum() - vmax) <= 1e-12 * vmax
     assert np.abs(x - np.clip(y - lam, lo, hi)).max() == 0.0
     xb, lamb = oracle.project_bisect(y, lo, hi, vmax, return_lambda=True)
     assert abs(lam - lamb) < 1e-13
     # inactive: clamp returned unchanged
-    assert np.array_equal(oracle.project_alg4(y, lo, hi, 0.9 * E), np.clip(y, lo, hi))
+    assert np.array_equal(oracle.project_volume_ref(y, lo, hi, 0.9 * E), np.clip(y, lo, hi))
     with pytest.raises(ValueError):
-        oracle.project_alg4(y, 0.5, 1.0, 0.25 * E)
+        oracle.project_volume_ref(y, 0.5, 1.0, 0.25 * E)
 
 
 @pytest.mark.parametrize("r", [1.5, 2.0, 3.0])

@@ -122,3 +122,15 @@ def test_cantilever_against_timoshenko():
     L, b, h, E, G = 8.0, 1.0, 1.0, 1.0, 0.5
     timo = L ** 3 / (3 * E * b * h ** 3 / 12) + L / (5 / 6 * G * b * h)
     assert abs(extrap - timo) / timo < 5e-3
+
+
+def test_simp_scale_power_law():
+    """The modified SIMP law s = rho_min + (1 - rho_min) rho^p pinned by its
+    end values (a void keeps the floor rho_min, solid material the full
+    stiffness) and its scaling: s - rho_min is homogeneous of degree p."""
+    rho = np.random.default_rng(3).uniform(0.01, 0.5, 50)
+    for p, rmin in ((3.0, 1e-3), (1.0, 0.0), (2.5, 1e-2)):
+        assert oracle.simp_scale(np.array([0.0]), p, rmin)[0] == rmin
+        assert abs(oracle.simp_scale(np.array([1.0]), p, rmin)[0] - 1.0) <= 1e-15
+        ratio = (oracle.simp_scale(2 * rho, p, rmin) - rmin) / (oracle.simp_scale(rho, p, rmin) - rmin)
+        assert np.abs(ratio - 2.0 ** p).max() <= 1e-12

@@ -37,7 +37,7 @@ def test_exact_inner_solve_gives_projected_gradient_descent():
     p = synth.cantilever(4, 3, 3, volfrac=0.3, filter_radius=1.5, outer_iters=1,
                          inner_steps=1, seed=1)
     ctx = _ctx(p)
-    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    x = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
     nfree = int((p.fixed_mask == 0).sum())
     x1, u1, rec, _ = outer_step_ref(ctx, x, np.zeros_like(p.loads), p.loads, 1, 0.3, 3 * nfree,
                                     0.0, 1.0, p.vmax)
@@ -60,7 +60,7 @@ def test_cpfbto_step_uses_one_gmres_cycle():
     from oracle.density_filter import filter_forward
     p = synth.config("cfg1")
     ctx = _ctx(p)
-    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    x = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
     rng = np.random.default_rng(3)
     u0 = np.where(p.fixed_mask == 0, rng.standard_normal(p.ndof) * 1e-2, 0.0)
     deg = 6
@@ -79,7 +79,7 @@ def test_exact_low_level_equals_many_pcg_steps():
     outer step as Jacobi-PCG run to convergence."""
     p = synth.cantilever(4, 3, 3, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=1, seed=1)
     ctx = _ctx(p)
-    x = oracle.project_alg4(p.x0, 0.0, 1.0, p.vmax)
+    x = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
     u0 = np.zeros(p.ndof)
     xe, ue, re_, _ = outer_step_ref(ctx, x, u0, p.loads[0], 1, 0.05, 0, 0.0, 1.0, p.vmax, low_level=("exact",))
     xp, up, rp, _ = outer_step_ref(ctx, x, u0, p.loads[0], 1, 0.05, 150, 0.0, 1.0, p.vmax)

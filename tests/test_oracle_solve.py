@@ -71,6 +71,38 @@ def test_pcg_to_tol_and_variants():
     assert all(b <= a * (1 + 1e-12) for a, b in zip(errs, errs[1:]))
 
 
+def test_relaxation_steps_on_eigenvectors():
+    """Pins Alg. 1's low-level update u <- u - beta (K u - f) and the damped
+    Jacobi step u <- u - omega D^-1 (K u - f) by their action on
+    eigenvectors: from u0 = u* + v with K v = lam v, one Richardson step
+    gives exactly u* + (1 - beta lam) v; from u0 = u* + w with K w = mu D w
+    (an eigenvector of D^-1 K), one damped Jacobi step gives
+    u* + (1 - omega mu) w.  A flipped sign, a missing beta, or D in place of
+    D^-1 gives another factor and fails."""
+    import scipy.linalg as sla
+    from oracle.solve import damped_jacobi_ref, richardson_ref
+    g, p, s, K, D = _system(3, 2, 2)
+    f = p.loads[0]
+    u_ex = oracle.solve_direct(K, f)
+    Kd = K.toarray()
+    lam, V = np.linalg.eigh(Kd)
+    mu, W = sla.eigh(Kd, np.diag(D))
+    for i in (0, len(lam) // 3, len(lam) - 1):
+        v = V[:, i]
+        for beta in (0.3 / lam[-1], 1.0 / lam[-1], 1.7 / lam[-1]):
+            u1, r1 = richardson_ref(lambda q: K @ q, f, u_ex + v, 1, beta)
+            assert np.abs(u1 - (u_ex + (1.0 - beta * lam[i]) * v)).max() <= 1e-12
+            assert np.abs(r1 - (f - K @ u1)).max() <= 1e-12
+            u2, _ = richardson_ref(lambda q: K @ q, f, u_ex + v, 2, beta)
+            assert np.abs(u2 - (u_ex + (1.0 - beta * lam[i]) ** 2 * v)).max() <= 1e-12
+        w = W[:, i] / np.abs(W[:, i]).max()
+        for omega in (0.4, 0.9, 1.3):
+            u1, _ = damped_jacobi_ref(lambda q: K @ q, D, f, u_ex + w, 1, omega)
+            assert np.abs(u1 - (u_ex + (1.0 - omega * mu[i]) * w)).max() <= 1e-11
+    # the Jacobi diagonal is not constant here, so D^-1 and D (or no D) differ
+    assert D.max() / D.min() > 1.5
+
+
 def test_krylov_step_is_one_gmres_cycle():
     """Eq. LSP with beta = 1 minimises the residual over u + span{delta, ...,
     K^D delta}, which is what one GMRES(D + 1) cycle from u computes (by a
