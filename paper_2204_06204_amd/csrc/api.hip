@@ -93,7 +93,11 @@ void modal_coefficients(double young, double poisson, Modal<double>& km, double&
   ke_diag = (lam + 4.0 * mu) / 9.0;
 }
 
-ProjWs proj_ws(fbto_grid_s* g) { return ProjWs{g->partials, g->max_partials, g->sc}; }
+// The projection's partial arrays are the grid's slots P_S0 .. P_DX.
+ProjWs proj_ws(fbto_grid_s* g) {
+  return ProjWs{g->partials + (size_t)P_S0 * 4 * g->max_partials, (int64_t)4 * g->max_partials, g->max_partials,
+                g->sc};
+}
 
 fbto_status_t check_grid(fbto_grid_t g) {
   if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");

@@ -258,16 +258,31 @@ size_t sort_ws_layout(int64_t E, SortWs* W);
 template <typename T>
 hipError_t launch_project_sorted(fbto_grid_s* g, const T* y, T* x, double lo, double hi, double vmax,
                                  double* lam_out, hipStream_t st);
-// Workspace of the volume projection: per-block partial slots (P_COUNT x 4 x
-// maxp doubles) and the search state in a Scalars record.
+// Workspace of the volume projection: kProjSlots arrays of maxp per-block
+// FP64 partials (array i at base + i * stride) and the search state in a
+// Scalars record.  On a grid handle the arrays are the partial slots
+// P_S0 .. P_DX (stride 4 maxp); a caller-free workspace packs them.
+enum ProjSlot {
+  L_S0, L_YMAX, L_NACT,   // seed: sum clamp(y), max y, #interior
+  L_E0,                   // evaluation sets: L_E0 + 11 q .. L_E0 + 11 q + 10, q = 0, 1
+  L_VOL = L_E0 + 22,      // sum x_new
+  L_DX,                   // max |x_new - x_old|
+  kProjSlots
+};
+static_assert(P_YMAX == P_S0 + L_YMAX && P_NACT == P_S0 + L_NACT && P_E0 == P_S0 + L_E0 &&
+                  P_VOL == P_S0 + L_VOL && P_DX == P_S0 + L_DX,
+              "the projection's slots are consecutive grid partial slots");
 struct ProjWs {
-  double* P;
+  double* base;
+  int64_t stride;
   int maxp;
   Scalars* sc;
 };
 // Projection of y onto {lo <= x <= hi, sum x <= vmax} with `passes` search
 // passes.  seeded: the seed partials (P_S0, P_YMAX, P_NACT) were left by
-// k_step.  lam_out, status_out: device FP64 scalars, may be NULL.
+// k_step and the search starts from the multiplier of the previous
+// projection; otherwise the seed pass runs and the search starts cold.
+// lam_out, status_out: device FP64 scalars, may be NULL.
 template <typename T>
 hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
                           int seeded, int passes, const T* x_old, double* lam_out, double* status_out,

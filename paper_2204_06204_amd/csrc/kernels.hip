@@ -2155,9 +2155,14 @@ __global__ void __launch_bounds__(kVecBlock)
   write_parts<3, 0x2u>(v, dst, blockIdx.x);
 }
 
+__device__ __forceinline__ double* lslot(const ProjWs& W, int i) { return W.base + i * W.stride; }
+
+// Seed of a cold projection: sum clamp(y), max y and the interior count;
+// the warm start of the search is cleared.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_proj_init(int64_t E, const T* y, double lo, double hi, double* P, int maxp) {
+    k_proj_init(int64_t E, const T* y, double lo, double hi, ProjWs W) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) W.sc->lam_prev = 0.0;
   double v[3] = {0.0, -INFINITY, 0.0};
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -2166,7 +2171,7 @@ __global__ void __launch_bounds__(kVecBlock)
     v[1] = fmax(v[1], yd);
     v[2] += (yd > lo && yd < hi) ? 1.0 : 0.0;
   }
-  double* dst[3] = {pslot(P, P_S0, 0, maxp), pslot(P, P_YMAX, 0, maxp), pslot(P, P_NACT, 0, maxp)};
+  double* dst[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
   write_parts<3, 0x2u>(v, dst, blockIdx.x);
 }
 
@@ -2177,19 +2182,19 @@ struct ProjDecision {
 };
 
 // First slot of the evaluation set q of the projection passes.
-__host__ __device__ constexpr int proj_set(int q) { return P_E0 + 11 * (q & 1); }
+__host__ __device__ constexpr int proj_set(int q) { return L_E0 + 11 * (q & 1); }
 // pass t reads set t and writes set t + 1: two disjoint runs of 11 slots
-static_assert(proj_set(0) + 11 <= proj_set(1) && proj_set(1) + 11 <= P_VOL, "projection slot sets overlap");
+static_assert(proj_set(0) + 11 <= proj_set(1) && proj_set(1) + 11 <= L_VOL, "projection slot sets overlap");
 
 // The search state after a pass (identical in every block).  `first`: the
 // partials are the seed (sum clamp(y), max y, #interior); otherwise the
 // evaluation at `lam` left in the slots of set `set`.
-__device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool first, int set, double lo, double hi,
+__device__ ProjDecision proj_decide(const ProjWs& W, int nb, bool first, int set, double lo, double hi,
                                     double vmax, double lam_prev, double lam, double a, double b) {
   ProjDecision d{};
   if (first) {
     double v[3];
-    const double* src[3] = {pslot(P, P_S0, 0, maxp), pslot(P, P_YMAX, 0, maxp), pslot(P, P_NACT, 0, maxp)};
+    const double* src[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
     const int cnt[3] = {nb, nb, nb};
     reduce_parts<3, 0x2u>(v, src, cnt);
     const double S0 = v[0], ymax = v[1], nact0 = v[2];
@@ -2219,7 +2224,7 @@ __device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool firs
   int cnt[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) {
-    src[i] = pslot(P, proj_set(set) + i, 0, maxp);
+    src[i] = lslot(W, proj_set(set) + i);
     cnt[i] = nb;
   }
   reduce_parts<11, 0x600u>(v, src, cnt);
@@ -2276,8 +2281,8 @@ __device__ ProjDecision proj_decide(const double* P, int maxp, int nb, bool firs
 // partials that blocks of the same pass have already overwritten.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, double* P, int maxp,
-                int nb, Scalars* sc) {
+    k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, ProjWs W, int nb) {
+  Scalars* sc = W.sc;
   const double* in = sc->ps[pass & 1];
   double* out = sc->ps[(pass + 1) & 1];
   if (pass > 0 && in[3] != 0.0) {            // already solved: carry the state forward
@@ -2286,7 +2291,7 @@ __global__ void __launch_bounds__(kVecBlock)
     return;
   }
   const ProjDecision d =
-      proj_decide(P, maxp, nb, pass == 0, pass, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+      proj_decide(W, nb, pass == 0, pass, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     out[0] = d.lam;
     out[1] = d.a;
@@ -2319,7 +2324,7 @@ __global__ void __launch_bounds__(kVecBlock)
   }
   double* dst[11];
 #pragma unroll
-  for (int i = 0; i < 11; ++i) dst[i] = pslot(P, proj_set(pass + 1) + i, 0, maxp);
+  for (int i = 0; i < 11; ++i) dst[i] = lslot(W, proj_set(pass + 1) + i);
   write_parts<11, 0x600u>(v, dst, blockIdx.x);
 }
 
@@ -2330,14 +2335,15 @@ __global__ void __launch_bounds__(kVecBlock)
 // status (also into *status_out) and lambda.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_proj_final(int64_t E, const T* y, T* x, double lo, double hi, double vmax, const T* x_old, double* P,
-                 int maxp, int nb, int passes, Scalars* sc, double* lam_out, double* status_out) {
+    k_proj_final(int64_t E, const T* y, T* x, double lo, double hi, double vmax, const T* x_old, ProjWs W, int nb,
+                 int passes, double* lam_out, double* status_out) {
+  Scalars* sc = W.sc;
   const double* in = sc->ps[passes & 1];
   double lam = in[0];
   bool bad = false, unfinished = false;
   if (in[3] == 0.0) {  // pass budget spent: decide from the last evaluation
     const ProjDecision d =
-        proj_decide(P, maxp, nb, false, passes, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+        proj_decide(W, nb, false, passes, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
     lam = d.done ? d.lam : d.b;
     bad = d.bad;
     unfinished = !d.done;
@@ -2360,7 +2366,7 @@ __global__ void __launch_bounds__(kVecBlock)
     x[e] = xe;
     v[0] += (double)xe;
   }
-  double* dst[2] = {pslot(P, P_VOL, 0, maxp), pslot(P, P_DX, 0, maxp)};
+  double* dst[2] = {lslot(W, L_VOL), lslot(W, L_DX)};
   write_parts<2, 0x2u>(v, dst, blockIdx.x);
 }
 
@@ -2380,14 +2386,13 @@ hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double l
   const int nb = vec_blocks(E);
   if (nb > W.maxp) return hipErrorInvalidValue;
   if (!seeded) {
-    hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, W.P, W.maxp);
+    hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, W);
   }
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W.P, W.maxp,
-                       nb, W.sc);
+    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W, nb);
   }
-  hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W.P,
-                     W.maxp, nb, passes, W.sc, lam_out, status_out);
+  hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W, nb,
+                     passes, lam_out, status_out);
   return hipGetLastError();
 }
 
