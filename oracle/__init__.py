@@ -28,7 +28,7 @@ from .sensitivity import (element_energy, element_bilinear, element_bilinear_at,
 from .density_filter import (cone_filter_matrix, filter_forward, filter_transpose, filter_weight_sums_at,
                              filter_forward_at, filter_transpose_at)
 from .projection import project_volume_ref, project_bisect, box_clamp
-from .outer import outer_step_ref, run_outer_ref, step_size
+from .outer import outer_step_ref, run_outer_ref, step_size, true_objective, relative_projection_error
 
 __all__ = [
     "material_lame", "element_stiffness", "KE_DIAG", "Grid",
@@ -38,5 +38,5 @@ __all__ = [
     "cone_filter_matrix", "filter_forward", "filter_transpose", "filter_weight_sums_at", "filter_forward_at",
     "filter_transpose_at",
     "project_volume_ref", "project_bisect", "box_clamp",
-    "outer_step_ref", "run_outer_ref", "step_size",
+    "outer_step_ref", "run_outer_ref", "step_size", "true_objective", "relative_projection_error",
 ]

@@ -132,3 +132,30 @@ def default_alpha0(ctx: OuterContext, x_init, f, inner_steps, lo, hi, vmax,
     _, _, _, g_x = outer_step_ref(ctx, x, np.zeros_like(F), F, 1, 0.0, inner_steps, lo, hi,
                                   vmax, mean_project)
     return max_move / float(np.abs(0.5 * g_x).max())
+
+
+def true_objective(ctx: OuterContext, x, f):
+    """The objective at a design with the low-level problem solved exactly
+    (Sec. 3, Eq. opt; Sec. 5 tracks it as l(v_k)):
+        l(x) = 1/2 sum_r f_r^T K(rho(x))^-1 f_r   (half the compliance),
+    and its gradient with respect to the design, through the filter:
+        grad l = 1/2 C^T(-ds_e u_e^T KE u_e)  with u_r = K^-1 f_r.
+    Returns (l, grad_l, U) from direct sparse solves."""
+    g = ctx.grid
+    rho = filter_forward(ctx.H, ctx.Hs, x)
+    s = simp_scale(rho, ctx.penal, ctx.rho_min)
+    ds = simp_dscale(rho, ctx.penal, ctx.rho_min)
+    K = assemble_K(g, s, ctx.fixed, ctx.springs, ctx.KE)
+    F = np.atleast_2d(f)
+    U = np.stack([solve_direct(K, F[r]) for r in range(F.shape[0])])
+    l = 0.5 * float(sum(F[r] @ U[r] for r in range(F.shape[0])))
+    grad = 0.5 * filter_transpose(ctx.H, ctx.Hs, -ds * element_energy(g, U, ctx.fixed, ctx.KE))
+    return l, grad, U
+
+
+def relative_projection_error(x, grad, alpha, lo, hi, vmax):
+    """Delta^v = || Proj_X(x - alpha grad) - x ||^2 / alpha^2, the high-level
+    optimality measure of Sec. 4 (defined after Thm. 1): zero exactly when x
+    satisfies the first-order conditions on X."""
+    z = project_volume_ref(np.asarray(x, dtype=np.float64) - alpha * np.asarray(grad), lo, hi, vmax)
+    return float(((z - x) ** 2).sum()) / (alpha * alpha)

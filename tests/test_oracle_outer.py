@@ -86,3 +86,42 @@ def test_exact_low_level_equals_many_pcg_steps():
     assert np.abs(ue - up).max() <= 1e-9 * np.abs(ue).max()
     assert np.abs(xe - xp).max() <= 1e-10
     assert abs(re_.compliance - rp.compliance) <= 1e-10 * re_.compliance
+
+
+def test_relative_projection_error_pins():
+    """Delta^v (Sec. 4, after Thm. 1) is 0 at a first-order point of X;
+    equals |g|^2 when the step stays inside the box and below the volume
+    bound (the projection is the identity); equals |g - mean g|^2 when the
+    volume bound is active and the box is not hit (the projection only
+    shifts by a constant)."""
+    from oracle import relative_projection_error as dv
+    # a KKT point: x_0 at hi with -g_0 pushing out, x_1 at lo with -g_1
+    # pushing below, interior entries with equal gradient = -(the multiplier)
+    x = np.array([1.0, 0.0, 0.5, 0.5])
+    g = np.array([-3.0, 2.0, -0.7, -0.7])
+    for alpha in (1e-3, 0.1, 1.0, 10.0):
+        assert dv(x, g, alpha, 0.0, 1.0, 2.0) * alpha ** 2 <= 1e-30   # |z - x| at rounding level
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0.3, 0.7, 50)
+    g = rng.normal(0.0, 1.0, 50)
+    alpha = 1e-3
+    assert abs(dv(x, g, alpha, 0.0, 1.0, x.sum() + 1.0) - (g ** 2).sum()) <= 1e-9 * (g ** 2).sum()
+    gp = g - g.mean()
+    assert abs(dv(x, g, alpha, 0.0, 1.0, x.sum()) - (gp ** 2).sum()) <= 1e-9 * (gp ** 2).sum()
+
+
+def test_true_objective_gradient_matches_fd():
+    """The exact objective's gradient (through the filter) against central
+    differences of direct solves, and l = compliance / 2."""
+    p = synth.cantilever(4, 3, 2, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=1, seed=4)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    x = synth.uniform_density(p.E, 9)
+    l, grad, U = oracle.true_objective(ctx, x, p.loads)
+    assert abs(2 * l - float(p.loads[0] @ U[0])) <= 1e-14 * abs(l)
+    h = 1e-5
+    for j in range(p.E):
+        xp, xm = x.copy(), x.copy()
+        xp[j] += h
+        xm[j] -= h
+        fd = (oracle.true_objective(ctx, xp, p.loads)[0] - oracle.true_objective(ctx, xm, p.loads)[0]) / (2 * h)
+        assert abs(fd - grad[j]) <= 1e-6 * np.abs(grad).max()
