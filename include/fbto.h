@@ -287,6 +287,28 @@ fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, v
                                      int32_t degree, double beta, int32_t mean_project,
                                      double lo, double vmax, double* info, void* stream);
 
+/* The projection of fbto_project_volume for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  No grid handle: n_elem is the length
+ * of y and x.  It calls no hipMalloc, hipFree or allocating routine.
+ * Its workspace -- the per-block FP64 partials of the passes and the search
+ * state, 222,016 bytes -- is a static device array that each GPU the
+ * library runs on holds until the process ends; the first call on a device
+ * looks up its address there.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, or two threads) race
+ * and give wrong results; calls ordered on one stream do not interfere.
+ * Each call starts cold (no warm start from an earlier multiplier), so the
+ * result equals fbto_project_volume's for the same y, bit for bit.
+ *   n_elem  1 .. FBTO_NOALLOC_MAX_ELEMS; larger values are rejected with
+ *           FBTO_ERR_ARG.
+ * y, x, lo, hi, vmax, max_passes, lambda, status, stream, the errors and
+ * the asynchrony are those of fbto_project_volume. */
+#define FBTO_NOALLOC_MAX_ELEMS 2147483647LL
+fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, const void* y,
+                                          void* x, double lo, double hi, double vmax,
+                                          int32_t max_passes, double* lambda, double* status,
+                                          void* stream);
+
 /* Tuning options of a grid handle (fbto_set_option).  They change how the
  * work is laid out or how long a search may run, not what is computed.
  *   FBTO_OPT_PROJ_PASSES  pass budget of the volume projection inside

@@ -18,6 +18,7 @@ FBTO_OPT_PROJ_PASSES, FBTO_OPT_APPLY_TILE, FBTO_OPT_CGF_TILE = 0, 1, 2
 FBTO_F64, FBTO_F32 = 0, 1
 FBTO_PCG_JACOBI, FBTO_RICHARDSON, FBTO_DAMPED_JACOBI, FBTO_KRYLOV = 0, 1, 2, 3
 FBTO_SOLVE_INFO = 8
+FBTO_NOALLOC_MAX_ELEMS = 2147483647
 FBTO_OUTER_INFO = 8
 SI = dict(rnorm2=0, rnormi=1, fnorm2=2, steps=3, status=4)
 OI = dict(compliance=0, dx_inf=1, r_inf=2, lam=3, volume=4, rrel=5, status=6, grad_mean=7)
@@ -51,6 +52,8 @@ _SIGS = {
                                         C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_krylov": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                          C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
+    "fbto_project_volume_noalloc": (C.c_int, [C.c_int, C.c_int64, _VP, _VP, C.c_double, C.c_double,
+                                              C.c_double, C.c_int32, _VP, _VP, _VP]),
     "fbto_set_option": (C.c_int, [_VP, C.c_int, C.c_int64]),
     "fbto_last_error": (C.c_char_p, []),
     "fbto_version": (C.c_char_p, []),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -413,6 +414,40 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
                             nullptr, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
   HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
+  return FBTO_OK;
+}
+
+// ---- allocation-free projection --------------------------------------------
+// fbto_project_volume_noalloc keeps the projection's per-block partials
+// (kProjSlots arrays of kMaxVecBlocks FP64 values) and its search state (one
+// Scalars record) in this array.  Each device holds its own copy until the
+// process ends; its address there is looked up once per device, and host
+// code uses only that address (the array's name is a host-side stand-in).
+constexpr size_t kNoAllocPartDoubles = (size_t)kProjSlots * kMaxVecBlocks;
+constexpr size_t kNoAllocDoubles = kNoAllocPartDoubles + (sizeof(Scalars) + sizeof(double) - 1) / sizeof(double);
+constexpr int kNoAllocMaxDevices = 64;
+static_assert(sizeof(Scalars) % sizeof(double) == 0, "the search state is a record of doubles");
+
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// The scratch address on the current device (looked up on its first use).
+fbto_status_t scratch_on_current_device(double** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocMaxDevices)
+    return fail(FBTO_ERR_UNSUPPORTED, "device %d: the scratch table holds devices 0 .. %d", dev,
+                kNoAllocMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    double* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(FBTO_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
   return FBTO_OK;
 }
 
@@ -887,6 +922,41 @@ fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, v
                          info, st, degree, beta);
   }
   if (s) return s;
+  return ok();
+}
+
+fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, const void* y, void* x, double lo,
+                                          double hi, double vmax, int32_t max_passes, double* lambda,
+                                          double* status, void* stream) {
+  if (check_prec(prec)) return FBTO_ERR_ARG;
+  if (n_elem < 1 || n_elem > FBTO_NOALLOC_MAX_ELEMS)
+    return fail(FBTO_ERR_ARG, "n_elem = %lld outside [1, %lld]: the allocation-free projection serves at most "
+                "%lld elements", (long long)n_elem, (long long)FBTO_NOALLOC_MAX_ELEMS,
+                (long long)FBTO_NOALLOC_MAX_ELEMS);
+  if (!y || !x) return fail(FBTO_ERR_ARG, "y and x must be non-NULL");
+  if (!(std::isfinite(lo) && std::isfinite(hi) && lo <= hi)) return fail(FBTO_ERR_ARG, "need finite lo <= hi");
+  if (!std::isfinite(vmax)) return fail(FBTO_ERR_ARG, "vmax must be finite");
+  if (max_passes < 0 || max_passes > kProjMaxPasses)
+    return fail(FBTO_ERR_ARG, "max_passes = %d outside [0, %d]", (int)max_passes, kProjMaxPasses);
+  if (vmax < lo * (double)n_elem)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g: the feasible set is empty", vmax,
+                lo * (double)n_elem);
+  const int nb = vec_blocks(n_elem);
+  if (nb > kMaxVecBlocks)
+    return fail(FBTO_ERR_ARG, "%d partial blocks exceed the scratch's %d", nb, kMaxVecBlocks);
+  double* base = nullptr;
+  if (fbto_status_t s = scratch_on_current_device(&base)) return s;
+  const ProjWs W{base, (int64_t)kMaxVecBlocks, kMaxVecBlocks, reinterpret_cast<Scalars*>(base + kNoAllocPartDoubles)};
+  const int passes = max_passes == 0 ? 8 : max_passes;
+  hipStream_t st = (hipStream_t)stream;
+  // cold start: k_proj_init writes the seed partials and clears the warm
+  // start; every later slot is written before it is read
+  if (prec == FBTO_F64)
+    HIP_TRY(launch_project<double>(W, n_elem, (const double*)y, (double*)x, lo, hi, vmax, 0, passes, nullptr,
+                                   lambda, status, st));
+  else
+    HIP_TRY(launch_project<float>(W, n_elem, (const float*)y, (float*)x, lo, hi, vmax, 0, passes, nullptr, lambda,
+                                  status, st));
   return ok();
 }
 

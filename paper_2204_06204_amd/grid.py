@@ -221,3 +221,22 @@ class Grid:
 
 
 __all__ = ["Grid", "FbtoError"]
+
+
+def project_volume_noalloc(y: torch.Tensor, x: Optional[torch.Tensor] = None, lo: float = 0.0,
+                           hi: float = 1.0, vmax: float = None, max_passes: int = 0,
+                           lam: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+                           stream=None) -> torch.Tensor:
+    """fbto_project_volume_noalloc: the projection of Grid.project_volume
+    (method "newton") without a grid handle and without device allocation
+    in the library; its workspace is a static device array shared by every
+    call on the GPU (calls that overlap on one GPU race)."""
+    lib = _lib.load()
+    if x is None:
+        x = torch.empty_like(y)
+    n = y.numel()
+    check(lib.fbto_project_volume_noalloc(
+        _prec(y), n, _ptr(y, None, n, "y"), _ptr(x, y.dtype, n, "x"), float(lo), float(hi), float(vmax),
+        int(max_passes), _ptr(lam, torch.float64, None, "lambda"), _ptr(status, torch.float64, None, "status"),
+        _stream(stream)), lib)
+    return x

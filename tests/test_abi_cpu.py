@@ -75,3 +75,24 @@ def test_host_side_argument_errors(lib):
     assert lib.fbto_project_volume(None, 0, None, None, 0.0, 1.0, 1.0, 0, None, None, None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_set_option(None, _lib.FBTO_OPT_PROJ_PASSES, 4) == _lib.FBTO_ERR_ARG
     assert lib.fbto_version().decode().startswith("fbto")
+
+
+def test_noalloc_projection_rejects_on_the_host(lib):
+    """The allocation-free projection checks its arguments before any HIP
+    call: sizes beyond its scratch's limit, empty inputs, bad budgets."""
+    from paper_2204_06204_amd import _lib
+    fake = C.c_void_p(0x1000)  # never dereferenced: every call below fails on the host
+    big = _lib.FBTO_NOALLOC_MAX_ELEMS + 1
+    assert lib.fbto_project_volume_noalloc(0, big, fake, fake, 0.0, 1.0, 1.0, 0, None, None,
+                                           None) == _lib.FBTO_ERR_ARG
+    assert "at most" in lib.fbto_last_error().decode()
+    assert lib.fbto_project_volume_noalloc(0, 0, fake, fake, 0.0, 1.0, 1.0, 0, None, None,
+                                           None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume_noalloc(0, 10, None, fake, 0.0, 1.0, 1.0, 0, None, None,
+                                           None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume_noalloc(0, 10, fake, fake, 0.0, 1.0, 1.0, 65, None, None,
+                                           None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume_noalloc(7, 10, fake, fake, 0.0, 1.0, 1.0, 0, None, None,
+                                           None) == _lib.FBTO_ERR_ARG
+    assert lib.fbto_project_volume_noalloc(1, 10, fake, fake, 0.5, 1.0, 4.0, 0, None, None,
+                                           None) == _lib.FBTO_ERR_INFEASIBLE
