@@ -47,8 +47,9 @@ def assemble_K(grid: Grid, s, fixed_mask=None, springs=None, KE=None) -> sp.csr_
     KE = element_stiffness() if KE is None else KE
     s = np.asarray(s, dtype=np.float64)
     edof = grid.elem_dofs()
-    rows = np.repeat(edof, 24, axis=1).ravel()
-    cols = np.tile(edof, (1, 24)).ravel()
+    nloc = edof.shape[1]  # 24 (hex8) or 8 (Q4)
+    rows = np.repeat(edof, nloc, axis=1).ravel()
+    cols = np.tile(edof, (1, nloc)).ravel()
     vals = (s[:, None, None] * KE[None, :, :]).ravel()
     K = sp.coo_matrix((vals, (rows, cols)), shape=(grid.ndof, grid.ndof)).tocsr()
     dof, k = _springs(springs)
@@ -94,22 +95,24 @@ def apply_K(grid: Grid, s, u, fixed_mask=None, springs=None, KE=None, chunk=1 <<
 def apply_K_rows(grid: Grid, s, u, nodes, fixed_mask=None, springs=None, KE=None):
     """Rows of K_bc u at the given nodes, each summed from its incident
     elements one by one (for sampled checks on grids too large to assemble).
-    Returns [len(nodes), 3] (single right-hand side)."""
+    Returns [len(nodes), d] (single right-hand side; d = 3, or 2 on a
+    plane grid)."""
     KE = element_stiffness() if KE is None else KE
+    d_n = getattr(grid, "dim", 3)
     s = np.asarray(s, dtype=np.float64)
     u = np.asarray(u, dtype=np.float64)
     free = None if fixed_mask is None else (np.asarray(fixed_mask) == 0)
     dof, k = _springs(springs)
     spring = dict(zip(dof.tolist(), k.tolist()))
-    out = np.zeros((len(nodes), 3))
+    out = np.zeros((len(nodes), d_n))
     for r, n in enumerate(nodes):
-        acc = np.zeros(3)
+        acc = np.zeros(d_n)
         for e, a in grid.node_elems(int(n)):
             edof = grid.elem_dofs([e])[0]
             ue = u[edof] if free is None else np.where(free[edof], u[edof], 0.0)
-            acc += s[e] * (KE[3 * a:3 * a + 3, :] @ ue)
-        for c in range(3):
-            d = 3 * int(n) + c
+            acc += s[e] * (KE[d_n * a:d_n * a + d_n, :] @ ue)
+        for c in range(d_n):
+            d = d_n * int(n) + c
             if d in spring and (free is None or free[d]):
                 acc[c] += spring[d] * u[d]
             if free is not None and not free[d]:

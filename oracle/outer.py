@@ -124,13 +124,14 @@ def run_outer_ref(ctx: OuterContext, x_init, f, iters, alpha0, inner_steps, lo, 
 
 
 def default_alpha0(ctx: OuterContext, x_init, f, inner_steps, lo, hi, vmax,
-                   max_move=0.2, mean_project=True):
+                   max_move=0.2, mean_project=True, low_level=None):
     """Step-size reading: alpha0 such that the first step moves no density
-    by more than `max_move`:  alpha0 = max_move / max|g_P(x_1) / 2|."""
+    by more than `max_move`:  alpha0 = max_move / max|g_P(x_1) / 2|
+    (low_level as in outer_step_ref)."""
     x = project_volume_ref(np.asarray(x_init, dtype=np.float64), lo, hi, vmax)
     F = np.atleast_2d(f)
     _, _, _, g_x = outer_step_ref(ctx, x, np.zeros_like(F), F, 1, 0.0, inner_steps, lo, hi,
-                                  vmax, mean_project)
+                                  vmax, mean_project, low_level)
     return max_move / float(np.abs(0.5 * g_x).max())
 
 

@@ -260,3 +260,86 @@ def small_cases() -> Sequence[Problem]:
                        inner_steps=5, seed=seed)
         out.append(p)
     return out
+
+
+# --------------------------------------------------------------------------
+# plane (2D) problems: the paper's own setting
+# --------------------------------------------------------------------------
+# Numbering on a plane grid: node n = i + (nx+1) * j, DOF 2*n + c
+# (c in {0: x, 1: y}), element e = ex + nx * ey, vectors [nrhs][2N].
+
+@dataclasses.dataclass
+class PlaneProblem:
+    """A plane-grid SIMP problem (Q4 elements, Gaussian filter)."""
+
+    name: str
+    nx: int
+    ny: int
+    volfrac: float
+    fixed_mask: np.ndarray            # uint8 [2N]
+    loads: np.ndarray                 # float64 [nrhs][2N]
+    x0: np.ndarray                    # float64 [E]
+    lo: float = 0.1                   # lower bound of the box (the paper's v_)
+    degree: int = 20                  # Krylov degree D of Alg. 3
+    beta: float = 1.0                 # step of the low-level update
+    filter_half: int = 3              # 7 x 7 window
+    filter_sigma: float = 1.4
+    young: float = 1.0
+    poisson: float = 0.3
+    penal: float = 3.0
+    rho_min: float = 0.0
+    note: str = ""
+
+    @property
+    def E(self) -> int:
+        return self.nx * self.ny
+
+    @property
+    def N(self) -> int:
+        return (self.nx + 1) * (self.ny + 1)
+
+    @property
+    def ndof(self) -> int:
+        return 2 * self.N
+
+    @property
+    def nrhs(self) -> int:
+        return int(self.loads.shape[0])
+
+    @property
+    def vmax(self) -> float:
+        return float(self.volfrac * self.E)
+
+
+def plane_cantilever(nx: int, ny: int, volfrac: float, *, name=None, note="") -> PlaneProblem:
+    """Plane cantilever: the x = 0 edge clamped (both DOFs), a unit -y load at
+    the free end's middle node (nx, ny // 2); initial design uniform at the
+    volume fraction."""
+    N = (nx + 1) * (ny + 1)
+    mask = np.zeros(2 * N, dtype=np.uint8)
+    for j in range(ny + 1):
+        mask[2 * (j * (nx + 1))] = mask[2 * (j * (nx + 1)) + 1] = 1
+    f = np.zeros((1, 2 * N))
+    f[0, 2 * (nx + (nx + 1) * (ny // 2)) + 1] = -1.0
+    return PlaneProblem(name=name or f"plane_cantilever_{nx}x{ny}", nx=nx, ny=ny, volfrac=volfrac,
+                        fixed_mask=mask, loads=f, x0=np.full(nx * ny, float(volfrac)), note=note)
+
+
+# Grid shapes and volume fractions of the paper's benchmark table (resolution
+# "a x b" read as a rows (y) by b columns (x)); the loads and supports of its
+# benchmarks exist only in its figures, so a cantilever stands in for each.
+PLANE_TABLE = (
+    ("teaser", 256, 128, 0.4), ("a", 576, 192, 0.3), ("b", 576, 192, 0.3), ("c", 384, 192, 0.3),
+    ("d", 240, 160, 0.4), ("e", 160, 160, 0.5), ("f", 384, 128, 0.5), ("g", 256, 128, 0.3),
+)
+
+
+def plane_config(name: str) -> PlaneProblem:
+    """A plane cantilever at one of the table's shapes ("plane_a" ...), or the
+    small parity case "plane_small" (48 x 16)."""
+    if name == "plane_small":
+        return plane_cantilever(48, 16, 0.4, name=name)
+    for key, nx, ny, vf in PLANE_TABLE:
+        if name == f"plane_{key}":
+            return plane_cantilever(nx, ny, vf, name=name, note=f"{ny} x {nx}, volume fraction {vf}")
+    raise KeyError(name)
