@@ -87,6 +87,25 @@ typedef struct fbto_grid_desc {
                              /* r <= 1 makes the filter the identity       */
 } fbto_grid_desc_t;
 
+/* Plane grid (the paper's own 2D setting): nx * ny unit-square bilinear
+ * quadrilaterals (Q4), plane stress, with the separable Gaussian density
+ * filter of the paper's experiments (Sec. 5: a 7 x 7 window, filter_half =
+ * 3).  1D weights g(d) = exp(-d^2 / (2 sigma^2)), |d| <= filter_half; the
+ * 2D weight H_ej = g(dx) g(dy) over element centres, truncated at the grid
+ * boundary and normalised by its row sum.  Numbering:
+ *   node n = i + (nx+1)*j, DOF 2*n + c (c = 0, 1 for x, y),
+ *   element e = ex + nx*ey, vectors [nrhs][2N]. */
+typedef struct fbto_grid2d_desc {
+  int32_t nx, ny;            /* elements per axis, each >= 1              */
+  int32_t max_rhs;           /* right-hand sides per call, 1..4            */
+  int32_t filter_half;       /* Gaussian window half-width, 0..8 (0: none) */
+  double young, poisson;     /* E > 0, -1 < nu < 0.5                       */
+  double penal;              /* SIMP exponent p >= 1                        */
+  double rho_min;            /* 0 <= rho_min < 1 (the paper's law: 0, with  */
+                             /* the box's lower bound lo > 0)               */
+  double filter_sigma;       /* sigma > 0 in element widths                 */
+} fbto_grid2d_desc_t;
+
 /* Slots of the FP64 info record written by fbto_inner_solve (per RHS,
  * FBTO_SOLVE_INFO doubles each) and by fbto_outer_step. */
 enum {
@@ -126,6 +145,18 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* desc,
                               const uint8_t* fixed_dof_mask,
                               int32_t n_springs, const int64_t* spring_dof,
                               const double* spring_k, fbto_grid_t* out);
+
+/* Create a plane-grid handle (fbto_grid2d_desc_t).  The handle serves the
+ * same calls as a voxel grid's -- fbto_apply_K, fbto_inner_solve (every
+ * method), fbto_solve_refined, fbto_sensitivity, fbto_filter, the
+ * projections and the three outer steps -- on [nrhs][2N] vectors; the CG
+ * steps run unfused in both precisions.
+ *   fixed_dof_mask  host, [2N] bytes, nonzero = DOF fixed (identity row and
+ *                   column, as on voxel grids).  May be NULL.  Plane grids
+ *                   take no springs.
+ * Errors: FBTO_ERR_ARG, FBTO_ERR_ALLOC, FBTO_ERR_HIP. */
+fbto_status_t fbto_setup_grid_2d(const fbto_grid2d_desc_t* desc, const uint8_t* fixed_dof_mask,
+                                 fbto_grid_t* out);
 
 /* Release the handle and its workspace (synchronises the device). */
 fbto_status_t fbto_destroy_grid(fbto_grid_t g);

@@ -30,9 +30,16 @@ class GridDesc(C.Structure):
                 ("rho_min", C.c_double), ("filter_radius", C.c_double)]
 
 
+class Grid2DDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("max_rhs", C.c_int32), ("filter_half", C.c_int32),
+                ("young", C.c_double), ("poisson", C.c_double), ("penal", C.c_double),
+                ("rho_min", C.c_double), ("filter_sigma", C.c_double)]
+
+
 _VP = C.c_void_p
 _SIGS = {
     "fbto_setup_grid": (C.c_int, [C.POINTER(GridDesc), _VP, C.c_int32, _VP, _VP, C.POINTER(_VP)]),
+    "fbto_setup_grid_2d": (C.c_int, [C.POINTER(Grid2DDesc), _VP, C.POINTER(_VP)]),
     "fbto_destroy_grid": (C.c_int, [_VP]),
     "fbto_grid_sizes": (C.c_int, [_VP, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "fbto_apply_K": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, _VP]),

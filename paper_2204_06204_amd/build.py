@@ -11,7 +11,7 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-SOURCES = ["csrc/kernels.hip", "csrc/project_sort.hip", "csrc/api.hip"]
+SOURCES = ["csrc/kernels.hip", "csrc/project_sort.hip", "csrc/plane.hip", "csrc/api.hip"]
 HEADERS = ["csrc/internal.h", "csrc/device.h"]
 OUT = os.path.join(PKG, "libfbto.so")
 

@@ -94,6 +94,40 @@ void modal_coefficients(double young, double poisson, Modal<double>& km, double&
   ke_diag = (lam + 4.0 * mu) / 9.0;
 }
 
+// Element stiffness of the unit-square Q4 in plane stress, by 2 x 2 Gauss
+// quadrature of B^T D B (exact for the bilinear element):
+//   D = E / (1 - nu^2) [[1, nu, 0], [nu, 1, 0], [0, 0, (1 - nu) / 2]],
+// strains (u_x,x, u_y,y, u_x,y + u_y,x); local DOF 2a + c, a = ax + 2 ay.
+void q4_plane_stress(double young, double poisson, Q4<double>& ke, double& ke_diag) {
+  const double f = young / (1.0 - poisson * poisson);
+  const double D[3][3] = {{f, f * poisson, 0.0}, {f * poisson, f, 0.0}, {0.0, 0.0, f * 0.5 * (1.0 - poisson)}};
+  const double gp[2] = {0.5 - 0.5 / std::sqrt(3.0), 0.5 + 0.5 / std::sqrt(3.0)};
+  for (int p = 0; p < 8; ++p)
+    for (int q = 0; q < 8; ++q) ke.k[p][q] = 0.0;
+  for (int ix = 0; ix < 2; ++ix)
+    for (int iy = 0; iy < 2; ++iy) {
+      const double x = gp[ix], y = gp[iy];
+      double B[3][8] = {};
+      for (int a = 0; a < 4; ++a) {
+        const int ax = a & 1, ay = a >> 1;
+        const double nx = ax ? x : 1.0 - x, ny = ay ? y : 1.0 - y;
+        const double dnx = (ax ? 1.0 : -1.0) * ny, dny = nx * (ay ? 1.0 : -1.0);
+        B[0][2 * a] = dnx;
+        B[1][2 * a + 1] = dny;
+        B[2][2 * a] = dny;
+        B[2][2 * a + 1] = dnx;
+      }
+      for (int p = 0; p < 8; ++p)
+        for (int q = 0; q < 8; ++q) {
+          double acc = 0.0;
+          for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) acc += B[i][p] * D[i][j] * B[j][q];
+          ke.k[p][q] += 0.25 * acc;
+        }
+    }
+  ke_diag = ke.k[0][0];  // the eight diagonal entries are equal on the square
+}
+
 // The projection's partial arrays are the grid's slots P_S0 .. P_DX.
 ProjWs proj_ws(fbto_grid_s* g) {
   return ProjWs{g->partials + (size_t)P_S0 * 4 * g->max_partials, (int64_t)4 * g->max_partials, g->max_partials,
@@ -230,7 +264,9 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   // step 0's product w = K z from the residual's z
   HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
   int k = 0;
-  if constexpr (sizeof(T) == 4) {
+  // FP32 on voxel grids: fused steps; FP64 and plane grids: unfused
+  const bool fused = sizeof(T) == 4 && g->dim == 3;
+  if (fused) {
     // fused steps: the update of step k and the product of step k + 1 in one pass
     for (; k + 1 < steps; ++k) {
       HIP_TRY(launch_cg_fused<T>(g, rho, set[k & 1], set[(k + 1) & 1], invD, nrhs, k, nb_a, cn.fn, rtol, st,
@@ -263,7 +299,7 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   }
   // last vector update of step k, into the caller's x; with one RHS and a
   // sensitivity wanted, fused with it
-  const CgSet<T>& cur = set[sizeof(T) == 4 ? (k & 1) : 0];
+  const CgSet<T>& cur = set[fused ? (k & 1) : 0];
   // The fused kernel reads x at halo nodes while their owners store x', so it
   // may only run when its input and output are different buffers: after an
   // odd number of fused steps, when the input is the second set.
@@ -338,7 +374,7 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
     int nb_v = 0, nb_a = 0;
     HIP_TRY(launch_minres<T>(g, 0, last, Y, R1, R2, W2, Wc, x, 0, 0, damp, st, &nb_v));
     int itn0 = 1;
-    if constexpr (sizeof(T) == 4) {
+    if (sizeof(T) == 4 && g->dim == 3) {
       // FP32: iterations 1 .. D fused (vector pass t with the product of
       // t + 1); products alternate between two buffers, the Lanczos
       // vectors rotate through three (halo nodes read them while their
@@ -582,6 +618,91 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   SETUP_TRY(hipMalloc(&g->sc, sizeof(Scalars)));
   SETUP_TRY(hipMemset(g->sc, 0, sizeof(Scalars)));
   g->max_partials = std::max(apply_max_blocks(G, g->n_cu), kMaxVecBlocks);
+  SETUP_TRY(hipMalloc(&g->partials, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
+  SETUP_TRY(hipMemset(g->partials, 0, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
+  SETUP_TRY(hipMalloc(&g->sink, kSinkBytes));
+  SETUP_TRY(hipDeviceSynchronize());
+#undef SETUP_TRY
+  *out = g;
+  return ok();
+}
+
+fbto_status_t fbto_setup_grid_2d(const fbto_grid2d_desc_t* d, const uint8_t* fixed_dof_mask, fbto_grid_t* out) {
+  if (!d || !out) return fail(FBTO_ERR_ARG, "desc and out must be non-NULL");
+  *out = nullptr;
+  if (d->nx < 1 || d->ny < 1) return fail(FBTO_ERR_ARG, "grid %d x %d: every axis needs >= 1 element", d->nx, d->ny);
+  if (d->nx > 65534 || d->ny > 65534) return fail(FBTO_ERR_ARG, "grid axis longer than 65534 elements");
+  const int64_t N = (int64_t)(d->nx + 1) * (d->ny + 1);
+  if (N >= ((int64_t)1 << 29))
+    return fail(FBTO_ERR_ARG, "grid has %lld nodes (limit 2^29, so that DOF indices fit 32 bits)", (long long)N);
+  if (d->max_rhs < 1 || d->max_rhs > 4) return fail(FBTO_ERR_ARG, "max_rhs = %d outside [1, 4]", d->max_rhs);
+  if (!(d->young > 0.0) || !std::isfinite(d->young)) return fail(FBTO_ERR_ARG, "young must be > 0");
+  if (!(d->poisson > -1.0 && d->poisson < 0.5)) return fail(FBTO_ERR_ARG, "poisson must be in (-1, 0.5)");
+  if (!(d->penal >= 1.0) || !std::isfinite(d->penal)) return fail(FBTO_ERR_ARG, "penal must be >= 1");
+  if (!(d->rho_min >= 0.0 && d->rho_min < 1.0)) return fail(FBTO_ERR_ARG, "rho_min must be in [0, 1)");
+  if (d->filter_half < 0 || d->filter_half > kGaussMaxHalf)
+    return fail(FBTO_ERR_ARG, "filter_half = %d outside [0, %d]", d->filter_half, kGaussMaxHalf);
+  if (!(d->filter_sigma > 0.0) || !std::isfinite(d->filter_sigma))
+    return fail(FBTO_ERR_ARG, "filter_sigma must be finite and > 0");
+
+  fbto_grid_s* g = new (std::nothrow) fbto_grid_s();
+  if (!g) return fail(FBTO_ERR_ALLOC, "host allocation failed");
+  g->dim = 2;
+  g->desc = fbto_grid_desc_t{d->nx, d->ny, 1, d->max_rhs, d->young, d->poisson, d->penal, d->rho_min, 0.0};
+  Geo& G = g->geo;
+  G.nx = d->nx;
+  G.ny = d->ny;
+  G.nz = 1;
+  G.nxn = d->nx + 1;
+  G.nyn = d->ny + 1;
+  G.nzn = 1;
+  G.N = N;
+  G.E = (int64_t)d->nx * d->ny;
+  G.ndof = 2 * N;
+  G.rnx = 1.0 / G.nx;
+  G.rny = 1.0 / G.ny;
+  G.rnxn = 1.0 / G.nxn;
+  G.rnyn = 1.0 / G.nyn;
+  q4_plane_stress(d->young, d->poisson, g->q4_64, g->ke_diag);
+  for (int p = 0; p < 8; ++p)
+    for (int q = 0; q < 8; ++q) g->q4_32.k[p][q] = (float)g->q4_64.k[p][q];
+  g->gauss64 = GaussW<double>{};
+  g->gauss32 = GaussW<float>{};
+  g->gauss64.half = g->gauss32.half = d->filter_half;
+  for (int k = -d->filter_half; k <= d->filter_half; ++k) {
+    const double w = std::exp(-(double)(k * k) / (2.0 * d->filter_sigma * d->filter_sigma));
+    g->gauss64.w[k + d->filter_half] = w;
+    g->gauss32.w[k + d->filter_half] = (float)w;
+  }
+  g->simp.penal = d->penal;
+  g->simp.rho_min = d->rho_min;
+  g->simp.cubic = d->penal == 3.0 ? 1 : 0;
+
+  std::vector<uint8_t> nm(N, 0);
+  if (fixed_dof_mask)
+    for (int64_t n = 0; n < N; ++n)
+      nm[n] = (uint8_t)((fixed_dof_mask[2 * n] ? 1 : 0) | (fixed_dof_mask[2 * n + 1] ? 2 : 0));
+
+  auto cleanup_fail = [&](fbto_status_t s) {
+    fbto_destroy_grid(g);
+    return s;
+  };
+#define SETUP_TRY(expr)                                                                      \
+  do {                                                                                       \
+    hipError_t _e = (expr);                                                                  \
+    if (_e != hipSuccess)                                                                    \
+      return cleanup_fail(fail(_e == hipErrorOutOfMemory ? FBTO_ERR_ALLOC : FBTO_ERR_HIP,     \
+                               "%s: %s", #expr, hipGetErrorString(_e)));                     \
+  } while (0)
+  SETUP_TRY(hipGetDevice(&g->device));
+  int ncu = 0;
+  SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device));
+  g->n_cu = ncu > 0 ? ncu : 256;
+  SETUP_TRY(hipMalloc(&g->mask, N));
+  SETUP_TRY(hipMemcpy(g->mask, nm.data(), N, hipMemcpyHostToDevice));
+  SETUP_TRY(hipMalloc(&g->sc, sizeof(Scalars)));
+  SETUP_TRY(hipMemset(g->sc, 0, sizeof(Scalars)));
+  g->max_partials = kMaxVecBlocks;
   SETUP_TRY(hipMalloc(&g->partials, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
   SETUP_TRY(hipMemset(g->partials, 0, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
   SETUP_TRY(hipMalloc(&g->sink, kSinkBytes));

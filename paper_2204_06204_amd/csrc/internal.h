@@ -35,6 +35,21 @@ struct Modal {
   T mu4[2];
 };
 
+// Element stiffness of the unit-square Q4 (plane stress), local DOF 2a + c.
+template <typename T>
+struct Q4 {
+  T k[8][8];
+};
+
+// 1D weights of the separable Gaussian filter of a plane grid: w[d + half]
+// for d = -half .. half.
+constexpr int kGaussMaxHalf = 8;
+template <typename T>
+struct GaussW {
+  T w[2 * kGaussMaxHalf + 1];
+  int half;
+};
+
 struct Simp {
   double penal;
   double rho_min;
@@ -162,6 +177,11 @@ struct SortWs {
 
 struct fbto_grid_s {
   fbto_grid_desc_t desc;
+  int dim = 3;               // 3: hex8 voxels; 2: Q4 plane grid (nz = 1 in geo, 2 DOFs per node)
+  fbto::Q4<double> q4_64;    // plane grids: element stiffness and filter weights
+  fbto::Q4<float> q4_32;
+  fbto::GaussW<double> gauss64;
+  fbto::GaussW<float> gauss32;
   fbto::Geo geo;
   fbto::Modal<double> km64;
   fbto::Modal<float> km32;
@@ -296,6 +316,26 @@ hipError_t launch_ir_accum(fbto_grid_s* g, double* u64, const float* d32, int nr
                            hipStream_t st);
 hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double steps_override,
                              hipStream_t st);
+
+// ---- plane grids (plane.hip); the launchers above dispatch to these ----
+template <typename T>
+hipError_t plane_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs, hipStream_t st);
+template <typename T>
+hipError_t plane_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD, T* invD_out,
+                       T* z, int nrhs, hipStream_t st, int* nb_out);
+template <typename T>
+hipError_t plane_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, int step,
+                          hipStream_t st, int* nb_out);
+template <typename T>
+hipError_t plane_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st);
+template <typename T>
+hipError_t plane_sens(fbto_grid_s* g, const T* rho, const T* u, const T* lam, int nrhs, T* dobj, const T* Hsi,
+                      hipStream_t st);
+template <typename T>
+hipError_t plane_filter(fbto_grid_s* g, int kind, const T* in, T* out, T* tmp, const T* Hsi, int want_sum,
+                        hipStream_t st);
+template <typename T>
+hipError_t plane_hs(fbto_grid_s* g, T* Hsi, hipStream_t st);
 // One vector pass of the Krylov step (MINRES recurrence), iteration `itn`
 // of 0 .. last (see k_minres); returns the block count of its partials.
 template <typename T>

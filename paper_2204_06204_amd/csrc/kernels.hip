@@ -1258,6 +1258,7 @@ int apply_max_blocks(const Geo&, int) { return kApplyMaxBlocks; }
 
 template <typename T>
 hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs, hipStream_t st) {
+  if (g->dim == 2) return plane_apply<T>(g, rho, u, y, nrhs, st);
   ApplyArgs<T> A{};
   A.rho = rho;
   A.u = u;
@@ -1268,6 +1269,7 @@ hipError_t launch_apply(fbto_grid_s* g, const T* rho, const T* u, T* y, int nrhs
 template <typename T>
 hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, const T* invD, T* z,
                         int nrhs, hipStream_t st, int* nb_out) {
+  if (g->dim == 2) return plane_resid<T>(g, rho, u, f, r, invD, nullptr, z, nrhs, st, nb_out);
   ApplyArgs<T> A{};
   A.rho = rho;
   A.u = u;
@@ -1281,6 +1283,7 @@ hipError_t launch_resid(fbto_grid_s* g, const T* rho, const T* u, const T* f, T*
 template <typename T>
 hipError_t launch_resid_diag(fbto_grid_s* g, const T* rho, const T* u, const T* f, T* r, T* invD_out, T* z,
                              int nrhs, hipStream_t st, int* nb_out) {
+  if (g->dim == 2) return plane_resid<T>(g, rho, u, f, r, nullptr, invD_out, z, nrhs, st, nb_out);
   ApplyArgs<T> A{};
   A.rho = rho;
   A.u = u;
@@ -1295,6 +1298,7 @@ hipError_t launch_resid_diag(fbto_grid_s* g, const T* rho, const T* u, const T* 
 template <typename T>
 hipError_t launch_apply_cg(fbto_grid_s* g, const T* rho, const T* z, const T* r, T* w, int nrhs, int step,
                            hipStream_t st, int* nb_out) {
+  if (g->dim == 2) return plane_apply_cg<T>(g, rho, z, r, w, nrhs, step, st, nb_out);
   ApplyArgs<T> A{};
   A.rho = rho;
   A.u = z;
@@ -1431,6 +1435,7 @@ __global__ void __launch_bounds__(kVecBlock)
 
 template <typename T>
 hipError_t launch_diag(fbto_grid_s* g, const T* rho, T* invD, hipStream_t st) {
+  if (g->dim == 2) return plane_diag<T>(g, rho, invD, st);
   hipLaunchKernelGGL((k_diag<T>), dim3(flat_grid(g->geo.N)), dim3(kVecBlock), 0, st, g->geo, rho, invD,
                      g->mask, g->simp, g->ke_diag, g->n_springs, g->spring_dof, spring_k_of<T>(g));
   return hipGetLastError();
@@ -1853,6 +1858,7 @@ __global__ void __launch_bounds__(kVecBlock)
 template <typename T>
 hipError_t launch_sens(fbto_grid_s* g, const T* rho, const T* u, const T* lam, int nrhs, T* dobj,
                        const T* Hsi, hipStream_t st) {
+  if (g->dim == 2) return plane_sens<T>(g, rho, u, lam, nrhs, dobj, Hsi, st);
   hipLaunchKernelGGL((k_sens<T>), dim3(flat_grid(g->geo.E)), dim3(kVecBlock), 0, st, g->geo, rho, u, lam, nrhs,
                      dobj, g->mask, modal_of<T>(g), g->simp, Hsi);
   return hipGetLastError();
@@ -2077,6 +2083,8 @@ static StencilW<T, R> stencil_weights(double r) {
 template <typename T>
 hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want_sum, hipStream_t st) {
   Vecs& V = vecs_of<T>(g);
+  if (g->dim == 2)  // separable Gaussian: two passes through the step buffer y (unused while filtering)
+    return plane_filter<T>(g, kind, in, out, (T*)V.y, (const T*)V.Hs, want_sum, st);
   // with a sum, the grid is capped so that its partials stay few
   const int nb = want_sum ? vec_blocks(g->geo.E) : flat_grid(g->geo.E);
   const double r = g->desc.filter_radius;
@@ -2111,6 +2119,7 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
 
 template <typename T>
 hipError_t launch_hs(fbto_grid_s* g, T* Hs, hipStream_t st) {
+  if (g->dim == 2) return plane_hs<T>(g, Hs, st);
   hipLaunchKernelGGL((k_hs<T>), dim3(flat_grid(g->geo.E)), dim3(kVecBlock), 0, st, g->geo, Hs, g->n_stencil,
                      (const int*)g->stencil_off, stencil_w_of<T>(g));
   return hipGetLastError();

@@ -104,7 +104,7 @@ class Grid:
     # ------------------------------------------------------------------
     def _nrhs(self, v: torch.Tensor) -> int:
         if v.numel() % self.ndof:
-            raise ValueError("vector length must be a multiple of 3N")
+            raise ValueError(f"vector length must be a multiple of {self.ndof} (the DOF count)")
         return v.numel() // self.ndof
 
     def apply_K(self, rho: torch.Tensor, u: torch.Tensor, y: Optional[torch.Tensor] = None,
@@ -220,7 +220,41 @@ class Grid:
         return x
 
 
-__all__ = ["Grid", "FbtoError"]
+class PlaneGrid(Grid):
+    """A plane grid of nx x ny Q4 elements with the separable Gaussian filter
+    (fbto_setup_grid_2d); vectors are [nrhs][2N].  Every method of Grid
+    applies to it."""
+
+    def __init__(self, nx: int, ny: int, *, fixed_mask: Optional[np.ndarray] = None, young: float = 1.0,
+                 poisson: float = 0.3, penal: float = 3.0, rho_min: float = 0.0, filter_half: int = 3,
+                 filter_sigma: float = 1.4, max_rhs: int = 1):
+        self.lib = _lib.load()
+        self.nx, self.ny, self.nz = int(nx), int(ny), 1
+        self.E = self.nx * self.ny
+        self.N = (self.nx + 1) * (self.ny + 1)
+        self.ndof = 2 * self.N
+        self.max_rhs = int(max_rhs)
+        desc = _lib.Grid2DDesc(self.nx, self.ny, self.max_rhs, int(filter_half), young, poisson, penal,
+                               rho_min, filter_sigma)
+        mask_p = None
+        if fixed_mask is not None:
+            m = np.ascontiguousarray(np.asarray(fixed_mask, dtype=np.uint8))
+            if m.size != self.ndof:
+                raise ValueError("fixed_mask must have 2N entries")
+            self._mask = m
+            mask_p = m.ctypes.data_as(C.c_void_p)
+        h = C.c_void_p()
+        check(self.lib.fbto_setup_grid_2d(C.byref(desc), mask_p, C.byref(h)), self.lib)
+        self.handle = h
+
+    @classmethod
+    def from_problem(cls, p, max_rhs: Optional[int] = None) -> "PlaneGrid":
+        return cls(p.nx, p.ny, fixed_mask=p.fixed_mask, young=p.young, poisson=p.poisson, penal=p.penal,
+                   rho_min=p.rho_min, filter_half=p.filter_half, filter_sigma=p.filter_sigma,
+                   max_rhs=max_rhs or p.nrhs)
+
+
+__all__ = ["Grid", "PlaneGrid", "FbtoError"]
 
 
 def project_volume_noalloc(y: torch.Tensor, x: Optional[torch.Tensor] = None, lo: float = 0.0,

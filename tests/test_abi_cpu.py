@@ -96,3 +96,20 @@ def test_noalloc_projection_rejects_on_the_host(lib):
                                            None) == _lib.FBTO_ERR_ARG
     assert lib.fbto_project_volume_noalloc(1, 10, fake, fake, 0.5, 1.0, 4.0, 0, None, None,
                                            None) == _lib.FBTO_ERR_INFEASIBLE
+
+
+def test_plane_grid_host_errors(lib):
+    from paper_2204_06204_amd import _lib
+    h = C.c_void_p()
+    bad = [
+        _lib.Grid2DDesc(0, 4, 1, 3, 1.0, 0.3, 3.0, 0.0, 1.4),      # empty axis
+        _lib.Grid2DDesc(4, 4, 5, 3, 1.0, 0.3, 3.0, 0.0, 1.4),      # max_rhs
+        _lib.Grid2DDesc(4, 4, 1, 9, 1.0, 0.3, 3.0, 0.0, 1.4),      # window half-width
+        _lib.Grid2DDesc(4, 4, 1, 3, 1.0, 0.3, 3.0, 0.0, 0.0),      # sigma
+        _lib.Grid2DDesc(4, 4, 1, 3, 1.0, 0.5, 3.0, 0.0, 1.4),      # poisson
+    ]
+    for d in bad:
+        assert lib.fbto_setup_grid_2d(C.byref(d), None, C.byref(h)) == _lib.FBTO_ERR_ARG
+        assert lib.fbto_last_error().decode() != ""
+        assert not h.value
+    assert lib.fbto_setup_grid_2d(None, None, C.byref(h)) == _lib.FBTO_ERR_ARG
