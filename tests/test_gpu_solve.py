@@ -296,3 +296,65 @@ def test_krylov_step_at_the_solution_is_a_fixed_point(dtype):
     g.inner_solve(rho_t, dev(f, dtype), u_t, 5, method="krylov", omega=1.0, info=info)
     assert torch.count_nonzero(u_t) == 0
     assert host(info)[0] == 0.0 and host(info)[4] == 0
+
+
+def _indefinite_case():
+    """A density field whose stiffness has a positive diagonal but is
+    indefinite: solid boundary layer, interior checkerboard of rho = 1 and
+    rho = -0.9 (s < 0).  The oracle's PCG meets p^T K p <= 0 on its third
+    step with a unit load at the centre node."""
+    n = 6
+    p = synth.cantilever(n, n, n, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=1)
+    og = OGrid(n, n, n)
+    ex, ey, ez = og.elem_coords()
+    inner = (ex > 0) & (ex < n - 1) & (ey > 0) & (ey < n - 1) & (ez > 0) & (ez < n - 1)
+    rho = np.where(inner & ((ex + ey + ez) % 2 == 1), -0.9, 1.0)
+    f = np.zeros(p.ndof)
+    f[3 * og.node(3, 3, 3) + 2] = -1.0
+    return p, og, rho, f
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pcg_reports_breakdown(dtype):
+    """p^T K p <= 0 stops the solve with FBTO_ERR_BREAKDOWN; the iterate is
+    the one of the last completed step (FP64: the oracle's, after two)."""
+    from paper_2204_06204_amd.grid import Grid
+    say(f"pcg breakdown {dtype}")
+    p, og, rho, f = _indefinite_case()
+    s = oracle.simp_scale(rho, p.penal, p.rho_min)
+    K = oracle.assemble_K(og, s, p.fixed_mask)
+    D = oracle.jacobi_diag(og, s, p.fixed_mask)
+    with pytest.raises(FloatingPointError):
+        oracle.pcg_ref(lambda v: K @ v, D, f, np.zeros(p.ndof), 3)
+    g = Grid.from_problem(p)
+    u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    g.inner_solve(dev(rho, dtype), dev(f, dtype), u, 10, info=info)
+    inf = host(info)
+    assert inf[4] == 5.0, inf          # FBTO_ERR_BREAKDOWN
+    # FP32 rounding may move the sign change of p^T K p by one step
+    assert inf[3] == 2.0 if dtype == torch.float64 else inf[3] in (2.0, 3.0), inf
+    if dtype == torch.float64:
+        u_ref, _ = oracle.pcg_ref(lambda v: K @ v, D, f, np.zeros(p.ndof), 2)
+        assert np.abs(host(u) - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_nonfinite_load_is_reported(dtype):
+    """A NaN in the load reaches the status slot as FBTO_ERR_NONFINITE, in the
+    inner solve and in the outer step's info record."""
+    from paper_2204_06204_amd.grid import Grid
+    say(f"nonfinite {dtype}")
+    p = synth.cantilever(12, 6, 5, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=3)
+    f = p.loads[0].copy()
+    free = np.flatnonzero(p.fixed_mask == 0)
+    f[free[len(free) // 2]] = np.nan
+    g = Grid.from_problem(p)
+    u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    g.inner_solve(dev(synth.uniform_density(p.E, 1), dtype), dev(f, dtype), u, 5, info=info)
+    assert host(info)[4] == 6.0
+    x = dev(oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax), dtype)
+    u.zero_()
+    g.outer_step(x, u, dev(f, dtype), 1, 1e-3, 5, 0.0, p.vmax, info=info)
+    assert host(info)[6] == 6.0
