@@ -264,8 +264,9 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   // step 0's product w = K z from the residual's z
   HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
   int k = 0;
-  // FP32 on voxel grids: fused steps; FP64 and plane grids: unfused
-  const bool fused = sizeof(T) == 4 && g->dim == 3;
+  // FP32 on voxel grids: fused steps (their buffer loads address each vector
+  // with 32-bit byte offsets); FP64, plane grids and larger grids: unfused
+  const bool fused = sizeof(T) == 4 && g->dim == 3 && g->geo.ndof * (int64_t)sizeof(T) < ((int64_t)1 << 31);
   if (fused) {
     // fused steps: the update of step k and the product of step k + 1 in one pass
     for (; k + 1 < steps; ++k) {

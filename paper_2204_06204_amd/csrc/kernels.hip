@@ -427,34 +427,55 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     al = (T)alpha;
     be = (T)beta;
   };
-  // fused CG step: loads of one plane, and the update at staging time
+  // fused CG step: loads of one plane, and the update at staging time.
+  // The loads go through buffer resources (FP32 only, 12 N < 2^32 bytes, which
+  // the host checks): a lane whose node is not needed -- the far-node slot of
+  // a thread without a far node, x and p outside the owner, planes past the
+  // slab -- passes an out-of-range offset, so its load returns 0 and makes no
+  // cache request, while every load is still issued unconditionally.
+  constexpr uint32_t kOOR = 0xFFFFFFF0u;
+  const int vbytes = (int)(G.ndof * (int64_t)sizeof(T));  // unused outside CGF
+  const int64_t rhs_off = (int64_t)rhs0 * G.ndof;
+  const __amdgpu_buffer_rsrc_t rs_r = __builtin_amdgcn_make_buffer_rsrc((void*)(A.ri + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_w = __builtin_amdgcn_make_buffer_rsrc((void*)(A.wi + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc((void*)(A.si + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc((void*)(A.xi + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_p = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pi + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_d = __builtin_amdgcn_make_buffer_rsrc((void*)A.invD, (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc((void*)A.mask, (short)0, (int)G.N, 0x00020000);
+  typedef float f3v __attribute__((ext_vector_type(3)));
+  auto bload3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) {
+    if constexpr (sizeof(T) == 4) {
+      const f3v t = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+      v[0] = t.x;
+      v[1] = t.y;
+      v[2] = t.z;
+    }
+  };
   auto issue_f = [&](int k, FusedStage<T>& S) {
-    const int kc = k < kend ? k : kend;  // as in issue
-    const bool kv = kc >= 0 && kc <= G.nz;
+    const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + kc * plane : 0;
-      const int64_t o = (int64_t)rhs0 * G.ndof + 3 * n;
-      const unsigned mv = A.mask[n];
+      const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
+      const uint32_t n = ok ? (uint32_t)(gcol[sl] + k * plane) : 0u;
+      const uint32_t ob = ok ? 12u * n : kOOR;
+      const unsigned mv = __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? n : kOOR, 0, 0);
       S.m[sl] = ok ? mv : 7u;
+      T sv[3];
+      bload3(rs_r, ob, S.r[sl]);
+      bload3(rs_w, ob, S.w[sl]);
+      bload3(rs_d, ob, S.d[sl]);
+      bload3(rs_s, ob, sv);  // allocated on the first step too, its contents unused
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        S.r[sl][c] = A.ri[o + c];
-        S.w[sl][c] = A.wi[o + c];
-        S.d[sl][c] = A.invD[3 * n + c];
-        const T sv = A.si[o + c];  // allocated on the first step too, its contents unused
-        S.s[sl][c] = first ? (T)0 : sv;
-      }
-      if (sl == 0) {  // p and x are used by the owner only: other threads all read node 0
-        const int64_t oo = (own_plane && writer && ok) ? o : (int64_t)rhs0 * G.ndof;
+      for (int c = 0; c < 3; ++c) S.s[sl][c] = first ? (T)0 : sv[c];
+      if (sl == 0) {  // p and x are used by the owner only
+        const uint32_t oo = (own_plane && writer && ok) ? ob : kOOR;
+        T pv[3];
+        bload3(rs_x, oo, S.x);
+        bload3(rs_p, oo, pv);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          S.x[c] = A.xi[oo + c];
-          const T pv = A.pi[oo + c];
-          S.p[c] = first ? (T)0 : pv;
-        }
+        for (int c = 0; c < 3; ++c) S.p[c] = first ? (T)0 : pv[c];
       }
     }
   };
@@ -476,7 +497,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         sn[c] = S.w[sl][c] + be * S.s[sl][c];
         rn[c] = S.r[sl][c] - al * sn[c];
         const T zn = S.d[sl][c] * rn[c];
-        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : zn;
+        if (sl == 0 || has_extra) nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : zn;
         if (sl == 0) {
           zq[c] = zn;  // unmasked: the output of a fixed DOF
           pn[c] = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
@@ -1361,6 +1382,7 @@ hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, con
   if constexpr (sizeof(T) == 8) {
     return hipErrorNotSupported;
   } else {
+    if (g->geo.ndof * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit buffer offsets
     ApplyArgs<T> A{};
     A.rho = rho;
     A.y = out.w;
