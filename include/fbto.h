@@ -318,6 +318,28 @@ fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, v
                                      int32_t degree, double beta, int32_t mean_project,
                                      double lo, double vmax, double* info, void* stream);
 
+/* Optimality metrics of a design, the error measures of Thm. 1 (Sec. 4)
+ * that Sec. 5 plots along a run:
+ *   l(x)    = 1/2 sum_r f_r^T K(rho(x))^-1 f_r        the true objective
+ *   Delta^v = |Proj_X(x - alpha grad l(x)) - x|^2 / alpha^2   high-level error
+ *   Delta   = sum_r |u_r - K^-1 f_r|^2                  low-level (tracking) error
+ * K^-1 f is computed by Jacobi-PCG in `prec` to ||f - K u*|| <= rtol ||f||
+ * (at most max_steps steps, warm-started from u) into library workspace;
+ * x and u are not modified.  grad l = 1/2 C^T(-ds_e u*_e^T KE u*_e) (the
+ * exact gradient; no mean projection).  The projection is the one of
+ * fbto_project_volume (hi = 1), run cold with its own search state, so the
+ * warm start of the outer steps is kept.  alpha: the step size at which
+ * Delta^v is measured (the paper's alpha_k), > 0.
+ *   out  device FP64 [5]: l, Delta^v, Delta, max_r ||f_r - K u*_r|| / ||f_r||,
+ *        status (0, FBTO_ERR_BREAKDOWN / _NONFINITE of the solve, or the
+ *        projection's FBTO_INEXACT).
+ * Synchronises the stream every 64 PCG steps.  The first call allocates the
+ * workspace (max_rhs x N DOF values).  Errors: FBTO_ERR_ARG,
+ * FBTO_ERR_INFEASIBLE, FBTO_ERR_ALLOC, FBTO_ERR_HIP. */
+fbto_status_t fbto_optimality(fbto_grid_t g, fbto_prec_t prec, const void* x, const void* u,
+                              const void* f, int32_t nrhs, double alpha, double lo, double vmax,
+                              double rtol, int32_t max_steps, double* out, void* stream);
+
 /* The projection of fbto_project_volume for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc.  No grid handle: n_elem is the length
@@ -344,10 +366,12 @@ fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, cons
  * work is laid out or how long a search may run, not what is computed.
  *   FBTO_OPT_PROJ_PASSES  pass budget of the volume projection inside
  *                         fbto_outer_step / _krylov / _exact, 1 .. 64
- *                         (default 4).  These projections start from the
- *                         previous multiplier and need 1-2 passes on the
- *                         workloads measured; FBTO_INEXACT in the info
- *                         record's status says the budget ran out.
+ *                         (default 2).  These projections start from the
+ *                         previous multiplier: the gradient-step kernel
+ *                         already evaluates the volume there, and one pass
+ *                         sufficed on every iteration of the workloads
+ *                         measured; FBTO_INEXACT in the info record's
+ *                         status says the budget ran out.
  *   FBTO_OPT_APPLY_TILE   tile of the z-marching K(rho)u kernels (apply,
  *   FBTO_OPT_CGF_TILE     residual and CG products; the fused CG step):
  *                         bx | by << 8 | dz << 16 (threads per tile row and

@@ -61,6 +61,8 @@ _SIGS = {
                                          C.c_int32, C.c_double, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_project_volume_noalloc": (C.c_int, [C.c_int, C.c_int64, _VP, _VP, C.c_double, C.c_double,
                                               C.c_double, C.c_int32, _VP, _VP, _VP]),
+    "fbto_optimality": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_double, C.c_double, C.c_double,
+                                  C.c_double, C.c_int32, _VP, _VP]),
     "fbto_set_option": (C.c_int, [_VP, C.c_int, C.c_int64]),
     "fbto_last_error": (C.c_char_p, []),
     "fbto_version": (C.c_char_p, []),

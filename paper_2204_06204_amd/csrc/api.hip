@@ -197,6 +197,9 @@ struct IrBufs {
 };
 struct GridExtra {
   IrBufs ir32, ir64;
+  void* ustar32 = nullptr;     // optimality metrics: K^-1 f, [max_rhs][ndof]
+  void* ustar64 = nullptr;
+  Scalars* sc_metrics = nullptr;  // search state of the metrics' projection
 };
 std::vector<std::pair<fbto_grid_s*, GridExtra*>>& extras() {
   static std::vector<std::pair<fbto_grid_s*, GridExtra*>> v;
@@ -219,6 +222,8 @@ void drop_extra(fbto_grid_s* g) {
         if (b->d) (void)hipFree(b->d);
         if (b->r64) (void)hipFree(b->r64);
       }
+      for (void* q : {e->ustar32, e->ustar64, (void*)e->sc_metrics})
+        if (q) (void)hipFree(q);
       delete e;
       v.erase(v.begin() + i);
       return;
@@ -451,6 +456,47 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
                             nullptr, nullptr, st));
   const int nbE = vec_blocks(g->geo.E);
   HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
+  return FBTO_OK;
+}
+
+// Optimality metrics of a design x with the caller's displacement u (the
+// error metrics of Thm. 1): u* = K(rho(x))^-1 f by Jacobi-PCG to rtol,
+// warm-started from u, in a workspace; then
+//   l = 1/2 sum_r f_r . u*_r,  grad l = 1/2 C^T(-ds_e u*_e^T KE u*_e),
+//   z = Proj_X(x - alpha grad l),  Delta^v = |z - x|^2 / alpha^2,
+//   Delta = sum_r |u_r - u*_r|^2.
+// The projection runs cold with its own search state, so the warm start of
+// the outer steps is left as it was.
+template <typename T>
+fbto_status_t optimality_run(fbto_grid_s* g, const T* x, const T* u, const T* f, int nrhs, double alpha, double lo,
+                             double vmax, double rtol, int max_steps, double* out, hipStream_t st) {
+  Vecs& V = vecs<T>(g);
+  GridExtra* ex = extra_of(g);
+  void*& us_buf = sizeof(T) == 8 ? ex->ustar64 : ex->ustar32;
+  const int64_t nd = g->geo.ndof, E = g->geo.E;
+  if (!us_buf) HIP_TRY(hipMalloc(&us_buf, (size_t)g->desc.max_rhs * nd * sizeof(T)));
+  if (!ex->sc_metrics) {
+    HIP_TRY(hipMalloc(&ex->sc_metrics, sizeof(Scalars)));
+    HIP_TRY(hipMemsetAsync(ex->sc_metrics, 0, sizeof(Scalars), st));
+  }
+  T* us = (T*)us_buf;
+  T* rho = (T*)V.rho;
+  HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
+  HIP_TRY(hipMemcpyAsync(us, u, (size_t)nrhs * nd * sizeof(T), hipMemcpyDeviceToDevice, st));
+  if (fbto_status_t s = pcg_solve<T>(g, rho, f, us, nrhs, max_steps, rtol, st)) return s;
+  int nb_lo = 0, nb_hi = 0;
+  HIP_TRY(launch_sqdist<T>(g, u, us, (int64_t)nrhs * nd, P_MET0, st, &nb_lo));
+  HIP_TRY(launch_dot<T>(g, f, us, nrhs, st));
+  HIP_TRY(launch_sens<T>(g, rho, us, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
+  HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 0, st));
+  // y = x - alpha grad l = x - (alpha / 2) C^T(dc/drho)
+  HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha, 0, lo, 1.0, st));
+  ProjWs W = proj_ws(g);
+  W.sc = ex->sc_metrics;
+  HIP_TRY(launch_project<T>(W, E, (const T*)V.y, (T*)V.ge, lo, 1.0, vmax, 0, kProjMaxPasses, nullptr, nullptr,
+                            nullptr, st));
+  HIP_TRY(launch_sqdist<T>(g, (const T*)V.ge, x, E, P_MET1, st, &nb_hi));
+  HIP_TRY(launch_opt_finish(g, nrhs, vec_blocks(nd), nb_lo, nb_hi, alpha, ex->sc_metrics, out, st));
   return FBTO_OK;
 }
 
@@ -1042,6 +1088,32 @@ fbto_status_t fbto_outer_step_krylov(fbto_grid_t g, fbto_prec_t prec, void* x, v
     if ((s = ensure_vecs<float>(g))) return s;
     s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k, alpha0, 0, mean_project, lo, vmax,
                          info, st, degree, beta);
+  }
+  if (s) return s;
+  return ok();
+}
+
+fbto_status_t fbto_optimality(fbto_grid_t g, fbto_prec_t prec, const void* x, const void* u, const void* f,
+                              int32_t nrhs, double alpha, double lo, double vmax, double rtol, int32_t max_steps,
+                              double* out, void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!x || !u || !f || !out) return fail(FBTO_ERR_ARG, "x, u, f and out must be non-NULL");
+  if (!(std::isfinite(alpha) && alpha > 0.0)) return fail(FBTO_ERR_ARG, "alpha must be finite and > 0");
+  if (!(rtol > 0.0 && rtol < 1.0)) return fail(FBTO_ERR_ARG, "rtol must be in (0, 1)");
+  if (max_steps < 1) return fail(FBTO_ERR_ARG, "max_steps must be >= 1");
+  if (!(std::isfinite(lo) && lo <= 1.0)) return fail(FBTO_ERR_ARG, "need lo <= 1");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g", vmax, lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s;
+  if (prec == FBTO_F64) {
+    if ((s = ensure_vecs<double>(g))) return s;
+    s = optimality_run<double>(g, (const double*)x, (const double*)u, (const double*)f, nrhs, alpha, lo, vmax,
+                               rtol, max_steps, out, st);
+  } else {
+    if ((s = ensure_vecs<float>(g))) return s;
+    s = optimality_run<float>(g, (const float*)x, (const float*)u, (const float*)f, nrhs, alpha, lo, vmax, rtol,
+                              max_steps, out, st);
   }
   if (s) return s;
   return ok();

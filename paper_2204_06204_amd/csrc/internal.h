@@ -112,6 +112,7 @@ enum PartSlot {
   P_VOL = P_E0 + 22,   // sum x_new
   P_DX,                // max |x_new - x_old|
   P_KRN0, P_KRN1,      // Krylov step: ||y||^2 of the new Lanczos vector, by iteration parity
+  P_MET0, P_MET1,      // optimality metrics: squared distances (low-level, high-level)
   P_COUNT
 };
 constexpr int kMaxVecBlocks = 1024;
@@ -206,7 +207,7 @@ struct fbto_grid_s {
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
   fbto::TileChoice tiles[2][2][6] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
   int tile_override[2] = {0, 0};         // FBTO_OPT_APPLY_TILE, FBTO_OPT_CGF_TILE (0: cost model)
-  int proj_passes_warm = 4;              // FBTO_OPT_PROJ_PASSES: projection passes of the outer steps
+  int proj_passes_warm = 2;              // FBTO_OPT_PROJ_PASSES: projection passes of the outer steps
   fbto::SortWs sort;                     // sort-based projection
 };
 
@@ -316,6 +317,14 @@ hipError_t launch_ir_accum(fbto_grid_s* g, double* u64, const float* d32, int nr
                            hipStream_t st);
 hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double steps_override,
                              hipStream_t st);
+// Partials of sum_i (a_i - b_i)^2 over n entries into slot `slot`; returns the block count.
+template <typename T>
+hipError_t launch_sqdist(fbto_grid_s* g, const T* a, const T* b, int64_t n, int slot, hipStream_t st, int* nb_out);
+// Optimality record out[0..4] = l, Delta^v, Delta, max_r ||r_r|| / ||f_r||, status from the
+// partials of f . u* (DOT), the two squared distances (MET0: low-level, MET1:
+// high-level, the latter divided by alpha^2) and the solve's and projection's states.
+hipError_t launch_opt_finish(fbto_grid_s* g, int nrhs, int nb_dot, int nb_lo, int nb_hi, double alpha,
+                             const Scalars* sc_proj, double* out, hipStream_t st);
 
 // ---- plane grids (plane.hip); the launchers above dispatch to these ----
 template <typename T>

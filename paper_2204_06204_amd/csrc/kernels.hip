@@ -1491,6 +1491,9 @@ __global__ void __launch_bounds__(kVecBlock)
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i_first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool first = step == 0;
+  // entries per thread and chunk: fewer with more load cases, so that the
+  // chunk stays in registers
+  constexpr int kU = NR <= 2 ? 8 : 4;
   T zv[kU][NR], wv[kU][NR], pv[kU][NR], sv[kU][NR], xv[kU][NR], rv[kU][NR], dv[kU];
   bool ok[kU];
   auto load_chunk = [&](int64_t i0) {
@@ -2160,10 +2163,44 @@ template hipError_t launch_hs<float>(fbto_grid_s*, float*, hipStream_t);
 // the nearest breakpoint) it becomes a Newton step safeguarded by the
 // bracket [a, b] with f(a) > vmax >= f(b), else bisection.
 // ===========================================================================
+// The evaluation of one search pass at lam for one entry: f(lam) and the
+// classification of the entry just right (+) and just left (-) of lam, plus
+// the nearest breakpoints on either side (slots of proj_decide).
+// (Written with selects only: branches here let the compiler pick v[9] or
+// v[10] by a dynamic index, which puts the array in scratch memory.)
+__device__ __forceinline__ void proj_eval(double (&v)[11], double yd, double lam, double lo, double hi) {
+  const double t = yd - lam;
+  v[0] += fmin(fmax(t, lo), hi);
+  const bool rU = t > hi, rL = !rU && t <= lo, rA = !rU && !rL;   // just right of lambda
+  v[3] += rU ? 1.0 : 0.0;
+  v[4] += rL ? 1.0 : 0.0;
+  v[1] += rA ? 1.0 : 0.0;
+  v[2] += rA ? yd : 0.0;
+  const bool lU = t >= hi, lL = !lU && t < lo, lA = !lU && !lL;   // just left of lambda
+  v[7] += lU ? 1.0 : 0.0;
+  v[8] += lL ? 1.0 : 0.0;
+  v[5] += lA ? 1.0 : 0.0;
+  v[6] += lA ? yd : 0.0;
+  const double b1 = yd - lo, b2 = yd - hi;
+  v[9] = fmax(v[9], fmax(b1 < lam ? b1 : -INFINITY, b2 < lam ? b2 : -INFINITY));
+  v[10] = fmax(v[10], fmax(b1 > lam ? -b1 : -INFINITY, b2 > lam ? -b2 : -INFINITY));
+}
+__device__ __forceinline__ void proj_eval_init(double (&v)[11]) {
+#pragma unroll
+  for (int i = 0; i < 11; ++i) v[i] = 0.0;
+  v[9] = -INFINITY;
+  v[10] = -INFINITY;
+}
+
+// The gradient step y = x - alpha/2 (g - mean g), with the seed of the
+// projection (sum clamp(y), max y, #interior) and its first evaluation, at
+// the multiplier of the previous projection (the warm start), into
+// evaluation set 0: the first search pass decides from it directly.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
     k_step(int64_t E, const T* x, const T* gx, T* y, double half_alpha, int mean_project, double lo,
-           double hi, double* P, int maxp, int nb_sum) {
+           double hi, double* P, int maxp, int nb_sum, const Scalars* sc) {
+  const double lam_w = sc->lam_prev;
   double mean = 0.0;
   if (mean_project) {
     double v[1];
@@ -2173,6 +2210,8 @@ __global__ void __launch_bounds__(kVecBlock)
     mean = v[0] / (double)E;
   }
   double v[3] = {0.0, -INFINITY, 0.0};
+  double ev[11];
+  proj_eval_init(ev);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
        e += (int64_t)gridDim.x * blockDim.x) {
     const T ye = (T)((double)x[e] - half_alpha * ((double)gx[e] - mean));
@@ -2181,9 +2220,14 @@ __global__ void __launch_bounds__(kVecBlock)
     v[0] += fmin(fmax(yd, lo), hi);
     v[1] = fmax(v[1], yd);
     v[2] += (yd > lo && yd < hi) ? 1.0 : 0.0;
+    proj_eval(ev, yd, lam_w, lo, hi);
   }
   double* dst[3] = {pslot(P, P_S0, 0, maxp), pslot(P, P_YMAX, 0, maxp), pslot(P, P_NACT, 0, maxp)};
   write_parts<3, 0x2u>(v, dst, blockIdx.x);
+  double* edst[11];
+#pragma unroll
+  for (int i = 0; i < 11; ++i) edst[i] = pslot(P, P_E0 + i, 0, maxp);  // evaluation set 0
+  write_parts<11, 0x600u>(ev, edst, blockIdx.x);
 }
 
 __device__ __forceinline__ double* lslot(const ProjWs& W, int i) { return W.base + i * W.stride; }
@@ -2217,39 +2261,11 @@ __host__ __device__ constexpr int proj_set(int q) { return L_E0 + 11 * (q & 1); 
 // pass t reads set t and writes set t + 1: two disjoint runs of 11 slots
 static_assert(proj_set(0) + 11 <= proj_set(1) && proj_set(1) + 11 <= L_VOL, "projection slot sets overlap");
 
-// The search state after a pass (identical in every block).  `first`: the
-// partials are the seed (sum clamp(y), max y, #interior); otherwise the
-// evaluation at `lam` left in the slots of set `set`.
-__device__ ProjDecision proj_decide(const ProjWs& W, int nb, bool first, int set, double lo, double hi,
-                                    double vmax, double lam_prev, double lam, double a, double b) {
+// Decision from the evaluation at lam left in evaluation set `set`, with the
+// bracket [a, b] of the root.
+__device__ ProjDecision proj_decide_eval(const ProjWs& W, int nb, int set, double lo, double hi, double vmax,
+                                         double lam, double a, double b) {
   ProjDecision d{};
-  if (first) {
-    double v[3];
-    const double* src[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
-    const int cnt[3] = {nb, nb, nb};
-    reduce_parts<3, 0x2u>(v, src, cnt);
-    const double S0 = v[0], ymax = v[1], nact0 = v[2];
-    d.bad = !isfinite(S0);
-    if (S0 <= vmax || d.bad) {
-      d.done = true;
-      d.lam = 0.0;
-      d.a = d.b = 0.0;
-      return d;
-    }
-    d.a = 0.0;
-    d.b = ymax - lo;
-    double l0;
-    if (lam_prev > d.a && lam_prev < d.b) l0 = lam_prev;
-    else if (nact0 > 0.0) {
-      l0 = (S0 - vmax) / nact0;
-      if (!(l0 > d.a && l0 < d.b)) l0 = 0.5 * (d.a + d.b);
-    } else {
-      l0 = 0.5 * (d.a + d.b);
-    }
-    d.lam = l0;
-    d.done = false;
-    return d;
-  }
   double v[11];
   const double* src[11];
   int cnt[11];
@@ -2306,13 +2322,52 @@ __device__ ProjDecision proj_decide(const ProjWs& W, int nb, bool first, int set
   return d;
 }
 
+// The search state after a pass (identical in every block).  `first`: from
+// the seed (sum clamp(y), max y, #interior), and -- warm_eval -- from the
+// evaluation at the warm start lam_prev in set 0 when lam_prev lies in the
+// bracket; otherwise from the evaluation at `lam` left in set `set`.
+__device__ ProjDecision proj_decide(const ProjWs& W, int nb, bool first, int set, double lo, double hi,
+                                    double vmax, double lam_prev, double lam, double a, double b,
+                                    bool warm_eval = false) {
+  if (!first) return proj_decide_eval(W, nb, set, lo, hi, vmax, lam, a, b);
+  ProjDecision d{};
+  double v[3];
+  const double* src[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
+  const int cnt[3] = {nb, nb, nb};
+  reduce_parts<3, 0x2u>(v, src, cnt);
+  const double S0 = v[0], ymax = v[1], nact0 = v[2];
+  d.bad = !isfinite(S0);
+  if (S0 <= vmax || d.bad) {
+    d.done = true;
+    d.lam = 0.0;
+    d.a = d.b = 0.0;
+    return d;
+  }
+  d.a = 0.0;
+  d.b = ymax - lo;
+  if (warm_eval && lam_prev > d.a && lam_prev < d.b)
+    return proj_decide_eval(W, nb, 0, lo, hi, vmax, lam_prev, d.a, d.b);
+  double l0;
+  if (lam_prev > d.a && lam_prev < d.b) l0 = lam_prev;
+  else if (nact0 > 0.0) {
+    l0 = (S0 - vmax) / nact0;
+    if (!(l0 > d.a && l0 < d.b)) l0 = 0.5 * (d.a + d.b);
+  } else {
+    l0 = 0.5 * (d.a + d.b);
+  }
+  d.lam = l0;
+  d.done = false;
+  return d;
+}
+
 // Pass t of the search: decides from the seed (t = 0) or from pass t - 1's
 // evaluation (set t & 1), then evaluates at the new multiplier into set
 // (t + 1) & 1.  The two sets keep a block that starts late from reading
 // partials that blocks of the same pass have already overwritten.
 template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
-    k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, ProjWs W, int nb) {
+    k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, ProjWs W, int nb,
+                int warm_eval) {
   Scalars* sc = W.sc;
   const double* in = sc->ps[pass & 1];
   double* out = sc->ps[(pass + 1) & 1];
@@ -2322,7 +2377,7 @@ __global__ void __launch_bounds__(kVecBlock)
     return;
   }
   const ProjDecision d =
-      proj_decide(W, nb, pass == 0, pass, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+      proj_decide(W, nb, pass == 0, pass, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2], warm_eval != 0);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     out[0] = d.lam;
     out[1] = d.a;
@@ -2334,25 +2389,10 @@ __global__ void __launch_bounds__(kVecBlock)
   if (d.done) return;
   const double lam = d.lam;
   double v[11];
-#pragma unroll
-  for (int i = 0; i < 11; ++i) v[i] = 0.0;
-  v[9] = -INFINITY;
-  v[10] = -INFINITY;
+  proj_eval_init(v);
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < E;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const double yd = (double)y[e];
-    const double t = yd - lam;
-    v[0] += fmin(fmax(t, lo), hi);
-    if (t > hi) v[3] += 1.0;            // just right of lambda
-    else if (t <= lo) v[4] += 1.0;
-    else { v[1] += 1.0; v[2] += yd; }
-    if (t >= hi) v[7] += 1.0;           // just left of lambda
-    else if (t < lo) v[8] += 1.0;
-    else { v[5] += 1.0; v[6] += yd; }
-    const double b1 = yd - lo, b2 = yd - hi;
-    if (b1 < lam) v[9] = fmax(v[9], b1); else if (b1 > lam) v[10] = fmax(v[10], -b1);
-    if (b2 < lam) v[9] = fmax(v[9], b2); else if (b2 > lam) v[10] = fmax(v[10], -b2);
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    proj_eval(v, (double)y[e], lam, lo, hi);
   double* dst[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) dst[i] = lslot(W, proj_set(pass + 1) + i);
@@ -2406,7 +2446,7 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
                        int mean_project, double lo, double hi, hipStream_t st) {
   const int nb = vec_blocks(g->geo.E);
   hipLaunchKernelGGL((k_step<T>), dim3(nb), dim3(kVecBlock), 0, st, g->geo.E, x, gx, y, half_alpha,
-                     mean_project, lo, hi, g->partials, g->max_partials, g->n_gsum);
+                     mean_project, lo, hi, g->partials, g->max_partials, g->n_gsum, (const Scalars*)g->sc);
   return hipGetLastError();
 }
 
@@ -2420,7 +2460,7 @@ hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double l
     hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, W);
   }
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W, nb);
+    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W, nb, seeded);
   }
   hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W, nb,
                      passes, lam_out, status_out);
@@ -2492,6 +2532,60 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
   return hipGetLastError();
 }
 
+// ===========================================================================
+// Optimality metrics of a design (Sec. 4, the error metrics of Thm. 1).
+// ===========================================================================
+template <typename T>
+__global__ void __launch_bounds__(kVecBlock)
+    k_sqdist(int64_t n, const T* a, const T* b, double* P, int maxp, int slot) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = (double)a[i] - (double)b[i];
+    v[0] += d * d;
+  }
+  double* dst[1] = {pslot(P, slot, 0, maxp)};
+  write_parts<1, 0u>(v, dst, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_sqdist(fbto_grid_s* g, const T* a, const T* b, int64_t n, int slot, hipStream_t st, int* nb_out) {
+  const int nb = vec_blocks(n);
+  hipLaunchKernelGGL((k_sqdist<T>), dim3(nb), dim3(kVecBlock), 0, st, n, a, b, g->partials, g->max_partials, slot);
+  if (nb_out) *nb_out = nb;
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(kVecBlock)
+    k_opt_finish(const double* P, int maxp, int nrhs, int nb_dot, int nb_lo, int nb_hi, double alpha,
+                 const Scalars* sc, const Scalars* sc_proj, double* out) {
+  double v[3];
+  const double* src[3] = {pslot(P, P_DOT, 0, maxp), pslot(P, P_MET0, 0, maxp), pslot(P, P_MET1, 0, maxp)};
+  const int cnt[3] = {nb_dot, nb_lo, nb_hi};
+  reduce_parts<3, 0u>(v, src, cnt);
+  if (threadIdx.x == 0) {
+    double rrel = 0.0, status = 0.0;
+    for (int R = 0; R < nrhs; ++R) {
+      const double fn = sc->fnorm2[R];
+      rrel = fmax(rrel, fn > 0.0 ? sc->rnorm2[R] / fn : sc->rnorm2[R]);
+      if (sc->status[R] != 0.0) status = sc->status[R];
+    }
+    const double ps = sc_proj->proj_status;
+    if (ps > 0.0 && (status == 0.0 || ps == (double)FBTO_ERR_NONFINITE)) status = ps;
+    out[0] = 0.5 * v[0];
+    out[1] = v[2] / (alpha * alpha);
+    out[2] = v[1];
+    out[3] = rrel;
+    out[4] = status;
+  }
+}
+
+hipError_t launch_opt_finish(fbto_grid_s* g, int nrhs, int nb_dot, int nb_lo, int nb_hi, double alpha,
+                             const Scalars* sc_proj, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_opt_finish, dim3(1), dim3(kVecBlock), 0, st, (const double*)g->partials, g->max_partials,
+                     nrhs, nb_dot, nb_lo, nb_hi, alpha, (const Scalars*)g->sc, sc_proj, out);
+  return hipGetLastError();
+}
+
 // ---- explicit instantiations ----------------------------------------------
 #define FBTO_INST(T)                                                                                   \
   template hipError_t launch_apply<T>(fbto_grid_s*, const T*, const T*, T*, int, hipStream_t);         \
@@ -2519,6 +2613,7 @@ hipError_t launch_solve_info(fbto_grid_s* g, double* info, int nrhs, double step
                                      hipStream_t);                                                     \
   template hipError_t launch_dot<T>(fbto_grid_s*, const T*, const T*, int, hipStream_t);               \
   template hipError_t launch_filter<T>(fbto_grid_s*, int, const T*, T*, int, hipStream_t);             \
+  template hipError_t launch_sqdist<T>(fbto_grid_s*, const T*, const T*, int64_t, int, hipStream_t, int*); \
   template hipError_t launch_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, double,       \
                                      double, hipStream_t);                                             \
   template hipError_t launch_project<T>(const ProjWs&, int64_t, const T*, T*, double, double, double, int, \

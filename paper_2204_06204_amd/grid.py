@@ -190,6 +190,19 @@ class Grid:
             raise ValueError(f"unknown method {method!r}")
         return x
 
+    def optimality(self, x, u, f, alpha: float, lo: float, vmax: float, rtol: float = 1e-8,
+                   max_steps: int = 100000, out: Optional[torch.Tensor] = None, stream=None):
+        """fbto_optimality: FP64 [5] = l(x), Delta^v, Delta, relative residual
+        of the exact solve, status."""
+        if out is None:
+            out = torch.zeros(5, dtype=torch.float64, device=x.device)
+        nr = self._nrhs(u)
+        check(self.lib.fbto_optimality(self.handle, _prec(x), _ptr(x, None, self.E, "x"),
+                                       _ptr(u, x.dtype, None, "u"), _ptr(f, x.dtype, u.numel(), "f"), nr,
+                                       float(alpha), float(lo), float(vmax), float(rtol), int(max_steps),
+                                       _ptr(out, torch.float64, None, "out"), _stream(stream)), self.lib)
+        return out
+
     def set_option(self, option: str, value: int):
         """fbto_set_option: "proj_passes", "apply_tile" or "cgf_tile"."""
         opt = {"proj_passes": _lib.FBTO_OPT_PROJ_PASSES, "apply_tile": _lib.FBTO_OPT_APPLY_TILE,

@@ -468,3 +468,34 @@ def test_pgd_with_exact_solves_cfg1_fp64():
         f = p.loads[0]
         c_true = float(f @ oracle.solve_direct(K, f))
         assert abs(recs[k][0] - c_true) <= 1e-9 * c_true, k
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_optimality_metrics_against_oracle(dtype):
+    """fbto_optimality: the true objective l(x), the high-level error
+    Delta^v and the low-level tracking error Delta of Thm. 1 against the
+    oracle's direct solve, at a design and displacement taken from three
+    outer iterations."""
+    say(f"optimality metrics {dtype}")
+    p = synth.config("cfg1")
+    alpha0 = 0.0016874513029055756
+    g = _grid(p)
+    x = dev(oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax), dtype)
+    u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    f = dev(p.loads[0], dtype)
+    for k in (1, 2, 3):
+        g.outer_step(x, u, f, k, alpha0, p.inner_steps, 0.0, p.vmax)
+    x_before, u_before = host(x).copy(), host(u).copy()
+    alpha = alpha0 * 4 ** -0.75
+    rtol = 1e-12 if dtype == torch.float64 else 1e-5
+    out = host(g.optimality(x, u, f, alpha, 0.0, p.vmax, rtol=rtol))
+    assert np.array_equal(host(x), x_before) and np.array_equal(host(u), u_before)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    l_ref, grad, U = oracle.true_objective(ctx, x_before, p.loads)
+    dv_ref = oracle.relative_projection_error(x_before, grad, alpha, 0.0, 1.0, p.vmax)
+    d_ref = float(((u_before - U[0]) ** 2).sum())
+    tl, tv = (1e-10, 1e-7) if dtype == torch.float64 else (2e-5, 2e-3)
+    assert abs(out[0] - l_ref) <= tl * l_ref
+    assert abs(out[1] - dv_ref) <= tv * dv_ref
+    assert abs(out[2] - d_ref) <= tv * d_ref
+    assert out[3] <= rtol and out[4] == 0.0
