@@ -344,6 +344,81 @@ def projection_timing(torch, reps=20):
     return out
 
 
+def optimality_history(g, p, torch):
+    """The true objective l(v_k) and the high-level error Delta^v_k of Thm. 1
+    (fbto_optimality, FP64 solve to a relative residual of 1e-8) along runs
+    of the three methods on the 128x64x64 workload: FBTO (Alg. 1, 8 PCG
+    steps), CPFBTO (Alg. 3, D = 20) and PGD with exact low-level solves,
+    every few iterations; alpha_k = alpha0 k^(-3/4)."""
+    dev = torch.device("cuda:0")
+    f64 = torch.tensor(p.loads[0], dtype=torch.float64, device=dev)
+    out = {}
+    for name, iters, every in (("fbto", 60, 10), ("cpfbto", 30, 5), ("pgd", 10, 2)):
+        x = g.project_volume(torch.tensor(p.x0, dtype=torch.float32, device=dev), lo=0.0, hi=1.0, vmax=p.vmax)
+        u = torch.zeros(p.ndof, dtype=torch.float32, device=dev)
+        f = f64.float()
+        info = torch.zeros(8, dtype=torch.float64, device=dev)
+        rows = []
+        t_run = 0.0
+        for k in range(1, iters + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if name == "fbto":
+                g.outer_step(x, u, f, k, ALPHA0_CFG3, p.inner_steps, 0.0, p.vmax, info=info)
+            elif name == "cpfbto":
+                g.outer_step(x, u, f, k, ALPHA0_CFG3, KRYLOV_DEGREE, 0.0, p.vmax, info=info, method="krylov")
+            else:
+                g.outer_step(x, u, f, k, ALPHA0_CFG3, 100000, 0.0, p.vmax, info=info, method="exact", rtol=PGD_RTOL)
+            torch.cuda.synchronize()
+            t_run += time.perf_counter() - t0
+            if k % every == 0 or k == 1:
+                alpha_k = ALPHA0_CFG3 * (k + 1) ** -0.75
+                m = g.optimality(x.double(), u.double(), f64, alpha_k, 0.0, p.vmax, rtol=1e-8).cpu().tolist()
+                rows.append({"k": k, "seconds": t_run, "l": m[0], "delta_v": m[1], "delta_u": m[2],
+                             "rel_residual": m[3], "status": m[4], "compliance_inexact": float(info[0])})
+        out[name] = rows
+    return out
+
+
+def plane_path(torch):
+    """Alg. 3 (D = 20, beta = 1, box [0.1, 1], eta = 3, 7x7 Gaussian filter) on
+    plane cantilevers at two of the paper's table shapes, FP32 and FP64,
+    seconds per outer iteration beside the paper's figure for the shape
+    (its hardware: a GTX 1060 mobile GPU)."""
+    import synth
+    from paper_2204_06204_amd.grid import PlaneGrid
+    a0 = json.load(open(os.path.join(ROOT, "tests", "golden", "alpha0.json")))
+    paper = {"plane_a": 0.040, "plane_e": 0.011}
+    out = {}
+    dev = torch.device("cuda:0")
+    for name in ("plane_a", "plane_e"):
+        p = synth.plane_config(name)
+        g = PlaneGrid.from_problem(p)
+        rec = {"grid": [p.ny, p.nx], "volfrac": p.volfrac, "elements": p.E, "dofs": p.ndof,
+               "paper_s_per_iter": paper[name], "paper_hardware": "GTX 1060 mobile (1280 cores), 2D regular grid"}
+        alpha0 = a0.get(name, a0["plane_a"])
+        for dtype, tag in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+            x = torch.full((p.E,), p.volfrac, dtype=dtype, device=dev)
+            u = torch.zeros(p.ndof, dtype=dtype, device=dev)
+            f = torch.tensor(p.loads[0], dtype=dtype, device=dev)
+            info = torch.zeros(8, dtype=torch.float64, device=dev)
+            n = 50
+            for k in range(1, 6):
+                g.outer_step(x, u, f, k, alpha0, p.degree, p.lo, p.vmax, info=info, method="krylov", beta=p.beta)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for k in range(6, 6 + n):
+                g.outer_step(x, u, f, k, alpha0, p.degree, p.lo, p.vmax, info=info, method="krylov", beta=p.beta)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / n
+            rec[f"{tag}_s_per_iter"] = dt
+            rec[f"{tag}_speedup_vs_paper"] = paper[name] / dt
+            rec[f"{tag}_status"] = float(info[6])
+        out[name] = rec
+        g.close()
+    return out
+
+
 def cpu_baseline(p, seconds):
     """The CPU FP64 oracle (as it stands) running outer iterations of the same
     workload on the host cores for about `seconds`."""
@@ -447,6 +522,8 @@ def main():
     osizes = None if args.no_sizes else outer_sizes(torch)
     proj = None if args.no_sizes else projection_timing(torch)
     fixed4 = None if (args.no_sizes or args.no_fixed_err) else fixed_error_cfg4(torch)
+    hist = None if args.no_sizes else optimality_history(g, p, torch)
+    plane = None if args.no_sizes else plane_path(torch)
     cpu = None if args.no_cpu_baseline else cpu_baseline(p, args.cpu_seconds)
 
     value = args.steps / dt32
@@ -503,6 +580,8 @@ def main():
         "fixed_error_cfg4": fixed4,
         "outer_sizes": osizes,
         "projection": proj,
+        "optimality_history": hist,
+        "plane_path": plane,
         "cpu_baseline": cpu,
         "kernel_hash": kernel_hash(),
     }
