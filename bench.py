@@ -75,7 +75,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-sizes", action="store_true",
                     help="skip the K(rho)u timings at 256x128x128 and 384x192x192")
-    ap.add_argument("--profile-only", choices=["apply", "outer", "cpfbto", "project"], default=None,
+    ap.add_argument("--profile-only", choices=["apply", "outer", "cpfbto", "project", "fused_large", "plane"],
+                    default=None,
                     help="run only a short loop of one kind (for rocprofv3)")
     return ap.parse_args()
 
@@ -469,6 +470,23 @@ def main():
             print(json.dumps(projection_timing(torch)), flush=True)
         elif args.profile_only == "outer":
             outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, true_obj=False)
+        elif args.profile_only == "fused_large":
+            # FP32 Jacobi-PCG solves of 41 steps (40 fused steps each) on the
+            # 384x192x192 cantilever with one load case
+            import synth as _s
+            g.close()
+            p = _s.config("cfg5")
+            g = Grid.from_problem(p, max_rhs=1)
+            dev = torch.device("cuda:0")
+            rho = torch.tensor(p.x0, dtype=torch.float32, device=dev)
+            f = torch.tensor(p.loads[0], dtype=torch.float32, device=dev)
+            u = torch.zeros_like(f)
+            for _ in range(args.warmup + args.steps):
+                u.zero_()
+                g.inner_solve(rho, f, u, 41)
+            torch.cuda.synchronize()
+        elif args.profile_only == "plane":
+            plane_path(torch)
         else:
             outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, krylov=KRYLOV_DEGREE,
                        true_obj=False)
