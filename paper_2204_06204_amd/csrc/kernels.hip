@@ -290,6 +290,14 @@ struct MinresStage {
   unsigned m[2];
 };
 
+// A value that is the same in every lane of the wave, kept in a scalar
+// register (FP32; FP64 values stay in vector registers).
+template <typename T>
+__device__ __forceinline__ T wave_uniform(T v) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  else return v;
+}
+
 template <typename T, int NR, int MODE>
 __global__ void __launch_bounds__(kApplyMaxThreads)
     k_apply(ApplyArgs<T> A, int rhs0) {
@@ -424,8 +432,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     double alpha, beta;
     cg_coefficients(pre[0], pre[1], pre[2], pre[3], rhs0, A.step, A.rtol, const_cast<Scalars*>(A.sc),
                     lb == 0 && tid == 0, alpha, beta);
-    al = (T)alpha;
-    be = (T)beta;
+    // the same value in every lane: kept in scalar registers
+    al = wave_uniform((T)alpha);
+    be = wave_uniform((T)beta);
   };
   // fused CG step: loads of one plane, and the update at staging time.
   // The loads go through buffer resources (FP32 only, 12 N < 2^32 bytes, which
@@ -450,6 +459,20 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       v[0] = t.x;
       v[1] = t.y;
       v[2] = t.z;
+    }
+  };
+  const __amdgpu_buffer_rsrc_t rs_xo = __builtin_amdgcn_make_buffer_rsrc((void*)(A.xo + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_ro = __builtin_amdgcn_make_buffer_rsrc((void*)(A.ro + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_po = __builtin_amdgcn_make_buffer_rsrc((void*)(A.po + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_so = __builtin_amdgcn_make_buffer_rsrc((void*)(A.so + rhs_off), (short)0, vbytes, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs_y = __builtin_amdgcn_make_buffer_rsrc((void*)(A.y + rhs_off), (short)0, vbytes, 0x00020000);
+  auto bstore3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) {
+    if constexpr (sizeof(T) == 4) {
+      f3v t;
+      t.x = v[0];
+      t.y = v[1];
+      t.z = v[2];
+      __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(__attribute__((ext_vector_type(3))) unsigned, t), rs, off, 0, 0);
     }
   };
   auto issue_f = [&](int k, FusedStage<T>& S) {
@@ -485,12 +508,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const bool owner = sl == 0 && writer && own_plane;  // the owner's node index is valid
-      const int64_t o = (int64_t)rhs0 * G.ndof + 3 * (owner ? gcol[0] + k * plane : 0);
-      T* const sink = A.sink + kSinkStride * tid;
-      T* xo = owner ? A.xo + o : sink;
-      T* ro = owner ? A.ro + o : sink + 3;
-      T* po = owner ? A.po + o : sink + 6;
-      T* so = owner ? A.so + o : sink + 9;
+      // the owner's byte offset; other threads store out of range (dropped)
+      const uint32_t ob = owner ? 12u * (uint32_t)(gcol[0] + k * plane) : kOOR;
       T xn[3], rn[3], pn[3], sn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -509,15 +528,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           }
         }
       }
-      if (sl == 0) {  // one vector per output (the four may alias: sink)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) ro[c] = rn[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) po[c] = pn[c];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) so[c] = sn[c];
+      if (sl == 0) {
+        bstore3(rs_xo, ob, xn);
+        bstore3(rs_ro, ob, rn);
+        bstore3(rs_po, ob, pn);
+        bstore3(rs_so, ob, sn);
       }
     }
   };
@@ -525,10 +540,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   // fused MINRES step: the scalar recurrence of iteration t (every block,
   // same order; block 0 keeps the state), as in k_minres
   T ms = (T)0, mc1 = (T)0, mas = (T)0, minvb = (T)0, mwc1 = (T)0, mwc2 = (T)0, minvg = (T)0, mstep = (T)0;
-  auto uniform = [](T v) -> T {  // the value is the same in every lane: keep it in a scalar register
-    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
-    else return v;
-  };
+  auto uniform = [](T v) -> T { return wave_uniform(v); };
   auto mrf_prologue = [&]() {
     const int itn = A.step;
     double v[3];
@@ -863,9 +875,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
             part[4 * r + 2] += own_only((double)fv[c] * (double)fv[c]);
           }
         } else {
-          T* const yd = wr ? A.y + o : sink;
+          if constexpr (MODE == MODE_CGF) {
+            // the owner's store; other threads store out of range (dropped)
+            bstore3(rs_y, wr ? 12u * (uint32_t)n : kOOR, acc);
+          } else {
+            T* const yd = wr ? A.y + o : sink;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) yd[c] = acc[c];
+            for (int c = 0; c < 3; ++c) yd[c] = acc[c];
+          }
           if constexpr (MODE == MODE_CG) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
