@@ -139,7 +139,10 @@ enum {
  *                   (ignored on fixed DOFs).  May be NULL if n_springs = 0.
  *   out             receives the handle.
  * Allocates device workspace (FP32 and FP64 vectors for max_rhs RHS are
- * allocated on first use of each precision).  Errors: FBTO_ERR_ARG,
+ * allocated on first use of each precision).  Limits: every axis <= 65534
+ * elements, fewer than 2^29 nodes, and a node plane (nx+1)(ny+1) of at most
+ * 22,369,621 nodes (the K u kernels address a few planes with 32-bit byte
+ * offsets).  Errors: FBTO_ERR_ARG, FBTO_ERR_UNSUPPORTED (plane too large),
  * FBTO_ERR_ALLOC, FBTO_ERR_HIP. */
 fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* desc,
                               const uint8_t* fixed_dof_mask,

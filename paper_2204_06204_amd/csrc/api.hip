@@ -269,9 +269,8 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   // step 0's product w = K z from the residual's z
   HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
   int k = 0;
-  // FP32 on voxel grids: fused steps (their buffer loads address each vector
-  // with 32-bit byte offsets); FP64, plane grids and larger grids: unfused
-  const bool fused = sizeof(T) == 4 && g->dim == 3 && g->geo.ndof * (int64_t)sizeof(T) < ((int64_t)1 << 31);
+  // FP32 on voxel grids: fused steps; FP64 and plane grids: unfused
+  const bool fused = sizeof(T) == 4 && g->dim == 3;
   if (fused) {
     // fused steps: the update of step k and the product of step k + 1 in one pass
     for (; k + 1 < steps; ++k) {
@@ -556,6 +555,13 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
     return fail(FBTO_ERR_ARG, "grid has %lld nodes (limit 2^29, so that DOF indices fit 32 bits)",
                 (long long)N);
   if (d->max_rhs < 1 || d->max_rhs > 4) return fail(FBTO_ERR_ARG, "max_rhs = %d outside [1, 4]", d->max_rhs);
+  {
+    // the K u kernels address four node planes of FP64 values with 32-bit byte offsets
+    const int64_t plane = (int64_t)(d->nx + 1) * (d->ny + 1);
+    if (24 * plane * 4 >= ((int64_t)1 << 31))
+      return fail(FBTO_ERR_UNSUPPORTED, "a node plane of %lld nodes exceeds the %lld the K u kernels address",
+                  (long long)plane, (long long)(((int64_t)1 << 31) / 96));
+  }
   if (!(d->young > 0.0) || !std::isfinite(d->young)) return fail(FBTO_ERR_ARG, "young must be > 0");
   if (!(d->poisson > -1.0 && d->poisson < 0.5)) return fail(FBTO_ERR_ARG, "poisson must be in (-1, 0.5)");
   if (!(d->penal >= 1.0) || !std::isfinite(d->penal)) return fail(FBTO_ERR_ARG, "penal must be >= 1");

@@ -335,10 +335,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 
   // node columns staged by this thread: slot 0 its own (ex, ey), slot 1 one
   // node of the tile's far column / row (threads 0 .. BX + BY).
-  // Every memory operation of the z-march is issued unconditionally (threads
-  // without a far node re-read their own node and stage it once more; planes
-  // past the slab load clamped addresses; stores without an owner go to the
-  // sink).  With no branch around them the compiler can
+  // Every memory operation of the z-march is issued unconditionally (loads
+  // and stores a thread does not need go out of range, see below).  With no
+  // branch around them the compiler can
   // count the loads in flight and wait only for the ones it consumes, so
   // the planes prefetched for the next layers stay in flight.
   const bool has_extra = tid <= BX + BY;
@@ -353,28 +352,84 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
   }
 
-  // Planes past the slab's last one (kend) are staged but never read: their
-  // loads re-read plane kend, which the block has just loaded (a cache hit,
-  // no HBM traffic).
+  // Memory access of the z-march.  Every array is addressed through a buffer
+  // resource based at the block's first plane ez0, with 32-bit byte offsets
+  // relative to it (the host keeps 3 b plane (dz + 3) < 2^31, b the value
+  // size).  A lane whose node is not needed -- the far-node slot of a thread
+  // without a far node, planes past the slab, values only the owner of a
+  // node uses, outputs of a thread that owns none -- passes an out-of-range
+  // offset: its load returns 0 and its store is dropped, without a cache
+  // request, while every memory instruction is still issued unconditionally.
+  // out-of-range offset: the resources span 2^31 - 1 bytes, and kOOR plus the
+  // 8 and 16 of an FP64 triple's later values stays above that (no wrap to 0)
+  constexpr uint32_t kOOR = 0x80000000u;
+  const int64_t pbase = (int64_t)ez0 * plane;               // first node of plane ez0
+  const int64_t vbase = (int64_t)rhs0 * G.ndof + 3 * pbase;  // its first value in RHS rhs0
+  auto rsrc = [](const void* p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
+  };
+  auto vres = [&](const T* v, int r = 0) { return rsrc(v ? v + vbase + (int64_t)r * G.ndof : v); };  // [nrhs][3N]
+  auto dres = [&](const T* v) { return rsrc(v ? v + 3 * pbase : v); };  // [3N], one set
+  // byte offset of the first value of node column `col` in plane k (k >= ez0)
+  auto voff = [&](int col, int k) -> uint32_t {
+    return (uint32_t)(3 * sizeof(T)) * (uint32_t)(col + (k - ez0) * plane);
+  };
+  const __amdgpu_buffer_rsrc_t rs_m = rsrc(A.mask + pbase);
+  auto bload3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) {
+    if constexpr (sizeof(T) == 4) {
+      typedef float f3v __attribute__((ext_vector_type(3)));
+      const f3v t = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+      v[0] = t.x;
+      v[1] = t.y;
+      v[2] = t.z;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        v[c] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8u * c, 0, 0));  // a 2-dword vector
+    }
+  };
+  typedef unsigned u2v __attribute__((ext_vector_type(2)));
+  auto bstore3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) {
+    if constexpr (sizeof(T) == 4) {
+      typedef unsigned u3v __attribute__((ext_vector_type(3)));
+      u3v t;
+      t.x = __builtin_bit_cast(unsigned, v[0]);
+      t.y = __builtin_bit_cast(unsigned, v[1]);
+      t.z = __builtin_bit_cast(unsigned, v[2]);
+      __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, 0);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v[c]), rs, off + 8u * c, 0, 0);
+    }
+  };
+  // the mask byte of a node (kOOR: 0)
+  auto bmask = [&](int col, int k, bool ok) -> unsigned {
+    return __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? (uint32_t)(col + (k - ez0) * plane) : kOOR, 0, 0);
+  };
+
+  // Planes past the slab's last one (kend) are staged but never read; their
+  // loads are out of range.
+  __amdgpu_buffer_rsrc_t rs_u[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) rs_u[r] = vres(A.u, r);
   auto issue = [&](int k, ApplyStage<T, NR>& S) {
-    const int kc = k < kend ? k : kend;
-    const bool kv = kc >= 0 && kc <= G.nz;
+    const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + kc * plane : 0;
-      const unsigned mv = A.mask[n];
+      const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
+      const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
+      const unsigned mv = bmask(gcol[sl], k, ok);
       S.m[sl] = ok ? mv : 7u;
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) S.v[sl][r][c] = A.u[(int64_t)(rhs0 + r) * G.ndof + 3 * n + c];
+      for (int r = 0; r < NR; ++r) bload3(rs_u[r], ob, S.v[sl][r]);
     }
   };
   auto stage = [&](const ApplyStage<T, NR>& S, int buf) {
     T* nb = nodes + buf * (NR * 3 * NS);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
+      if (sl == 1 && !has_extra) continue;  // no far node: nothing staged
 #pragma unroll
       for (int r = 0; r < NR; ++r)
 #pragma unroll
@@ -401,9 +456,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   // when it is used: consuming a load right after it was issued would make
   // the wave wait for every load issued before it (the counter is in order),
   // including the node planes prefetched for the next layers.
+  const __amdgpu_buffer_rsrc_t rs_rho = rsrc(A.rho + (int64_t)G.nx * G.ny * ez0);
   auto load_rho = [&](int ez) -> T {
     const bool el = col_elem && ez >= 0 && ez < G.nz && ez < kend;  // element layers of this block
-    return A.rho[el ? ex + G.nx * (ey + G.ny * ez) : 0];
+    const uint32_t off = el ? (uint32_t)sizeof(T) * (uint32_t)(ex + G.nx * (ey + G.ny * (ez - ez0))) : kOOR;
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs_rho, off, 0, 0));
+    else
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs_rho, off, 0, 0));
   };
   auto scale_of = [&](int ez, T rv) -> T {
     const bool el = col_elem && ez >= 0 && ez < G.nz;
@@ -437,53 +497,17 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     be = wave_uniform((T)beta);
   };
   // fused CG step: loads of one plane, and the update at staging time.
-  // The loads go through buffer resources (FP32 only, 12 N < 2^32 bytes, which
-  // the host checks): a lane whose node is not needed -- the far-node slot of
-  // a thread without a far node, x and p outside the owner, planes past the
-  // slab -- passes an out-of-range offset, so its load returns 0 and makes no
-  // cache request, while every load is still issued unconditionally.
-  constexpr uint32_t kOOR = 0xFFFFFFF0u;
-  const int vbytes = (int)(G.ndof * (int64_t)sizeof(T));  // unused outside CGF
-  const int64_t rhs_off = (int64_t)rhs0 * G.ndof;
-  const __amdgpu_buffer_rsrc_t rs_r = __builtin_amdgcn_make_buffer_rsrc((void*)(A.ri + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_w = __builtin_amdgcn_make_buffer_rsrc((void*)(A.wi + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_s = __builtin_amdgcn_make_buffer_rsrc((void*)(A.si + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_x = __builtin_amdgcn_make_buffer_rsrc((void*)(A.xi + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_p = __builtin_amdgcn_make_buffer_rsrc((void*)(A.pi + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_d = __builtin_amdgcn_make_buffer_rsrc((void*)A.invD, (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_m = __builtin_amdgcn_make_buffer_rsrc((void*)A.mask, (short)0, (int)G.N, 0x00020000);
-  typedef float f3v __attribute__((ext_vector_type(3)));
-  auto bload3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) {
-    if constexpr (sizeof(T) == 4) {
-      const f3v t = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
-      v[0] = t.x;
-      v[1] = t.y;
-      v[2] = t.z;
-    }
-  };
-  const __amdgpu_buffer_rsrc_t rs_xo = __builtin_amdgcn_make_buffer_rsrc((void*)(A.xo + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_ro = __builtin_amdgcn_make_buffer_rsrc((void*)(A.ro + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_po = __builtin_amdgcn_make_buffer_rsrc((void*)(A.po + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_so = __builtin_amdgcn_make_buffer_rsrc((void*)(A.so + rhs_off), (short)0, vbytes, 0x00020000);
-  const __amdgpu_buffer_rsrc_t rs_y = __builtin_amdgcn_make_buffer_rsrc((void*)(A.y + rhs_off), (short)0, vbytes, 0x00020000);
-  auto bstore3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) {
-    if constexpr (sizeof(T) == 4) {
-      f3v t;
-      t.x = v[0];
-      t.y = v[1];
-      t.z = v[2];
-      __builtin_amdgcn_raw_buffer_store_b96(__builtin_bit_cast(__attribute__((ext_vector_type(3))) unsigned, t), rs, off, 0, 0);
-    }
-  };
+  const __amdgpu_buffer_rsrc_t rs_r = vres(A.ri), rs_w = vres(A.wi), rs_s = vres(A.si), rs_x = vres(A.xi),
+                               rs_p = vres(A.pi), rs_d = dres(A.invD);
+  const __amdgpu_buffer_rsrc_t rs_xo = vres(A.xo), rs_ro = vres(A.ro), rs_po = vres(A.po), rs_so = vres(A.so);
   auto issue_f = [&](int k, FusedStage<T>& S) {
     const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
-      const uint32_t n = ok ? (uint32_t)(gcol[sl] + k * plane) : 0u;
-      const uint32_t ob = ok ? 12u * n : kOOR;
-      const unsigned mv = __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? n : kOOR, 0, 0);
+      const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
+      const unsigned mv = bmask(gcol[sl], k, ok);
       S.m[sl] = ok ? mv : 7u;
       T sv[3];
       bload3(rs_r, ob, S.r[sl]);
@@ -509,7 +533,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     for (int sl = 0; sl < 2; ++sl) {
       const bool owner = sl == 0 && writer && own_plane;  // the owner's node index is valid
       // the owner's byte offset; other threads store out of range (dropped)
-      const uint32_t ob = owner ? 12u * (uint32_t)(gcol[0] + k * plane) : kOOR;
+      const uint32_t ob = owner ? voff(gcol[0], k) : kOOR;
       T xn[3], rn[3], pn[3], sn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -521,10 +545,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           zq[c] = zn;  // unmasked: the output of a fixed DOF
           pn[c] = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
           xn[c] = S.x[c] + al * pn[c];
-          if (owner) {
-            part[0] += (double)rn[c] * (double)zn;  // r.z
-            part[2] += (double)rn[c] * (double)rn[c];  // r.r
-            part[3] = fmax(part[3], fabs((double)rn[c]));
+          if constexpr (NP >= 4) {
+            if (owner) {
+              part[0] += (double)rn[c] * (double)zn;  // r.z
+              part[2] += (double)rn[c] * (double)rn[c];  // r.r
+              part[3] = fmax(part[3], fabs((double)rn[c]));
+            }
           }
         }
       }
@@ -596,29 +622,26 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     minvg = uniform((T)(gamma > kTinyNorm ? 1.0 / gamma : 0.0));
     mstep = uniform((T)(A.damp * phi));
   };
+  // fused MINRES step (single vectors, rhs0 = 0): the memory access of the fused CG step
+  const __amdgpu_buffer_rsrc_t rs_mY = vres(A.mY), rs_mR1 = vres(A.mR1), rs_mR2 = vres(A.mR2), rs_mW = vres(A.mW),
+                               rs_mW2 = vres(A.mW2), rs_mx = vres(A.mx), rs_mR3 = vres(A.mR3);
   auto issue_m = [&](int k, MinresStage<T>& S) {
-    const bool kv = k >= 0 && k <= G.nz;
+    const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + k * plane : 0;
-      const unsigned mv = A.mask[n];
+      const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
+      const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
+      const unsigned mv = bmask(gcol[sl], k, ok);
       S.m[sl] = ok ? mv : 7u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        S.y[sl][c] = A.mY[3 * n + c];
-        S.r1[sl][c] = A.mR1[3 * n + c];
-        S.r2[sl][c] = A.mR2[3 * n + c];
-      }
-      if (sl == 0) {  // the iterate and the directions: owner only, other threads read node 0
-        const int no = (own_plane && writer && ok) ? n : 0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          S.w[c] = A.mW[3 * no + c];
-          S.w2[c] = A.mW2[3 * no + c];
-          S.x[c] = A.mx[3 * no + c];
-        }
+      bload3(rs_mY, ob, S.y[sl]);
+      bload3(rs_mR1, ob, S.r1[sl]);
+      bload3(rs_mR2, ob, S.r2[sl]);
+      if (sl == 0) {  // the iterate and the directions: owner only
+        const uint32_t oo = (own_plane && writer && ok) ? ob : kOOR;
+        bload3(rs_mW, oo, S.w);
+        bload3(rs_mW2, oo, S.w2);
+        bload3(rs_mx, oo, S.x);
       }
     }
   };
@@ -633,15 +656,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int c = 0; c < 3; ++c) {
         const T r1m = itn >= 2 ? S.r1[sl][c] : (T)0;  // R1 holds no vector yet on the first iteration
         yn[c] = ms * S.y[sl][c] - mc1 * r1m - mas * S.r2[sl][c];
-        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : yn[c];
+        if (sl == 0 || has_extra) nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : yn[c];
       }
       if (sl == 0) {
         const bool owner = writer && own_plane;
-        const int64_t o = 3 * (int64_t)(owner ? gcol[0] + k * plane : 0);
-        T* const sink = A.sink + kSinkStride * tid;
-        T* r3o = owner ? A.mR3 + o : sink;
-        T* w2o = owner ? A.mW2 + o : sink + 3;
-        T* xo = owner ? A.mx + o : sink + 6;
+        const uint32_t ob = owner ? voff(gcol[0], k) : kOOR;
         T wn[3], xn[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -649,18 +668,17 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           const T wm = itn >= 3 ? S.w[c] : (T)0, w2m = itn >= 4 ? S.w2[c] : (T)0;
           wn[c] = (S.r1[0][c] * minvb - mwc1 * w2m - mwc2 * wm) * minvg;
           xn[c] = S.x[c] + mstep * wn[c];
-          if (owner) {
-            part[0] += (double)yn[c] * (double)yn[c];        // ||y||^2
-            part[2] += (double)S.r2[0][c] * (double)yn[c];   // <R2, y>: R1.R2 of iteration t + 1
+          if constexpr (NP >= 3) {
+            if (owner) {
+              part[0] += (double)yn[c] * (double)yn[c];        // ||y||^2
+              part[2] += (double)S.r2[0][c] * (double)yn[c];   // <R2, y>: R1.R2 of iteration t + 1
+            }
           }
         }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) r3o[c] = yn[c];
+        bstore3(rs_mR3, ob, yn);
         if (itn >= 2) {  // finishes iteration t - 1 (uniform)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) w2o[c] = wn[c];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) xo[c] = xn[c];
+          bstore3(rs_mW2, ob, wn);
+          bstore3(rs_mx, ob, xn);
         }
       }
     }
@@ -688,22 +706,25 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   // loads them at the output instead: the queue would not fit its registers.
   constexpr bool kOwnQ = sizeof(T) == 4 && (MODE == MODE_RESID || MODE == MODE_CG);
   T oq[2][NR][2][3];
+  __amdgpu_buffer_rsrc_t rs_f[NR], rs_cr[NR], rs_y[NR], rs_z[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    rs_f[r] = vres(A.f, r);
+    rs_cr[r] = vres(A.r, r);
+    rs_y[r] = vres(A.y, r);
+    rs_z[r] = vres(A.z, r);
+  }
+  const __amdgpu_buffer_rsrc_t rs_do = dres(A.invD_out);
   auto load_own = [&](int k, T (&q)[NR][2][3]) {
     const bool ok = gcol[0] >= 0 && k < kend;  // planes this block outputs
-    const int n = ok ? gcol[0] + k * plane : 0;
+    const uint32_t ob = ok ? voff(gcol[0], k) : kOOR;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      const int64_t o = (int64_t)(rhs0 + r) * G.ndof + 3 * n;
       if constexpr (MODE == MODE_RESID) {
-        const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // valid either way
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          q[r][0][c] = A.f[o + c];
-          q[r][1][c] = dsrc[c];
-        }
+        bload3(rs_f[r], ob, q[r][0]);
+        bload3(rs_d, A.invD ? ob : kOOR, q[r][1]);
       } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) q[r][0][c] = A.r[o + c];
+        bload3(rs_cr[r], ob, q[r][0]);
       }
     }
   };
@@ -800,16 +821,15 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     __syncthreads();
     {
       // every thread runs the output code; a thread that owns no output node
-      // reads its own LDS slots and a valid node, and stores to the sink
+      // reads its own LDS slots, loads and stores out of range
       const bool wr = emit && writer;
       const int n = wr ? gcol[0] + ez * plane : 0;
+      const uint32_t ob = wr ? voff(gcol[0], ez) : kOOR;
       const unsigned m = wr ? (mq & 0xffu) : 0u;
       const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - BX : tl, tlbb = wr ? tid - BX - 1 : tl;
-      T* const sink = A.sink + kSinkStride * tid;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const T* cr = corners + (cb * NR + r) * 9 * TS;
-        const int64_t o = (int64_t)(rhs0 + r) * G.ndof + 3 * n;
         T acc[3], pv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -837,15 +857,20 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
         auto own_only = [wr](double v) { return wr ? v : 0.0; };
         if constexpr (MODE == MODE_RESID) {
           const bool zout = A.invD || A.invD_out;
-          T* const yd = wr ? A.y + o : sink;
-          T* const zd = (wr && zout) ? A.z + o : sink + 3;
-          T fv[3], rv[3], dv[3];
+          T fv[3], rv[3], dv[3], dl[3], zv[3];
+          if constexpr (kOwnQ) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              fv[c] = oq[P][r][0][c];
+              dl[c] = oq[P][r][1][c];
+            }
+          } else {
+            bload3(rs_f[r], ob, fv);
+            bload3(rs_d, A.invD ? ob : kOOR, dl);
+          }
           const T D = ((dcol + dcorn[cb * TS + tl1]) + dcorn[cb * TS + tlb]) + dcorn[cb * TS + tlbb];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            const T* const dsrc = A.invD ? A.invD + 3 * n : A.f + o;  // valid either way
-            fv[c] = kOwnQ ? oq[P][r][0][c] : A.f[o + c];
-            const T dl = kOwnQ ? oq[P][r][1][c] : dsrc[c];
             rv[c] = fv[c] - acc[c];
             if (A.invD_out) {  // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements
               T d = (T)A.ke_diag * D;
@@ -855,19 +880,13 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
               if ((m >> c) & 1u) d = (T)1;
               dv[c] = d > (T)0 ? (T)1 / d : (T)0;
             } else {
-              dv[c] = dl;
+              dv[c] = dl[c];
             }
+            zv[c] = dv[c] * rv[c];
           }
-          T* const dd = (wr && A.invD_out) ? A.invD_out + 3 * n : sink + 6;  // sink + 6 .. 8
-          // one vector per output (the outputs may alias: sink)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) yd[c] = rv[c];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) zd[c] = dv[c] * rv[c];
-          if (A.invD_out) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) dd[c] = dv[c];
-          }
+          bstore3(rs_y[r], ob, rv);
+          bstore3(rs_z[r], zout ? ob : kOOR, zv);
+          if (A.invD_out) bstore3(rs_do, ob, dv);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             part[4 * r + 0] += own_only((double)rv[c] * (double)rv[c]);
@@ -875,18 +894,18 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
             part[4 * r + 2] += own_only((double)fv[c] * (double)fv[c]);
           }
         } else {
-          if constexpr (MODE == MODE_CGF) {
-            // the owner's store; other threads store out of range (dropped)
-            bstore3(rs_y, wr ? 12u * (uint32_t)n : kOOR, acc);
-          } else {
-            T* const yd = wr ? A.y + o : sink;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) yd[c] = acc[c];
-          }
+          bstore3(rs_y[r], ob, acc);
           if constexpr (MODE == MODE_CG) {
+            T rv3[3];
+            if constexpr (kOwnQ) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) rv3[c] = oq[P][r][0][c];
+            } else {
+              bload3(rs_cr[r], ob, rv3);
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-              const T rv = kOwnQ ? oq[P][r][0][c] : A.r[o + c];
+              const T rv = rv3[c];
               part[4 * r + 0] += own_only((double)rv * (double)pv[c]);      // r.z
               part[4 * r + 1] += own_only((double)acc[c] * (double)pv[c]);  // w.z
               part[4 * r + 2] += own_only((double)rv * (double)rv);         // r.r
@@ -1194,6 +1213,13 @@ static size_t apply_lds_bytes(int bx, int by) {
 // the busiest CU in wave-layers (each block: its waves x (layers + 1 for the
 // prologue)), with a floor of kMinWaves resident waves per round below which
 // latency, not issue, sets the time.
+// The z-march addresses each vector from the block's first plane with
+// 32-bit byte offsets: its planes (dz + 3 at most: the slab, the halo layer
+// below, the prefetched plane above) must span less than 2 GiB.
+bool apply_offsets_fit(const Geo& G, int dz, size_t value_bytes) {
+  return (int64_t)(3 * value_bytes) * G.nxn * G.nyn * (dz + 3) < ((int64_t)1 << 31);
+}
+
 template <typename T, int NR, int MODE>
 static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
   // fixed fields of a caller's override (FBTO_OPT_APPLY_TILE / _CGF_TILE)
@@ -1224,6 +1250,8 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
       const int tiles_y = (G.nyn + by - 2) / (by - 1);
       for (int dz = 1; dz <= std::min(G.nzn, 64); ++dz) {
         if (want_dz && dz != want_dz) continue;
+        // the planes a block reads, addressed by 32-bit byte offsets
+        if (!apply_offsets_fit(G, dz, sizeof(T))) continue;
         const int slabs = (G.nzn + dz - 1) / dz;
         const int64_t nb = (int64_t)tiles_x * tiles_y * slabs;
         if (nb > kApplyMaxBlocks) continue;
@@ -1399,7 +1427,6 @@ hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, con
   if constexpr (sizeof(T) == 8) {
     return hipErrorNotSupported;
   } else {
-    if (g->geo.ndof * (int64_t)sizeof(T) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;  // 32-bit buffer offsets
     ApplyArgs<T> A{};
     A.rho = rho;
     A.y = out.w;
