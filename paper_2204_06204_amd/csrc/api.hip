@@ -673,7 +673,6 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   g->max_partials = std::max(apply_max_blocks(G, g->n_cu), kMaxVecBlocks);
   SETUP_TRY(hipMalloc(&g->partials, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
   SETUP_TRY(hipMemset(g->partials, 0, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
-  SETUP_TRY(hipMalloc(&g->sink, kSinkBytes));
   SETUP_TRY(hipDeviceSynchronize());
 #undef SETUP_TRY
   *out = g;
@@ -758,7 +757,6 @@ fbto_status_t fbto_setup_grid_2d(const fbto_grid2d_desc_t* d, const uint8_t* fix
   g->max_partials = kMaxVecBlocks;
   SETUP_TRY(hipMalloc(&g->partials, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
   SETUP_TRY(hipMemset(g->partials, 0, (size_t)P_COUNT * 4 * g->max_partials * sizeof(double)));
-  SETUP_TRY(hipMalloc(&g->sink, kSinkBytes));
   SETUP_TRY(hipDeviceSynchronize());
 #undef SETUP_TRY
   *out = g;
@@ -769,7 +767,7 @@ fbto_status_t fbto_destroy_grid(fbto_grid_t g) {
   if (!g) return fail(FBTO_ERR_ARG, "grid handle is NULL");
   (void)hipDeviceSynchronize();
   void* ps[] = {g->mask, g->spring_dof, g->spring_k64, g->spring_k32, g->stencil_off,
-                g->stencil_w64, g->stencil_w32, g->sc, g->partials, g->sink, g->sort.base};
+                g->stencil_w64, g->stencil_w32, g->sc, g->partials, g->sort.base};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   free_vecs(g->v64);

@@ -117,7 +117,6 @@ enum PartSlot {
 };
 constexpr int kMaxVecBlocks = 1024;
 constexpr int kProjMaxPasses = 64;   // pass budget limit of the volume projection
-constexpr size_t kSinkBytes = 64 * 1024;  // scratch for stores of threads that own no output
 
 // Workspace vectors of one precision.  The CG vectors come in two sets:
 // the fused CG step reads one and writes the other (x of the second set is
@@ -199,7 +198,6 @@ struct fbto_grid_s {
   float* stencil_w32 = nullptr;
   fbto::Scalars* sc = nullptr;     // device
   double* partials = nullptr;      // device [P_COUNT][4][max_partials]
-  void* sink = nullptr;            // device [kSinkBytes]: stores of apply threads without an output
   int max_partials = 0;
   fbto::Vecs v64, v32;
   int device = 0;

@@ -111,7 +111,6 @@ enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4
 constexpr int kApplyMaxThreads = 512;
 constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
-constexpr int kSinkStride = 16;  // sink entries per thread
 constexpr double kTinyNorm = 1e-30;  // Krylov step: a norm below this is zero (FP32 reciprocals stay finite)
 
 // Bits 3 R + 1 for R < nr: the |r|_inf entries (max-reduced) of the
@@ -122,7 +121,6 @@ constexpr unsigned rinf_mask(int nr) {
   for (int R = 0; R < nr; ++R) m |= 1u << (3 * R + 1);
   return m;
 }
-static_assert(kApplyMaxThreads * kSinkStride * sizeof(double) <= kSinkBytes, "sink too small");
 
 template <typename T>
 struct ApplyArgs {
@@ -137,7 +135,6 @@ struct ApplyArgs {
   T* z;                // RESID: z = D^-1 r
   const T* r;          // CG: current residual (for r.z, r.r)
   const uint8_t* mask; // bits 0-2: fixed DOFs of the node; bit 3: the node has a spring
-  T* sink;             // [kApplyMaxThreads * kSinkStride]: stores of threads without an owned node
   Modal<T> km;
   Simp sp;
   int nspring;
@@ -290,6 +287,54 @@ struct MinresStage {
   unsigned m[2];
 };
 
+// Buffer access of the z-march kernels.  A resource spans 2^31 - 1 bytes
+// from its base; kOOR, and kOOR plus the 8 and 16 bytes of an FP64 triple's
+// later values, lie beyond it, so an access there loads 0 or is dropped
+// without a cache request.
+constexpr uint32_t kOOR = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t zrsrc(const void* p) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
+}
+typedef float zf3 __attribute__((ext_vector_type(3)));
+typedef unsigned zu3 __attribute__((ext_vector_type(3)));
+typedef unsigned zu2 __attribute__((ext_vector_type(2)));
+template <typename T>
+__device__ __forceinline__ void zload3(__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) {
+  if constexpr (sizeof(T) == 4) {
+    const zf3 t = __builtin_bit_cast(zf3, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+    v[0] = t.x;
+    v[1] = t.y;
+    v[2] = t.z;
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8u * c, 0, 0));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void zstore3(__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) {
+  if constexpr (sizeof(T) == 4) {
+    zu3 t;
+    t.x = __builtin_bit_cast(unsigned, v[0]);
+    t.y = __builtin_bit_cast(unsigned, v[1]);
+    t.z = __builtin_bit_cast(unsigned, v[2]);
+    __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, 0);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(zu2, v[c]), rs, off + 8u * c, 0, 0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ T zload1(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+  if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+  else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void zstore1(__amdgpu_buffer_rsrc_t rs, uint32_t off, T v) {
+  if constexpr (sizeof(T) == 4) __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rs, off, 0, 0);
+  else __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(zu2, v), rs, off, 0, 0);
+}
+
 // A value that is the same in every lane of the wave, kept in a scalar
 // register (FP32; FP64 values stay in vector registers).
 template <typename T>
@@ -360,14 +405,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   // node uses, outputs of a thread that owns none -- passes an out-of-range
   // offset: its load returns 0 and its store is dropped, without a cache
   // request, while every memory instruction is still issued unconditionally.
-  // out-of-range offset: the resources span 2^31 - 1 bytes, and kOOR plus the
-  // 8 and 16 of an FP64 triple's later values stays above that (no wrap to 0)
-  constexpr uint32_t kOOR = 0x80000000u;
   const int64_t pbase = (int64_t)ez0 * plane;               // first node of plane ez0
   const int64_t vbase = (int64_t)rhs0 * G.ndof + 3 * pbase;  // its first value in RHS rhs0
-  auto rsrc = [](const void* p) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
-  };
+  auto rsrc = [](const void* p) { return zrsrc(p); };
   auto vres = [&](const T* v, int r = 0) { return rsrc(v ? v + vbase + (int64_t)r * G.ndof : v); };  // [nrhs][3N]
   auto dres = [&](const T* v) { return rsrc(v ? v + 3 * pbase : v); };  // [3N], one set
   // byte offset of the first value of node column `col` in plane k (k >= ez0)
@@ -375,34 +415,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     return (uint32_t)(3 * sizeof(T)) * (uint32_t)(col + (k - ez0) * plane);
   };
   const __amdgpu_buffer_rsrc_t rs_m = rsrc(A.mask + pbase);
-  auto bload3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) {
-    if constexpr (sizeof(T) == 4) {
-      typedef float f3v __attribute__((ext_vector_type(3)));
-      const f3v t = __builtin_bit_cast(f3v, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
-      v[0] = t.x;
-      v[1] = t.y;
-      v[2] = t.z;
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        v[c] = __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs, off + 8u * c, 0, 0));  // a 2-dword vector
-    }
-  };
-  typedef unsigned u2v __attribute__((ext_vector_type(2)));
-  auto bstore3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) {
-    if constexpr (sizeof(T) == 4) {
-      typedef unsigned u3v __attribute__((ext_vector_type(3)));
-      u3v t;
-      t.x = __builtin_bit_cast(unsigned, v[0]);
-      t.y = __builtin_bit_cast(unsigned, v[1]);
-      t.z = __builtin_bit_cast(unsigned, v[2]);
-      __builtin_amdgcn_raw_buffer_store_b96(t, rs, off, 0, 0);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2v, v[c]), rs, off + 8u * c, 0, 0);
-    }
-  };
+  auto bload3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, T (&v)[3]) { zload3<T>(rs, off, v); };
+  auto bstore3 = [](__amdgpu_buffer_rsrc_t rs, uint32_t off, const T (&v)[3]) { zstore3<T>(rs, off, v); };
   // the mask byte of a node (kOOR: 0)
   auto bmask = [&](int col, int k, bool ok) -> unsigned {
     return __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? (uint32_t)(col + (k - ez0) * plane) : kOOR, 0, 0);
@@ -460,10 +474,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   auto load_rho = [&](int ez) -> T {
     const bool el = col_elem && ez >= 0 && ez < G.nz && ez < kend;  // element layers of this block
     const uint32_t off = el ? (uint32_t)sizeof(T) * (uint32_t)(ex + G.nx * (ey + G.ny * (ez - ez0))) : kOOR;
-    if constexpr (sizeof(T) == 4)
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(rs_rho, off, 0, 0));
-    else
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(rs_rho, off, 0, 0));
+    return zload1<T>(rs_rho, off);
   };
   auto scale_of = [&](int ez, T rv) -> T {
     const bool el = col_elem && ez >= 0 && ez < G.nz;
@@ -1029,10 +1040,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int plane = G.nxn * G.nyn;
   const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
   const bool elem_owner = writer && ex < G.nx && ey < G.ny;
-  // As in k_apply, every load and store of the z-march is issued without a
-  // branch around it: threads without a far node restage their own node,
-  // planes past the slab are loaded and staged but never read, and stores
-  // without an owner go to the sink.
+  // As in k_apply, the vectors are addressed through buffer resources based
+  // at the block's first plane ez0: a thread without a far node, a plane past
+  // the slab or a thread that owns no node gets an out-of-range offset, so its
+  // loads return 0 and its stores are dropped, with no branch around them.
   const bool has_extra = tid <= BX + BY;
   int li[2], gcol[2];
   li[0] = tx + NW * ty;
@@ -1044,7 +1055,17 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     li[1] = has_extra ? lx + NW * ly : li[0];
     gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
   }
-  T* const sink = A.sink + kSinkStride * tid;
+  const int64_t pbase = (int64_t)ez0 * plane;  // first node of plane ez0
+  auto vres = [&](const T* v) { return zrsrc(v ? v + 3 * pbase : v); };
+  auto voff = [&](int col, int k) -> uint32_t {
+    return (uint32_t)(3 * sizeof(T)) * (uint32_t)(col + (k - ez0) * plane);
+  };
+  const __amdgpu_buffer_rsrc_t rs_m = zrsrc(A.mask + pbase), rs_x = vres(A.xi), rs_r = vres(A.ri),
+                               rs_d = vres(A.invD), rs_p = vres(A.pi), rs_w = vres(A.wi), rs_s = vres(A.si),
+                               rs_f = vres(A.fvec), rs_xo = vres(A.xo);
+  const int64_t ebase = (int64_t)ez0 * G.nx * G.ny;  // first element of layer ez0
+  const __amdgpu_buffer_rsrc_t rs_rho = zrsrc(A.rho + ebase), rs_hs = zrsrc(A.Hsi ? A.Hsi + ebase : A.Hsi),
+                               rs_do = zrsrc(A.dobj + ebase);
 
   // step coefficients (every block, same order; called after the first
   // planes' loads are issued, so the two latencies overlap)
@@ -1060,46 +1081,35 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     double alpha, beta;
     cg_coefficients(pre[0], pre[1], pre[2], pre[3], 0, A.step, A.rtol, const_cast<Scalars*>(A.sc),
                     lb == 0 && tid == 0, alpha, beta);
-    al = (T)alpha;
-    be = (T)beta;
+    al = wave_uniform((T)alpha);
+    be = wave_uniform((T)beta);
   };
   double part[3] = {0.0, 0.0, 0.0};  // r'.r', max|r'|, f.x'
 
+  auto owns = [&](int k) { return k >= 0 && k <= G.nz && writer && k >= k0 && k < kend; };
   auto issue = [&](int k, SensStage<T>& S) {
-    const int kc = k < kend ? k : kend;  // planes past kend are never read: re-load plane kend
-    const bool kv = kc >= 0 && kc <= G.nz;
-    const bool own = k >= 0 && k <= G.nz && writer && k >= k0 && k < kend;
+    const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes past kend are never read
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
-      const bool ok = kv && gcol[sl] >= 0;
-      const int n = ok ? gcol[sl] + kc * plane : 0;
-      const unsigned mv = A.mask[n];
+      const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
+      const uint32_t off = ok ? voff(gcol[sl], k) : kOOR;
+      const unsigned mv = __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? (uint32_t)(gcol[sl] + (k - ez0) * plane) : kOOR, 0, 0);
       S.m[sl] = ok ? mv : 7u;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        S.x[sl][c] = A.xi[3 * n + c];
-        S.r[sl][c] = A.ri[3 * n + c];
-        S.d[sl][c] = A.invD[3 * n + c];
-        const T pv = A.pi[3 * n + c];  // allocated on the first step too, its contents unused
-        S.p[sl][c] = first ? (T)0 : pv;
-      }
-      if (sl == 0) {  // used by the owner only: other threads all read node 0 (one cached line)
-        const int no = own ? n : 0;
-        const T* const fsrc = A.fvec ? A.fvec + 3 * no : A.wi + 3 * no;  // valid either way
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          S.w[c] = A.wi[3 * no + c];
-          const T sv = A.si[3 * no + c];
-          S.s[c] = first ? (T)0 : sv;
-          const T fv = fsrc[c];
-          S.f[c] = A.fvec ? fv : (T)0;
-        }
+      zload3<T>(rs_x, off, S.x[sl]);
+      zload3<T>(rs_r, off, S.r[sl]);
+      zload3<T>(rs_d, off, S.d[sl]);
+      zload3<T>(rs_p, first ? kOOR : off, S.p[sl]);  // allocated on the first step too, its contents unused
+      if (sl == 0) {  // used by the owner only
+        const uint32_t oo = owns(k) ? off : kOOR;
+        zload3<T>(rs_w, oo, S.w);
+        zload3<T>(rs_s, first ? kOOR : oo, S.s);
+        zload3<T>(rs_f, A.fvec ? oo : kOOR, S.f);
       }
     }
   };
   auto stage = [&](const SensStage<T>& S, int buf, int k) {
     T* nb = nodes + buf * (3 * NS);
-    const bool own = k >= 0 && k <= G.nz && writer && k >= k0 && k < kend;
+    const bool own = owns(k);
 #pragma unroll
     for (int sl = 0; sl < 2; ++sl) {
       T xn[3];
@@ -1107,12 +1117,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int c = 0; c < 3; ++c) {
         const T pn = S.d[sl][c] * S.r[sl][c] + be * S.p[sl][c];
         xn[c] = S.x[sl][c] + al * pn;
-        nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : xn[c];
+        if (sl == 0 || has_extra) nb[c * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : xn[c];
       }
       if (sl == 0) {
-        T* const xo = own ? A.xo + 3 * (gcol[0] + k * plane) : sink;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
+        zstore3<T>(rs_xo, own ? voff(gcol[0], k) : kOOR, xn);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           const T rn = S.r[0][c] - al * (S.w[c] + be * S.s[c]);
@@ -1133,13 +1141,17 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int c = 0; c < 3; ++c) u4[a][c] = nb[c * NS + li[0] + o4[a]];
     face_modes(u4, F);
   };
+  // byte offset of the element of layer ez in this thread's column (kOOR if
+  // the element is not this block's)
+  auto eoff = [&](int ez) -> uint32_t {
+    const bool el = elem_owner && ez >= k0 && ez < elem_end;
+    return el ? (uint32_t)sizeof(T) * (uint32_t)(ex + G.nx * (ey + G.ny * (ez - ez0))) : kOOR;
+  };
   // density and 1/Hs of the element of a layer, loaded a layer ahead
-  const bool col_elem = elem_owner;
   auto load_elem = [&](int ez, T (&v)[2]) {
-    const bool el = col_elem && ez >= k0 && ez < elem_end;
-    const int e = el ? ex + G.nx * (ey + G.ny * ez) : 0;
-    v[0] = A.rho[e];
-    const T hv = (A.Hsi ? A.Hsi : A.rho)[e];  // valid either way
+    const uint32_t off = eoff(ez);
+    v[0] = zload1<T>(rs_rho, off);
+    const T hv = zload1<T>(rs_hs, A.Hsi ? off : kOOR);
     v[1] = A.Hsi ? hv : (T)1;
   };
 
@@ -1165,7 +1177,6 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     issue(ez + 2, S);
     read_face((ez + 1) & 1, F[P ^ 1]);
     {
-      const bool el = elem_owner && ez >= k0 && ez < elem_end;
       T c[3][8], z[3][8];
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
@@ -1182,10 +1193,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int q = 1; q < 8; ++q) en += (double)c[i][q] * (double)z[i][q];
-      const int e = el ? ex + G.nx * (ey + G.ny * ez) : 0;
       const double val = -(double)simp_ds<T>(ev[P][0], A.sp) * en * (double)ev[P][1];
-      T* const dst = el ? A.dobj + e : sink + 3;
-      *dst = (T)val;
+      zstore1<T>(rs_do, eoff(ez), (T)val);
     }
     stage(S, ez & 1, ez + 2);
     __syncthreads();
@@ -1209,10 +1218,6 @@ static size_t apply_lds_bytes(int bx, int by) {
   return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by + 2 * bx * by);
 }
 
-// Tile shape and slab depth for one apply variant.  The cost is the work of
-// the busiest CU in wave-layers (each block: its waves x (layers + 1 for the
-// prologue)), with a floor of kMinWaves resident waves per round below which
-// latency, not issue, sets the time.
 // The z-march addresses each vector from the block's first plane with
 // 32-bit byte offsets: its planes (dz + 3 at most: the slab, the halo layer
 // below, the prefetched plane above) must span less than 2 GiB.
@@ -1220,6 +1225,10 @@ bool apply_offsets_fit(const Geo& G, int dz, size_t value_bytes) {
   return (int64_t)(3 * value_bytes) * G.nxn * G.nyn * (dz + 3) < ((int64_t)1 << 31);
 }
 
+// Tile shape and slab depth for one apply variant.  The cost is the work of
+// the busiest CU in wave-layers (each block: its waves x (layers + 1 for the
+// prologue)), with a floor of kMinWaves resident waves per round below which
+// latency, not issue, sets the time.
 template <typename T, int NR, int MODE>
 static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
   // fixed fields of a caller's override (FBTO_OPT_APPLY_TILE / _CGF_TILE)
@@ -1332,7 +1341,6 @@ static hipError_t launch_apply_mode(fbto_grid_s* g, ApplyArgs<T> A, int nrhs, hi
   A.P = g->partials;
   A.maxp = g->max_partials;
   A.sc = g->sc;
-  A.sink = static_cast<T*>(g->sink);
   // one RHS per launch: the per-RHS state of the z-march (two face-mode
   // sets, the modal carry, staged loads) fills the register file at NR = 1
   hipError_t e = hipSuccess;
@@ -1419,7 +1427,6 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
   A.xo = x;
   A.dobj = dobj;
   A.Hsi = Hsi;
-  A.sink = static_cast<T*>(g->sink);
   A.fvec = f;
   A.step = step;
   A.n_apply = n_apply;
