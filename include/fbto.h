@@ -377,12 +377,16 @@ fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, cons
  *                         status says the budget ran out.
  *   FBTO_OPT_APPLY_TILE   tile of the z-marching K(rho)u kernels (apply,
  *   FBTO_OPT_CGF_TILE     residual and CG products; the fused CG step):
- *                         bx | by << 8 | dz << 16 (threads per tile row and
- *                         column, 8 <= bx <= 64, 4 <= by <= 64,
- *                         128 <= bx * by <= 256, slab depth dz 1 .. 64; a
- *                         zero field is chosen by the cost model), or 0 for
- *                         the cost model alone.  A shape the kernel cannot
- *                         run makes the next launch fail (FBTO_ERR_HIP).
+ *                         bx | by << 8 | dz << 16 | cap << 24 (threads per
+ *                         tile row and column, 8 <= bx <= 64,
+ *                         4 <= by <= 64, 128 <= bx * by <= 256, slab depth
+ *                         dz 1 .. 64; a zero field is chosen by the cost
+ *                         model; cap 2 .. 15 limits the blocks resident on
+ *                         a CU by the LDS each block requests, 0 leaves
+ *                         them to the registers and LDS the kernel needs),
+ *                         or 0 for the built-in choice.  A shape the kernel
+ *                         cannot run makes the next launch fail
+ *                         (FBTO_ERR_HIP).
  * Errors: FBTO_ERR_ARG for an unknown option or a value out of range. */
 typedef enum fbto_option {
   FBTO_OPT_PROJ_PASSES = 0,

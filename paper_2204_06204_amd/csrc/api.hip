@@ -650,6 +650,9 @@ fbto_status_t fbto_setup_grid(const fbto_grid_desc_t* d, const uint8_t* fixed_do
   int ncu = 0;
   SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device));
   g->n_cu = ncu > 0 ? ncu : 256;
+  int lds_cu = 0;
+  SETUP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
+  g->lds_per_cu = lds_cu > 0 ? lds_cu : 160 * 1024;
   SETUP_TRY(hipMalloc(&g->mask, N));
   SETUP_TRY(hipMemcpy(g->mask, nm.data(), N, hipMemcpyHostToDevice));
   g->n_springs = n_springs;
@@ -750,6 +753,9 @@ fbto_status_t fbto_setup_grid_2d(const fbto_grid2d_desc_t* d, const uint8_t* fix
   int ncu = 0;
   SETUP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, g->device));
   g->n_cu = ncu > 0 ? ncu : 256;
+  int lds_cu = 0;
+  SETUP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, g->device));
+  g->lds_per_cu = lds_cu > 0 ? lds_cu : 160 * 1024;
   SETUP_TRY(hipMalloc(&g->mask, N));
   SETUP_TRY(hipMemcpy(g->mask, nm.data(), N, hipMemcpyHostToDevice));
   SETUP_TRY(hipMalloc(&g->sc, sizeof(Scalars)));
@@ -787,10 +793,14 @@ fbto_status_t fbto_set_option(fbto_grid_t g, fbto_option_t option, int64_t value
       return ok();
     case FBTO_OPT_APPLY_TILE:
     case FBTO_OPT_CGF_TILE: {
-      if (value < 0 || value >= ((int64_t)1 << 24)) return fail(FBTO_ERR_ARG, "tile value %lld out of range", (long long)value);
+      if (value < 0 || value >= ((int64_t)1 << 28)) return fail(FBTO_ERR_ARG, "tile value %lld out of range", (long long)value);
       const int bx = (int)(value & 0xff), by = (int)((value >> 8) & 0xff), dz = (int)((value >> 16) & 0xff);
+      const int cap = (int)((value >> 24) & 0xf);
       if ((bx && (bx < 8 || bx > 64)) || (by && (by < 4 || by > 64)) || dz > 64 || (bx && by && (bx * by < 128 || bx * by > 256)))
         return fail(FBTO_ERR_ARG, "tile %d x %d x %d outside the kernel's limits", bx, by, dz);
+      if (cap && (cap < 2 || lds_for_block_cap(g->lds_per_cu, cap) > (int)kApplyMaxLds))
+        return fail(FBTO_ERR_ARG, "blocks per CU %d: not 2 or more, or needs more than %d bytes of LDS per block", cap,
+                    (int)kApplyMaxLds);
       g->tile_override[option == FBTO_OPT_CGF_TILE ? 1 : 0] = (int)value;
       for (auto& a : g->tiles)  // chosen again on the next launch
         for (auto& b : a)

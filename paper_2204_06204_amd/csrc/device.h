@@ -79,29 +79,35 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV]) {
 // Reduce NV arrays of per-block partials (entry i: n[i] values at src[i];
 // sum, or max where bit i of MAXMASK is set).  Every block computes the same
 // result in the same order; the producing kernel has finished, so plain
-// loads see its stores.
+// loads see its stores.  Each round loads two entries per thread of every
+// array before folding any, so that the arrays cost one memory latency per
+// round, not one each.
 template <int NV, unsigned MAXMASK>
 __device__ __forceinline__ void reduce_parts(double (&v)[NV], const double* const (&src)[NV],
                                              const int (&n)[NV]) {
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   const int nthr = blockDim.x * blockDim.y * blockDim.z;
-  // four strided loads in flight per thread and array, folded in a fixed order
+  int nmax = 0;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    const bool is_max = (MAXMASK >> i) & 1u;
-    const double id = is_max ? -INFINITY : 0.0;
-    double acc = id;
-    for (int k = tid; k < n[i]; k += 4 * nthr) {
-      double x[4];
+    nmax = n[i] > nmax ? n[i] : nmax;
+    v[i] = ((MAXMASK >> i) & 1u) ? -INFINITY : 0.0;
+  }
+  for (int k = tid; k - tid < nmax; k += 2 * nthr) {
+    double x[NV][2];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+    for (int i = 0; i < NV; ++i) {
+      const double id = ((MAXMASK >> i) & 1u) ? -INFINITY : 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
         const int kk = k + u * nthr;
-        x[u] = kk < n[i] ? src[i][kk] : id;
+        x[i][u] = kk < n[i] ? src[i][kk] : id;
       }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc = is_max ? fmax(acc, x[u]) : acc + x[u];
     }
-    v[i] = acc;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) v[i] = ((MAXMASK >> i) & 1u) ? fmax(v[i], x[i][u]) : v[i] + x[i][u];
   }
   block_reduce<NV, MAXMASK>(v);
 }

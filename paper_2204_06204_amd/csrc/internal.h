@@ -150,7 +150,14 @@ struct CgSet {
 // Tile shape and slab depth of one apply variant (chosen once per grid).
 struct TileChoice {
   int bx, by, dz, tiles_x, tiles_y, slabs, nblocks;
+  int cap;  // resident blocks per CU at most (0: as the registers and LDS allow)
 };
+
+constexpr size_t kApplyMaxLds = 64 * 1024;  // LDS of one z-march block at most
+
+// LDS a block requests so that at most `cap` blocks fit on a CU with
+// lds_per_cu bytes (allocation granule 512 bytes).
+constexpr int lds_for_block_cap(int lds_per_cu, int cap) { return (lds_per_cu / (cap + 1) / 512 + 1) * 512; }
 
 struct StencilPt {
   int dx, dy, dz;
@@ -202,6 +209,7 @@ struct fbto_grid_s {
   fbto::Vecs v64, v32;
   int device = 0;
   int n_cu = 256;
+  int lds_per_cu = 160 * 1024;
   int n_gsum = 0;                        // blocks of the last filter launch that left a sum
   fbto::TileChoice tiles[2][2][6] = {};  // apply tiling by [FP64][NR - 1][mode], chosen on first use
   int tile_override[2] = {0, 0};         // FBTO_OPT_APPLY_TILE, FBTO_OPT_CGF_TILE (0: cost model)

@@ -109,7 +109,6 @@ static int flat_grid(int64_t n) {
 //          other Y buffer.
 enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_CG = 2, MODE_CGF = 3, MODE_SENSF = 4, MODE_MRF = 5 };
 constexpr int kApplyMaxThreads = 512;
-constexpr size_t kApplyMaxLds = 64 * 1024;
 constexpr int kApplyMaxBlocks = 8192;
 constexpr double kTinyNorm = 1e-30;  // Krylov step: a norm below this is zero (FP32 reciprocals stay finite)
 
@@ -343,8 +342,16 @@ __device__ __forceinline__ T wave_uniform(T v) {
   else return v;
 }
 
+// Waves per SIMD the register allocation of a z-march variant must allow:
+// three for the single-RHS FP32 fused steps (at most 168 VGPRs), which run
+// many blocks per CU on large grids; the others are left to the compiler.
 template <typename T, int NR, int MODE>
-__global__ void __launch_bounds__(kApplyMaxThreads)
+constexpr int apply_min_waves() {
+  return (sizeof(T) == 4 && NR == 1 && (MODE == MODE_CGF || MODE == MODE_MRF)) ? 3 : 1;
+}
+
+template <typename T, int NR, int MODE>
+__global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_per_eu(apply_min_waves<T, NR, MODE>())))
     k_apply(ApplyArgs<T> A, int rhs0) {
   extern __shared__ __align__(16) unsigned char apply_smem[];
   const int b = blockIdx.x;
@@ -485,6 +492,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   static_assert(MODE != MODE_MRF || NR == 1, "the fused MINRES step handles one RHS per launch");
   constexpr int NP = MODE == MODE_APPLY ? 1 : 4 * NR;  // partial values per block
   double part[NP];
+  // fused CG step: r.z and r.r (sums of non-negative terms) and max|r| of
+  // the thread's owned nodes, at most 3 (dz + 1) terms, accumulate in T and
+  // join the FP64 partials before the block reduction
+  T cpart[3] = {(T)0, (T)0, (T)0};
 #pragma unroll
   for (int i = 0; i < NP; ++i) part[i] = 0.0;
 
@@ -556,12 +567,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
           zq[c] = zn;  // unmasked: the output of a fixed DOF
           pn[c] = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
           xn[c] = S.x[c] + al * pn[c];
-          if constexpr (NP >= 4) {
-            if (owner) {
-              part[0] += (double)rn[c] * (double)zn;  // r.z
-              part[2] += (double)rn[c] * (double)rn[c];  // r.r
-              part[3] = fmax(part[3], fabs((double)rn[c]));
-            }
+          if (owner) {
+            cpart[0] += rn[c] * zn;     // r.z
+            cpart[1] += rn[c] * rn[c];  // r.r
+            cpart[2] = fmax(cpart[2], fabs(rn[c]));
           }
         }
       }
@@ -956,6 +965,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       dst[4 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
       dst[4 * r + 3] = pslot(A.P, P_RI0 + par, rhs0 + r, A.maxp);
     }
+    if constexpr (MODE == MODE_CGF) {
+      part[0] = (double)cpart[0];
+      part[2] = (double)cpart[1];
+      part[3] = (double)cpart[2];
+    }
     write_parts<4 * NR, 0x8888u>(part, dst, lb);
   }
   if constexpr (MODE == MODE_MRF) {
@@ -1230,7 +1244,7 @@ bool apply_offsets_fit(const Geo& G, int dz, size_t value_bytes) {
 // prologue)), with a floor of kMinWaves resident waves per round below which
 // latency, not issue, sets the time.
 template <typename T, int NR, int MODE>
-static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
+static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int override_shape) {
   // fixed fields of a caller's override (FBTO_OPT_APPLY_TILE / _CGF_TILE)
   const int want_bx = override_shape & 0xff, want_by = (override_shape >> 8) & 0xff,
             want_dz = (override_shape >> 16) & 0xff;
@@ -1238,15 +1252,18 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
   TileChoice best{};
   double best_cost = 1e300;
   // The fused steps on large grids (2^22 elements and more): rows of 32
-  // node columns and 6 rows, slabs of 33 layers.  A wave then stages two
-  // contiguous 384-byte runs per vector, and the L1 path, which bounds these
-  // steps there, carries fewer partial lines.  Measured against the cost
-  // model's choice: 167 against 223 us at 256x128x128, 513 against 550 us at
-  // 384x192x192 (FP32 CG step); on smaller grids the model's tiles win.
+  // node columns and 6 rows, slabs of 33 layers; the CG step with at most
+  // two blocks per CU.  A wave then stages two contiguous 384-byte runs per
+  // vector, and the L1 path, which bounds these steps there, carries fewer
+  // partial lines.  Measured (FP32): the CG step takes 163 us at
+  // 256x128x128 and 518 us at 384x192x192, against 172 and 557 us with the
+  // same tiles and as many blocks as fit (four), and 223 and 550 us with the
+  // cost model's choice; the MINRES step 147 and 500 us, against 172 and
+  // 537 us with the cap of two.  On smaller grids the model's tiles win.
   if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
     if (override_shape == 0 && G.E >= ((int64_t)1 << 22)) {
-      const int bx = 32, by = 6, dz = std::min(33, G.nzn);
-      const size_t lds = apply_lds_bytes<T, NR>(bx, by);
+      const int bx = 32, by = 6, dz = std::min(33, G.nzn), cap = MODE == MODE_CGF ? 2 : 0;
+      const size_t lds = std::max(apply_lds_bytes<T, NR>(bx, by), cap ? (size_t)lds_for_block_cap(lds_per_cu, cap) : 0);
       int occ = 0;
       const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, 64 * 3, lds);
       const int tiles_x = (G.nxn + bx - 2) / (bx - 1), tiles_y = (G.nyn + by - 2) / (by - 1);
@@ -1254,7 +1271,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
       const int64_t nb = (int64_t)tiles_x * tiles_y * slabs;
       if (oe == hipSuccess && occ >= 1 && lds <= kApplyMaxLds && nb <= kApplyMaxBlocks &&
           apply_offsets_fit(G, dz, sizeof(T)))
-        return TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb};
+        return TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb, cap};
     }
   }
   for (int bx = 8; bx <= 64; ++bx) {
@@ -1295,7 +1312,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int override_shape) {
                             (rem ? std::max((double)rem * w, kMinWaves) * layers : 0.0);
         if (cost < best_cost) {
           best_cost = cost;
-          best = TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb};
+          best = TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb, (override_shape >> 24) & 0xf};
         }
       }
     }
@@ -1308,7 +1325,7 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
                                  int* nb_out) {
   TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][NR - 1][MODE];
   if (t.nblocks == 0) {
-    t = choose_tile<T, NR, MODE>(g->geo, g->n_cu, g->tile_override[MODE == MODE_CGF ? 1 : 0]);
+    t = choose_tile<T, NR, MODE>(g->geo, g->n_cu, g->lds_per_cu, g->tile_override[MODE == MODE_CGF ? 1 : 0]);
     if (t.nblocks == 0) return hipErrorInvalidConfiguration;
   }
   if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
@@ -1323,7 +1340,8 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
   A.nblocks = t.nblocks;
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
-  const size_t lds = apply_lds_bytes<T, NR>(t.bx, t.by);
+  size_t lds = apply_lds_bytes<T, NR>(t.bx, t.by);
+  if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
   const int threads = (t.bx * t.by + 63) / 64 * 64;  // whole waves
   hipLaunchKernelGGL((k_apply<T, NR, MODE>), dim3(grid), dim3(threads), lds, st, A, rhs0);
   return hipGetLastError();
@@ -1408,7 +1426,7 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
                           int* nb_out) {
   TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][0][MODE_SENSF];
   if (t.nblocks == 0) {
-    t = choose_tile<T, 1, MODE_SENSF>(g->geo, g->n_cu, g->tile_override[0]);
+    t = choose_tile<T, 1, MODE_SENSF>(g->geo, g->n_cu, g->lds_per_cu, g->tile_override[0]);
     if (t.nblocks == 0) return hipErrorInvalidConfiguration;
   }
   if (t.nblocks > g->max_partials) return hipErrorInvalidValue;
@@ -1442,7 +1460,8 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
   const int threads = (t.bx * t.by + 63) / 64 * 64;
-  const size_t lds = sens_lds_bytes<T>(t.bx, t.by);
+  size_t lds = sens_lds_bytes<T>(t.bx, t.by);
+  if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
   hipLaunchKernelGGL((k_cg_sens<T>), dim3(grid), dim3(threads), lds, st, A);
   return hipGetLastError();
 }

@@ -358,3 +358,40 @@ def test_nonfinite_load_is_reported(dtype):
     u.zero_()
     g.outer_step(x, u, dev(f, dtype), 1, 1e-3, 5, 0.0, p.vmax, info=info)
     assert host(info)[6] == 6.0
+
+
+@pytest.mark.parametrize("tile", [(11, 23, 5, 0), (32, 6, 3, 2), (16, 8, 9, 3), (64, 4, 1, 0)])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_pcg_tile_override_matches_oracle(tile, dtype):
+    """Tile shapes, slab depths and block caps set by fbto_set_option change
+    the layout of the z-march only: the PCG iterate still follows the
+    oracle's recurrence (a grid of several tiles and slabs, ragged in x, y
+    and z for every shape)."""
+    bx, by, dz, cap = tile
+    say(f"pcg tile {tile} {dtype}")
+    p = synth.cantilever(45, 14, 10, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=6)
+    og, g, rho_t, s, K, D = _setup(p, dtype, 6)
+    value = bx | (by << 8) | (dz << 16) | (cap << 24)
+    g.set_option("cgf_tile", value)
+    g.set_option("apply_tile", value)
+    f = p.loads[0]
+    u_t = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    m = 7
+    g.inner_solve(rho_t, dev(f, dtype), u_t, m, info=info)
+    u_ref, r_ref = oracle.pcg_ref(lambda v: K @ v, D, f, np.zeros(p.ndof), m)
+    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    assert np.abs(host(u_t) - u_ref).max() <= tol * np.abs(u_ref).max()
+    assert host(info)[3] == m
+
+
+def test_tile_option_limits():
+    from paper_2204_06204_amd._lib import FbtoError
+    p = synth.cantilever(8, 4, 4, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=2, seed=1)
+    from paper_2204_06204_amd.grid import Grid
+    g = Grid.from_problem(p)
+    for bad in (7, 65, 8 | (4 << 8), 16 | (65 << 8), 16 | (16 << 8) | (65 << 16), 1 << 24, 1 << 28, -1):
+        with pytest.raises(FbtoError):
+            g.set_option("cgf_tile", bad)
+    g.set_option("cgf_tile", 16 | (16 << 8) | (4 << 16) | (2 << 24))
+    g.close()
