@@ -1673,11 +1673,16 @@ __global__ void __launch_bounds__(kVecBlock)
   write_parts<2 * NR + 1, 0xAAAu>(v, dst, blockIdx.x);
 }
 
+// Threads of the one-block finishing kernels: a block of 256 measured twice
+// as fast as one of 1024 for the few thousand partials they reduce (fewer
+// waves meet at each barrier).
+constexpr int kFinishThreads = 256;
+
 // Reduce the final residual norms into the scalars (slots RN1, RI1 with n_r
 // partials, f.f from FN); with `info`, also write the outer-iteration record
 // (compliance from DOT, projection results, gradient mean).
 template <int NR>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(kFinishThreads)
     k_pcg_finish(const double* P, int maxp, int n_r, int n_fn, Scalars* sc, double* info, int n_dot, int n_e,
                  int n_gsum, int64_t E) {
   double v[3 * NR + 4];
@@ -1779,7 +1784,7 @@ hipError_t launch_cg_step(fbto_grid_s* g, const T* x_in, T* x, T* r, const T* z_
 }
 hipError_t launch_pcg_finish(fbto_grid_s* g, int nrhs, int n_r, int n_fn, double* info, int n_dot, int n_e,
                              int n_gsum, hipStream_t st) {
-  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_finish<NR>), dim3(1), dim3(1024), 0, st,
+  FBTO_NR_DISPATCH(nrhs, hipLaunchKernelGGL((k_pcg_finish<NR>), dim3(1), dim3(kFinishThreads), 0, st,
                                             (const double*)g->partials, g->max_partials, n_r, n_fn, g->sc, info,
                                             n_dot, n_e, n_gsum, g->geo.E));
   return hipGetLastError();
@@ -2091,8 +2096,13 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
       okxy[dy][dx] = col && jx >= 0 && jx < G.nx && jy >= 0 && jy < G.ny;
       offxy[dy][dx] = okxy[dy][dx] ? jx + G.nx * jy : 0;
     }
-  T win[D][D][D];  // [plane][dy][dx]
-  auto load_plane = [&](int jz, T (&pl)[D][D]) {
+  // every plane the slab reads (its kFiltDZ layers and R halo planes on
+  // each side) is loaded up front: one memory latency per block
+  constexpr int NP = kFiltDZ + 2 * R;
+  T win[NP][D][D];  // [plane][dy][dx]
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int jz = z0 - R + p;
     const bool zok = jz >= 0 && jz < G.nz;
 #pragma unroll
     for (int dy = 0; dy < D; ++dy)
@@ -2102,33 +2112,26 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
         const int j = ok ? offxy[dy][dx] + jz * plane : 0;
         T v = in[j];
         if (kind == FILT_TRANS) v *= Hsi[j];
-        pl[dy][dx] = ok ? v : (T)0;
+        win[p][dy][dx] = ok ? v : (T)0;
       }
-  };
-#pragma unroll
-  for (int p = 0; p < D - 1; ++p) load_plane(z0 - R + p, win[p]);
+  }
   double vs[1] = {0.0};
-  for (int ez = z0; ez < z1; ++ez) {
-    load_plane(ez + R, win[D - 1]);
+#pragma unroll
+  for (int l = 0; l < kFiltDZ; ++l) {
+    const int ez = z0 + l;
     T acc = (T)0;
 #pragma unroll
     for (int dz = 0; dz < D; ++dz)
 #pragma unroll
       for (int dy = 0; dy < D; ++dy)
 #pragma unroll
-        for (int dx = 0; dx < D; ++dx) acc += W.w[dx + D * (dy + D * dz)] * win[dz][dy][dx];
-    if (col) {
+        for (int dx = 0; dx < D; ++dx) acc += W.w[dx + D * (dy + D * dz)] * win[l + dz][dy][dx];
+    if (col && ez < z1) {
       const int e = ex + G.nx * (ey + G.ny * ez);
       const T res = kind == FILT_FWD ? acc * Hsi[e] : acc;
       out[e] = res;
       vs[0] += (double)res;
     }
-#pragma unroll
-    for (int p = 0; p < D - 1; ++p)
-#pragma unroll
-      for (int dy = 0; dy < D; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < D; ++dx) win[p][dy][dx] = win[p + 1][dy][dx];
   }
   if (want_sum) {
     double* dst[1] = {pslot(P, P_GSUM, 0, maxp)};
