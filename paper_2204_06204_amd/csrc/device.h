@@ -76,13 +76,53 @@ __device__ __forceinline__ void block_reduce(double (&v)[NV]) {
   __syncthreads();
 }
 
+// The same for a block of NTHR threads (a multiple of 64) through LDS: the
+// values are stored, then 16 lanes per value fold a strided sixteenth of the
+// block's entries each and a row-wise DPP butterfly joins the 16 lanes.
+// Every thread does about NV + NTHR / 16 operations, against some 20 per
+// value and wave for the DPP reduction of every value above.  The order of
+// operations is fixed.
+template <int NV, unsigned MAXMASK, int NTHR>
+__device__ __forceinline__ void block_reduce_lds(double (&v)[NV]) {
+  static_assert(NTHR % 64 == 0 && NTHR <= 1024, "whole waves");
+  constexpr int SEG = NTHR / 16;
+  __shared__ double sh[NV][NTHR];
+  __shared__ double res[NV];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) sh[i][tid] = v[i];
+  __syncthreads();
+  for (int t = tid; t < NV * 16; t += NTHR) {  // rows of 16 lanes: one value each
+    const int i = t >> 4, l = t & 15;
+    const bool is_max = (MAXMASK >> i) & 1u;
+    double acc = sh[i][l];
+#pragma unroll
+    for (int j = 1; j < SEG; ++j) {
+      const double x = sh[i][l + 16 * j];
+      acc = is_max ? fmax(acc, x) : acc + x;
+    }
+    const double a1 = dpp_move<0xB1, 0xf>(acc);   // quad_perm [1,0,3,2]
+    acc = is_max ? fmax(acc, a1) : acc + a1;
+    const double a2 = dpp_move<0x4E, 0xf>(acc);   // quad_perm [2,3,0,1]
+    acc = is_max ? fmax(acc, a2) : acc + a2;
+    const double a3 = dpp_move<0x141, 0xf>(acc);  // row_half_mirror
+    acc = is_max ? fmax(acc, a3) : acc + a3;
+    const double a4 = dpp_move<0x140, 0xf>(acc);  // row_mirror: every lane holds the row's result
+    acc = is_max ? fmax(acc, a4) : acc + a4;
+    if (l == 0) res[i] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = res[i];
+}
+
 // Reduce NV arrays of per-block partials (entry i: n[i] values at src[i];
 // sum, or max where bit i of MAXMASK is set).  Every block computes the same
 // result in the same order; the producing kernel has finished, so plain
 // loads see its stores.  Each round loads two entries per thread of every
 // array before folding any, so that the arrays cost one memory latency per
 // round, not one each.
-template <int NV, unsigned MAXMASK>
+template <int NV, unsigned MAXMASK, int NTHR = 0>
 __device__ __forceinline__ void reduce_parts(double (&v)[NV], const double* const (&src)[NV],
                                              const int (&n)[NV]) {
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
@@ -109,14 +149,17 @@ __device__ __forceinline__ void reduce_parts(double (&v)[NV], const double* cons
 #pragma unroll
       for (int u = 0; u < 2; ++u) v[i] = ((MAXMASK >> i) & 1u) ? fmax(v[i], x[i][u]) : v[i] + x[i][u];
   }
-  block_reduce<NV, MAXMASK>(v);
+  if constexpr (NTHR > 0) block_reduce_lds<NV, MAXMASK, NTHR>(v);
+  else block_reduce<NV, MAXMASK>(v);
 }
 
 // Block-reduce NV values and let thread 0 store them as this block's
-// partials: entry i goes to dst[i][block].
-template <int NV, unsigned MAXMASK>
+// partials: entry i goes to dst[i][block].  NTHR > 0: the block has NTHR
+// threads, reduced through LDS.
+template <int NV, unsigned MAXMASK, int NTHR = 0>
 __device__ __forceinline__ void write_parts(double (&v)[NV], double* const (&dst)[NV], int block) {
-  block_reduce<NV, MAXMASK>(v);
+  if constexpr (NTHR > 0) block_reduce_lds<NV, MAXMASK, NTHR>(v);
+  else block_reduce<NV, MAXMASK>(v);
   const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
   if (tid == 0) {
 #pragma unroll

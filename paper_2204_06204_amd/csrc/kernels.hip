@@ -1623,7 +1623,7 @@ __global__ void __launch_bounds__(kVecBlock)
       cnt[4 * R + 2] = cn.apply;
       cnt[4 * R + 3] = cn.fn;
     }
-    reduce_parts<4 * NR, 0u>(pre, src, cnt);
+    reduce_parts<4 * NR, 0u, kVecBlock>(pre, src, cnt);
   }
   T al[NR], be[NR];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -1670,7 +1670,7 @@ __global__ void __launch_bounds__(kVecBlock)
     dst[2 * R + 1] = pslot(P, P_RIF, R, maxp);
   }
   dst[2 * NR] = pslot(P, P_DOT, 0, maxp);
-  write_parts<2 * NR + 1, 0xAAAu>(v, dst, blockIdx.x);
+  write_parts<2 * NR + 1, 0xAAAu, kVecBlock>(v, dst, blockIdx.x);
 }
 
 // Threads of the one-block finishing kernels: a block of 256 measured twice
@@ -1717,7 +1717,7 @@ __global__ void __launch_bounds__(kFinishThreads)
   // max-reduced entries: |r|_inf of each RHS (3 R + 1, R < NR) and
   // |dx|_inf (3 NR + 2); the rest are sums
   constexpr unsigned MM = rinf_mask(NR) | (1u << (3 * NR + 2));
-  reduce_parts<3 * NR + 4, MM>(v, src, cnt);
+  reduce_parts<3 * NR + 4, MM, kFinishThreads>(v, src, cnt);
   if (threadIdx.x == 0) {
     double rinf = 0.0, rrel = 0.0, status = 0.0;
 #pragma unroll
@@ -2316,11 +2316,11 @@ __global__ void __launch_bounds__(kVecBlock)
     proj_eval(ev, yd, lam_w, lo, hi);
   }
   double* dst[3] = {pslot(P, P_S0, 0, maxp), pslot(P, P_YMAX, 0, maxp), pslot(P, P_NACT, 0, maxp)};
-  write_parts<3, 0x2u>(v, dst, blockIdx.x);
+  write_parts<3, 0x2u, kVecBlock>(v, dst, blockIdx.x);
   double* edst[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) edst[i] = pslot(P, P_E0 + i, 0, maxp);  // evaluation set 0
-  write_parts<11, 0x600u>(ev, edst, blockIdx.x);
+  write_parts<11, 0x600u, kVecBlock>(ev, edst, blockIdx.x);
 }
 
 __device__ __forceinline__ double* lslot(const ProjWs& W, int i) { return W.base + i * W.stride; }
@@ -2340,7 +2340,7 @@ __global__ void __launch_bounds__(kVecBlock)
     v[2] += (yd > lo && yd < hi) ? 1.0 : 0.0;
   }
   double* dst[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
-  write_parts<3, 0x2u>(v, dst, blockIdx.x);
+  write_parts<3, 0x2u, kVecBlock>(v, dst, blockIdx.x);
 }
 
 struct ProjDecision {
@@ -2367,7 +2367,7 @@ __device__ ProjDecision proj_decide_eval(const ProjWs& W, int nb, int set, doubl
     src[i] = lslot(W, proj_set(set) + i);
     cnt[i] = nb;
   }
-  reduce_parts<11, 0x600u>(v, src, cnt);
+  reduce_parts<11, 0x600u, kVecBlock>(v, src, cnt);
   const double F = v[0];
   const double lb = v[9], ub = -v[10];
   double next;
@@ -2427,7 +2427,7 @@ __device__ ProjDecision proj_decide(const ProjWs& W, int nb, bool first, int set
   double v[3];
   const double* src[3] = {lslot(W, L_S0), lslot(W, L_YMAX), lslot(W, L_NACT)};
   const int cnt[3] = {nb, nb, nb};
-  reduce_parts<3, 0x2u>(v, src, cnt);
+  reduce_parts<3, 0x2u, kVecBlock>(v, src, cnt);
   const double S0 = v[0], ymax = v[1], nact0 = v[2];
   d.bad = !isfinite(S0);
   if (S0 <= vmax || d.bad) {
@@ -2489,7 +2489,7 @@ __global__ void __launch_bounds__(kVecBlock)
   double* dst[11];
 #pragma unroll
   for (int i = 0; i < 11; ++i) dst[i] = lslot(W, proj_set(pass + 1) + i);
-  write_parts<11, 0x600u>(v, dst, blockIdx.x);
+  write_parts<11, 0x600u, kVecBlock>(v, dst, blockIdx.x);
 }
 
 // x = clamp(y - lambda, lo, hi) after `passes` passes.  A search still open
@@ -2531,7 +2531,7 @@ __global__ void __launch_bounds__(kVecBlock)
     v[0] += (double)xe;
   }
   double* dst[2] = {lslot(W, L_VOL), lslot(W, L_DX)};
-  write_parts<2, 0x2u>(v, dst, blockIdx.x);
+  write_parts<2, 0x2u, kVecBlock>(v, dst, blockIdx.x);
 }
 
 template <typename T>
@@ -2654,7 +2654,7 @@ __global__ void __launch_bounds__(kVecBlock)
   double v[3];
   const double* src[3] = {pslot(P, P_DOT, 0, maxp), pslot(P, P_MET0, 0, maxp), pslot(P, P_MET1, 0, maxp)};
   const int cnt[3] = {nb_dot, nb_lo, nb_hi};
-  reduce_parts<3, 0u>(v, src, cnt);
+  reduce_parts<3, 0u, kVecBlock>(v, src, cnt);
   if (threadIdx.x == 0) {
     double rrel = 0.0, status = 0.0;
     for (int R = 0; R < nrhs; ++R) {
