@@ -180,16 +180,29 @@ __device__ __forceinline__ int fdiv(int n, int d, double rd) {
 // --------------------------------------------------------------------------
 // SIMP scaling s = rho_min + (1 - rho_min) rho^p and ds/drho.
 // --------------------------------------------------------------------------
-// General exponents go through pow() in a separate function so that the
-// cubic case (the common SIMP exponent) keeps the hot loops free of it.
+// General exponents: FP64 goes through pow() in a separate function, so that
+// the cubic case (the common SIMP exponent) keeps the hot loops free of its
+// code; FP32 takes rho^e = 2^(e log2 rho) from the hardware's base-2
+// exponential and logarithm (a few ulp, no call: a call inside the z-march
+// makes the compiler keep its live scalar registers in vector lanes).
 __device__ __noinline__ double simp_pow(double rho, double e) { return pow(rho, e); }
+
+template <typename T>
+__device__ __forceinline__ T simp_pow_t(T rho, double e) {
+  if constexpr (sizeof(T) == 4) {
+    if (!(rho > 0.0f)) return rho == 0.0f ? (e == 0.0 ? 1.0f : 0.0f) : __builtin_nanf("");
+    return __builtin_amdgcn_exp2f((float)e * __builtin_amdgcn_logf(rho));
+  } else {
+    return simp_pow(rho, e);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ T simp_s(T rho, const Simp& sp) {
   const T rm = (T)sp.rho_min;
   T pw;
   if (sp.cubic) pw = rho * rho * rho;
-  else pw = (T)simp_pow((double)rho, sp.penal);
+  else pw = simp_pow_t<T>(rho, sp.penal);
   return rm + ((T)1 - rm) * pw;
 }
 template <typename T>
@@ -197,7 +210,7 @@ __device__ __forceinline__ T simp_ds(T rho, const Simp& sp) {
   const T rm = (T)sp.rho_min;
   T pw;
   if (sp.cubic) pw = rho * rho;
-  else pw = (T)simp_pow((double)rho, sp.penal - 1.0);
+  else pw = simp_pow_t<T>(rho, sp.penal - 1.0);
   return (T)sp.penal * ((T)1 - rm) * pw;
 }
 

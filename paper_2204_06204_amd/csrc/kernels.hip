@@ -531,20 +531,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
       const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
       const unsigned mv = bmask(gcol[sl], k, ok);
       S.m[sl] = ok ? mv : 7u;
-      T sv[3];
       bload3(rs_r, ob, S.r[sl]);
       bload3(rs_w, ob, S.w[sl]);
       bload3(rs_d, ob, S.d[sl]);
-      bload3(rs_s, ob, sv);  // allocated on the first step too, its contents unused
-#pragma unroll
-      for (int c = 0; c < 3; ++c) S.s[sl][c] = first ? (T)0 : sv[c];
+      bload3(rs_s, first ? kOOR : ob, S.s[sl]);  // zero on the first step (not read)
       if (sl == 0) {  // p and x are used by the owner only
         const uint32_t oo = (own_plane && writer && ok) ? ob : kOOR;
-        T pv[3];
         bload3(rs_x, oo, S.x);
-        bload3(rs_p, oo, pv);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) S.p[c] = first ? (T)0 : pv[c];
+        bload3(rs_p, first ? kOOR : oo, S.p);
       }
     }
   };

@@ -143,3 +143,40 @@ def test_apply_argument_errors():
         g.apply_K(rho_t, u)                       # nrhs 2 > max_rhs 1
     with pytest.raises(TypeError):
         g.apply_K(rho_t, u[: p.ndof].double())    # dtype mismatch (binding check)
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+@pytest.mark.parametrize("penal", [1.0, 3.5])
+def test_general_simp_exponent(penal, dtype):
+    """SIMP exponents other than 3 (Sec. 3's power law with a general p):
+    K(rho)u, the sensitivity and eight fused FP32 / unfused FP64 PCG steps
+    against the oracle, densities including 0 and 1."""
+    say(f"simp exponent {penal} {dtype}")
+    p = _case(23, 9, 7, 31)
+    p.penal = penal
+    og = OGrid(p.nx, p.ny, p.nz)
+    rho = synth.uniform_density(p.E, 5, 0.0, 1.0)
+    rho[:7] = 0.0
+    rho[7:14] = 1.0
+    rho_t = dev(rho, dtype)
+    rho_used = host(rho_t)
+    s = oracle.simp_scale(rho_used, penal, p.rho_min)
+    u_t = dev(synth.normal_vector(p.ndof, 6)[0], dtype)
+    u_used = host(u_t)
+    g = _grid(p)
+    # a few ulp of s_e from the FP32 exponential: 1024 eps instead of 256
+    ref = oracle.apply_K(og, s, u_used, p.fixed_mask, p.springs)
+    scale = abs_scale(og, s, u_used, p.fixed_mask, p.springs)
+    err = np.abs(host(g.apply_K(rho_t, u_t)) - ref)
+    assert np.all(err <= 1024 * EPS[dtype] * scale + 1e-300), float((err / (scale + 1e-300)).max())
+    d = host(g.sensitivity(rho_t, u_t))
+    dref = oracle.compliance_gradient(og, rho_used, u_used[None, :], p.fixed_mask, penal, p.rho_min)
+    assert np.abs(d - dref).max() <= (1e-12 if dtype == torch.float64 else 2e-5) * np.abs(dref).max()
+    K = oracle.assemble_K(og, s, p.fixed_mask, p.springs)
+    D = oracle.jacobi_diag(og, s, p.fixed_mask, p.springs)
+    f = p.loads[0]
+    x_t = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    g.inner_solve(rho_t, dev(f, dtype), x_t, 8)
+    x_ref, _ = oracle.pcg_ref(lambda v: K @ v, D, f, np.zeros(p.ndof), 8)
+    tol = 1e-10 if dtype == torch.float64 else 2e-4
+    assert np.abs(host(x_t) - x_ref).max() <= tol * np.abs(x_ref).max()
