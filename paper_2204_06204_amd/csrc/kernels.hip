@@ -492,10 +492,14 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   static_assert(MODE != MODE_MRF || NR == 1, "the fused MINRES step handles one RHS per launch");
   constexpr int NP = MODE == MODE_APPLY ? 1 : 4 * NR;  // partial values per block
   double part[NP];
-  // fused CG step: r.z and r.r (sums of non-negative terms) and max|r| of
-  // the thread's owned nodes, at most 3 (dz + 1) terms, accumulate in T and
-  // join the FP64 partials before the block reduction
-  T cpart[3] = {(T)0, (T)0, (T)0};
+  // The thread's own sums of non-negative terms (r.r, r.z = sum r^2 / d,
+  // f.f) and max|r| over its owned nodes, at most 3 (dz + 1) terms per RHS,
+  // accumulate in T and join the FP64 partials before the block reduction;
+  // sums with terms of either sign (w.z) stay FP64 throughout.
+  //   RESID: r.r, max|r|, f.f   CG, CGF: r.z, r.r, max|r|
+  T tpart[NR][3];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) tpart[r][0] = tpart[r][1] = tpart[r][2] = (T)0;
 #pragma unroll
   for (int i = 0; i < NP; ++i) part[i] = 0.0;
 
@@ -562,9 +566,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
           pn[c] = S.d[sl][c] * S.r[sl][c] + be * S.p[c];
           xn[c] = S.x[c] + al * pn[c];
           if (owner) {
-            cpart[0] += rn[c] * zn;     // r.z
-            cpart[1] += rn[c] * rn[c];  // r.r
-            cpart[2] = fmax(cpart[2], fabs(rn[c]));
+            tpart[0][0] += rn[c] * zn;     // r.z
+            tpart[0][1] += rn[c] * rn[c];  // r.r
+            tpart[0][2] = fmax(tpart[0][2], fabs(rn[c]));
           }
         }
       }
@@ -869,6 +873,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
         // partial sums count owned nodes only (a select: values of a thread
         // without an owned node may be anything, NaN included)
         auto own_only = [wr](double v) { return wr ? v : 0.0; };
+        auto own_t = [wr](T v) { return wr ? v : (T)0; };
         if constexpr (MODE == MODE_RESID) {
           const bool zout = A.invD || A.invD_out;
           T fv[3], rv[3], dv[3], dl[3], zv[3];
@@ -903,9 +908,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
           if (A.invD_out) bstore3(rs_do, ob, dv);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            part[4 * r + 0] += own_only((double)rv[c] * (double)rv[c]);
-            part[4 * r + 1] = fmax(part[4 * r + 1], own_only(fabs((double)rv[c])));
-            part[4 * r + 2] += own_only((double)fv[c] * (double)fv[c]);
+            tpart[r][0] += own_t(rv[c] * rv[c]);
+            tpart[r][1] = fmax(tpart[r][1], own_t(fabs(rv[c])));
+            tpart[r][2] += own_t(fv[c] * fv[c]);
           }
         } else {
           bstore3(rs_y[r], ob, acc);
@@ -920,10 +925,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
               const T rv = rv3[c];
-              part[4 * r + 0] += own_only((double)rv * (double)pv[c]);      // r.z
+              tpart[r][0] += own_t(rv * pv[c]);                             // r.z
               part[4 * r + 1] += own_only((double)acc[c] * (double)pv[c]);  // w.z
-              part[4 * r + 2] += own_only((double)rv * (double)rv);         // r.r
-              part[4 * r + 3] = fmax(part[4 * r + 3], own_only(fabs((double)rv)));
+              tpart[r][1] += own_t(rv * rv);                                // r.r
+              tpart[r][2] = fmax(tpart[r][2], own_t(fabs(rv)));
             }
           }
           if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
@@ -959,10 +964,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
       dst[4 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
       dst[4 * r + 3] = pslot(A.P, P_RI0 + par, rhs0 + r, A.maxp);
     }
-    if constexpr (MODE == MODE_CGF) {
-      part[0] = (double)cpart[0];
-      part[2] = (double)cpart[1];
-      part[3] = (double)cpart[2];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      part[4 * r + 0] = (double)tpart[r][0];
+      part[4 * r + 2] = (double)tpart[r][1];
+      part[4 * r + 3] = (double)tpart[r][2];
     }
     write_parts<4 * NR, 0x8888u>(part, dst, lb);
   }
@@ -989,9 +995,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     double* dst[3 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      v[3 * r + 0] = part[4 * r + 0];
-      v[3 * r + 1] = part[4 * r + 1];
-      v[3 * r + 2] = part[4 * r + 2];
+      v[3 * r + 0] = (double)tpart[r][0];
+      v[3 * r + 1] = (double)tpart[r][1];
+      v[3 * r + 2] = (double)tpart[r][2];
       dst[3 * r + 0] = pslot(A.P, P_RNF, rhs0 + r, A.maxp);
       dst[3 * r + 1] = pslot(A.P, P_RIF, rhs0 + r, A.maxp);
       dst[3 * r + 2] = pslot(A.P, P_FN, rhs0 + r, A.maxp);
