@@ -417,13 +417,16 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
     }
     HIP_TRY(launch_minres<T>(g, last, last, Y, R1, R2, W2, Wc, x, 0, nb_v, damp, st, nullptr));
   }
-  T* invD = (T*)V.invD;
-  HIP_TRY(launch_diag<T>(g, rho, invD, st));
-  if (!cn_out) return residual_norms<T>(g, rho, u, f, (T*)V.r[0], invD, nrhs, st);
+  // the final residual and its norms; the residual kernel forms the Jacobi
+  // diagonal on the way (its partials are written when it forms or reads one)
+  int nb = 0;
+  HIP_TRY(launch_resid_diag<T>(g, rho, u, f, (T*)V.r[0], (T*)V.invD, (T*)V.q, nrhs, st, &nb));
+  if (!cn_out) {
+    HIP_TRY(launch_pcg_finish(g, nrhs, nb, nb, nullptr, 0, 0, 0, st));
+    return FBTO_OK;
+  }
   // inside an outer step: leave the residual norms and f . u as partials
   // for the step's final reduction
-  int nb = 0;
-  HIP_TRY(launch_resid<T>(g, rho, u, f, (T*)V.r[0], invD, (T*)V.q, nrhs, st, &nb));
   HIP_TRY(launch_dot<T>(g, f, u, nrhs, st));
   *cn_out = CgCounts{nb, nb, vec_blocks(g->geo.ndof)};
   return FBTO_OK;
