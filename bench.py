@@ -13,8 +13,10 @@ of the FP32 path (FP32 storage and arithmetic, FP64 reductions); the same
 line carries the FP64 path, the K(rho)u rate in GDOF/s with its roofline
 fraction, the time to a fixed residual (FP32 + FP64 refinement vs FP64),
 and the CPU oracle timed on the host cores.  `roofline` is that of the
-kernel that dominates the step, the fused Jacobi-PCG step; `outer_roofline`
-sets the whole iteration against its algorithmic bytes.
+kernel that dominates the step, the fused Jacobi-PCG step
+(`fused_step_sizes` gives the same kernel on the 256x128x128 and
+384x192x192 grids); `outer_roofline` sets the whole iteration against its
+algorithmic bytes.
 """
 from __future__ import annotations
 
@@ -297,6 +299,25 @@ def apply_sizes(torch):
     return out
 
 
+def fused_sizes(torch):
+    """The fused CG step (FP32, one load case) on the two larger grids,
+    timed as in the headline roofline: HIP events around solves of 41 and 9
+    steps; HBM fraction of the same algorithmic bytes (11*3N*4 + N + 4E)."""
+    import synth
+    from paper_2204_06204_amd.grid import Grid
+    out = {}
+    for name in ("cfg4", "cfg5"):
+        p = synth.config(name)
+        g = Grid.from_problem(p, max_rhs=1)
+        t = fused_step_timing(g, p, torch, reps=5)
+        nbytes = 11 * p.ndof * 4 + p.N + 4 * p.E
+        out[name] = {"us": t * 1e6, "hbm_frac": nbytes / t / 1e9 / HBM_PEAK_GBS, "bytes": nbytes,
+                     "grid": [p.nx, p.ny, p.nz]}
+        g.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def projection_timing(torch, reps=20):
     """The two device projections onto {0 <= x <= 1, sum x <= vmax}
     (fbto_project_volume: safeguarded Newton; fbto_project_volume_sorted:
@@ -537,6 +558,7 @@ def main():
 
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
     sizes = None if args.no_sizes else apply_sizes(torch)
+    fsizes = None if args.no_sizes else fused_sizes(torch)
     osizes = None if args.no_sizes else outer_sizes(torch)
     proj = None if args.no_sizes else projection_timing(torch)
     fixed4 = None if (args.no_sizes or args.no_fixed_err) else fixed_error_cfg4(torch)
@@ -588,6 +610,7 @@ def main():
                      "kernel": "k_apply<float, 1, CGF> (fused Jacobi-PCG step, 7 of the 8 steps of an "
                                "outer iteration), algorithmic bytes 11*3N*4 + N + E*4 = "
                                f"{bytes_fused} per launch, {t_fused * 1e6:.2f} us per launch"},
+        "fused_step_sizes": fsizes,
         "outer_roofline": {"bytes_per_iter": bytes_outer, "ceiling_iter_s": HBM_PEAK_GBS * 1e9 / bytes_outer,
                            "frac": value * bytes_outer / (HBM_PEAK_GBS * 1e9)},
         "pgd_path": {"outer_iter_s": steps_pgd / dtpgd, "ms_per_step": dtpgd / steps_pgd * 1e3,
