@@ -81,7 +81,9 @@ typedef struct fbto_grid_desc {
   int32_t nx, ny, nz;        /* elements per axis, each >= 1              */
   int32_t max_rhs;           /* right-hand sides per call, 1..4            */
   double young, poisson;     /* E > 0, -1 < nu < 0.5                       */
-  double penal;              /* SIMP exponent p >= 1                        */
+  double penal;              /* SIMP exponent p >= 1 (p = 3 by products;   */
+                             /* other p: FP64 pow(), FP32 2^(p log2 rho)   */
+                             /* from the hardware, a few ulp)              */
   double rho_min;            /* 0 <= rho_min < 1 (stiffness floor)          */
   double filter_radius;      /* cone-filter radius r in element widths;    */
                              /* r <= 1 makes the filter the identity       */
