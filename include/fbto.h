@@ -379,9 +379,10 @@ fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, cons
  *                         status says the budget ran out.
  *   FBTO_OPT_APPLY_TILE   tile of the z-marching K(rho)u kernels (apply,
  *   FBTO_OPT_CGF_TILE     residual and CG products; the fused CG step):
- *                         bx | by << 8 | dz << 16 | cap << 24 (threads per
- *                         tile row and column, 8 <= bx <= 64,
- *                         4 <= by <= 64, 128 <= bx * by <= 256, slab depth
+ *                         bx | by << 8 | dz << 16 | cap << 24 (element
+ *                         columns per tile row and column, 8 <= bx <= 64,
+ *                         4 <= by <= 64, with one thread per node column:
+ *                         128 <= (bx + 1) (by + 1) <= 256; slab depth
  *                         dz 1 .. 64; a zero field is chosen by the cost
  *                         model; cap 2 .. 15 limits the blocks resident on
  *                         a CU by the LDS each block requests, 0 leaves

@@ -139,7 +139,7 @@ struct ApplyArgs {
   int nspring;
   const int64_t* sdof;
   const T* sk;
-  int bx, by;          // tile shape (threads = bx * by)
+  int bx, by;          // tile of bx * by element columns (threads = (bx + 1) * (by + 1), one per node column)
   int tiles_x, tiles_y, slabs, dz, nblocks, per_xcd;
   double* P;           // partial slots
   int maxp;
@@ -291,6 +291,9 @@ struct MinresStage {
 // later values, lie beyond it, so an access there loads 0 or is dropped
 // without a cache request.
 constexpr uint32_t kOOR = 0x80000000u;
+// node columns a z-march thread stages per plane (one per thread: the
+// block has a thread for every node column of its tile)
+constexpr int kSlots = 1;
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t zrsrc(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
 }
@@ -360,18 +363,23 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   const Geo G = A.g;
   const int BX = A.bx, BY = A.by;
   const int NW = BX + 1;          // LDS node row
-  const int NS = NW * (BY + 1);   // LDS nodes per plane
-  const int TS = BX * BY;
+  const int NS = NW * (BY + 1);   // LDS nodes per plane = threads with a node
+  const int TS = NS;              // corner slots: one per thread (element threads write them)
   T* nodes = reinterpret_cast<T*>(apply_smem);   // [2][NR][3][NS]
   T* corners = nodes + 2 * NR * 3 * NS;         // [2][NR][9][TS]
   T* dcorn = corners + 2 * NR * 9 * TS;          // [2][TS] density sums of the diagonal
 
-  // The block is padded to whole waves (the DPP reductions read every lane
-  // of a wave); padding threads mirror thread 0 and store nothing.
+  // One thread per node column of the tile: thread (tx, ty), tx <= BX,
+  // ty <= BY, stages node (x0 + tx, y0 + ty) of every plane, and for
+  // tx < BX, ty < BY computes element column (x0 + tx, y0 + ty) as well.
+  // The threads of the tile's far column and row (tx = BX or ty = BY) run
+  // the element code on neighbouring LDS values; nothing reads what they
+  // produce.  The block is padded to whole waves (the DPP reductions read
+  // every lane of a wave); padding threads mirror thread 0 and store nothing.
   const int tid = threadIdx.x;
-  const bool live = tid < TS;
+  const bool live = tid < NS;
   const int tl = live ? tid : 0;
-  const int ty = tl / BX, tx = tl - ty * BX;
+  const int ty = tl / NW, tx = tl - ty * NW;
   const int bxi = lb % A.tiles_x;
   const int t2 = lb / A.tiles_x;
   const int byi = t2 % A.tiles_y;
@@ -382,27 +390,24 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   const int kend = min(k0 + A.dz, G.nz + 1);  // emitted planes [k0, kend)
   const int ez0 = k0 == 0 ? 0 : k0 - 1;        // first element layer (a halo layer if k0 > 0)
   const int plane = G.nxn * G.nyn;
-  const bool col_elem = ex >= 0 && ex < G.nx && ey >= 0 && ey < G.ny;
-  const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
+  const bool elem_t = live && tx < BX && ty < BY;  // a thread with an element column
+  const bool col_elem = elem_t && ex >= 0 && ex < G.nx && ey >= 0 && ey < G.ny;
+  // nodes whose four element columns are all in the tile: their outputs
+  const bool writer = live && tx >= 1 && ty >= 1 && tx < BX && ty < BY && ex <= G.nx && ey <= G.ny;
 
-  // node columns staged by this thread: slot 0 its own (ex, ey), slot 1 one
-  // node of the tile's far column / row (threads 0 .. BX + BY).
+  // The node column staged by this thread (slot 0; the staging code keeps a
+  // second slot, compiled out, for layouts with more nodes than threads).
   // Every memory operation of the z-march is issued unconditionally (loads
   // and stores a thread does not need go out of range, see below).  With no
   // branch around them the compiler can
   // count the loads in flight and wait only for the ones it consumes, so
   // the planes prefetched for the next layers stay in flight.
-  const bool has_extra = tid <= BX + BY;
+  constexpr bool has_extra = false;
   int li[2], gcol[2];
-  li[0] = tx + NW * ty;
+  li[0] = tl;  // padding threads stage thread 0's node again (the same value into the same slot)
   gcol[0] = (ex >= 0 && ex <= G.nx && ey >= 0 && ey <= G.ny) ? ex + G.nxn * ey : -1;
-  {
-    const int lx = tid <= BY ? BX : tid - BY - 1;
-    const int ly = tid <= BY ? tid : BY;
-    const int i1 = x0 + lx, j1 = y0 + ly;
-    li[1] = has_extra ? lx + NW * ly : li[0];  // the own node again: the same value, same thread
-    gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
-  }
+  li[1] = li[0];
+  gcol[1] = gcol[0];
 
   // Memory access of the z-march.  Every array is addressed through a buffer
   // resource based at the block's first plane ez0, with 32-bit byte offsets
@@ -437,7 +442,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   auto issue = [&](int k, ApplyStage<T, NR>& S) {
     const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
       const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
       const unsigned mv = bmask(gcol[sl], k, ok);
@@ -449,7 +454,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   auto stage = [&](const ApplyStage<T, NR>& S, int buf) {
     T* nb = nodes + buf * (NR * 3 * NS);
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       if (sl == 1 && !has_extra) continue;  // no far node: nothing staged
 #pragma unroll
       for (int r = 0; r < NR; ++r)
@@ -458,6 +463,10 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
           nb[(r * 3 + c) * NS + li[sl]] = ((S.m[sl] >> c) & 1u) ? (T)0 : S.v[sl][r][c];
     }
   };
+  // the lower-left node of the thread's element (node 0's for threads
+  // without an element, whose face values nothing reads: their reads stay
+  // inside the plane)
+  const int lf = elem_t ? li[0] : 0;
   auto read_face = [&](int buf, T (&F)[NR][4][3], T (&own)[NR][3]) {
     const T* nb = nodes + buf * (NR * 3 * NS);
     const int o4[4] = {0, 1, NW, NW + 1};
@@ -467,7 +476,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) u4[a][c] = nb[(r * 3 + c) * NS + li[0] + o4[a]];
+        for (int c = 0; c < 3; ++c) u4[a][c] = nb[(r * 3 + c) * NS + lf + o4[a]];
 #pragma unroll
       for (int c = 0; c < 3; ++c) own[r][c] = u4[0][c];
       face_modes(u4, F[r]);
@@ -530,7 +539,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
       const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
       const unsigned mv = bmask(gcol[sl], k, ok);
@@ -550,7 +559,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     T* nb = nodes + buf * (3 * NS);
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       const bool owner = sl == 0 && writer && own_plane;  // the owner's node index is valid
       // the owner's byte offset; other threads store out of range (dropped)
       const uint32_t ob = owner ? voff(gcol[0], k) : kOOR;
@@ -647,7 +656,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes the block reads
     const bool own_plane = k >= k0 && k < kend;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
       const uint32_t ob = ok ? voff(gcol[sl], k) : kOOR;
       const unsigned mv = bmask(gcol[sl], k, ok);
@@ -668,7 +677,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const bool own_plane = k >= k0 && k < kend;
     const int itn = A.step;
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       T yn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -844,7 +853,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
       const int n = wr ? gcol[0] + ez * plane : 0;
       const uint32_t ob = wr ? voff(gcol[0], ez) : kOOR;
       const unsigned m = wr ? (mq & 0xffu) : 0u;
-      const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - BX : tl, tlbb = wr ? tid - BX - 1 : tl;
+      const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - NW : tl, tlbb = wr ? tid - NW - 1 : tl;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const T* cr = corners + (cb * NR + r) * 9 * TS;
@@ -1035,12 +1044,12 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int BX = A.bx, BY = A.by;
   const int NW = BX + 1;
   const int NS = NW * (BY + 1);
-  const int TS = BX * BY;
   T* nodes = reinterpret_cast<T*>(apply_smem);  // [2][3][NS]
+  // one thread per node column of the tile, as in k_apply
   const int tid = threadIdx.x;
-  const bool live = tid < TS;
+  const bool live = tid < NS;
   const int tl = live ? tid : 0;
-  const int ty = tl / BX, tx = tl - ty * BX;
+  const int ty = tl / NW, tx = tl - ty * NW;
   const int bxi = lb % A.tiles_x;
   const int t2 = lb / A.tiles_x;
   const int byi = t2 % A.tiles_y;
@@ -1052,23 +1061,18 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int ez0 = k0 == 0 ? 0 : k0 - 1;
   const int elem_end = min(k0 + A.dz, G.nz);   // element layers [k0, elem_end) belong to this slab
   const int plane = G.nxn * G.nyn;
-  const bool writer = tx >= 1 && ty >= 1 && ex <= G.nx && ey <= G.ny;
+  const bool writer = live && tx >= 1 && ty >= 1 && tx < BX && ty < BY && ex <= G.nx && ey <= G.ny;
   const bool elem_owner = writer && ex < G.nx && ey < G.ny;
   // As in k_apply, the vectors are addressed through buffer resources based
-  // at the block's first plane ez0: a thread without a far node, a plane past
-  // the slab or a thread that owns no node gets an out-of-range offset, so its
-  // loads return 0 and its stores are dropped, with no branch around them.
-  const bool has_extra = tid <= BX + BY;
+  // at the block's first plane ez0: a plane past the slab or a thread that
+  // owns no node gets an out-of-range offset, so its loads return 0 and its
+  // stores are dropped, with no branch around them.
+  constexpr bool has_extra = false;
   int li[2], gcol[2];
-  li[0] = tx + NW * ty;
+  li[0] = tl;  // padding threads stage thread 0's node again (the same value into the same slot)
   gcol[0] = (ex >= 0 && ex <= G.nx && ey >= 0 && ey <= G.ny) ? ex + G.nxn * ey : -1;
-  {
-    const int lx = tid <= BY ? BX : tid - BY - 1;
-    const int ly = tid <= BY ? tid : BY;
-    const int i1 = x0 + lx, j1 = y0 + ly;
-    li[1] = has_extra ? lx + NW * ly : li[0];
-    gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
-  }
+  li[1] = li[0];
+  gcol[1] = gcol[0];
   const int64_t pbase = (int64_t)ez0 * plane;  // first node of plane ez0
   auto vres = [&](const T* v) { return zrsrc(v ? v + 3 * pbase : v); };
   auto voff = [&](int col, int k) -> uint32_t {
@@ -1104,7 +1108,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   auto issue = [&](int k, SensStage<T>& S) {
     const bool kv = k >= 0 && k <= kend && k <= G.nz;  // planes past kend are never read
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       const bool ok = kv && gcol[sl] >= 0 && (sl == 0 || has_extra);
       const uint32_t off = ok ? voff(gcol[sl], k) : kOOR;
       const unsigned mv = __builtin_amdgcn_raw_buffer_load_b8(rs_m, ok ? (uint32_t)(gcol[sl] + (k - ez0) * plane) : kOOR, 0, 0);
@@ -1125,7 +1129,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     T* nb = nodes + buf * (3 * NS);
     const bool own = owns(k);
 #pragma unroll
-    for (int sl = 0; sl < 2; ++sl) {
+    for (int sl = 0; sl < kSlots; ++sl) {
       T xn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1145,6 +1149,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       }
     }
   };
+  // the lower-left node of the thread's element (node 0's for threads
+  // without an element: their reads stay inside the plane)
+  const int lf = (live && tx < BX && ty < BY) ? li[0] : 0;
   auto read_face = [&](int buf, T (&F)[4][3]) {
     const T* nb = nodes + buf * (3 * NS);
     const int o4[4] = {0, 1, NW, NW + 1};
@@ -1152,7 +1159,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) u4[a][c] = nb[c * NS + li[0] + o4[a]];
+      for (int c = 0; c < 3; ++c) u4[a][c] = nb[c * NS + lf + o4[a]];
     face_modes(u4, F);
   };
   // byte offset of the element of layer ez in this thread's column (kOOR if
@@ -1229,7 +1236,8 @@ static size_t sens_lds_bytes(int bx, int by) {
 
 template <typename T, int NR>
 static size_t apply_lds_bytes(int bx, int by) {
-  return sizeof(T) * (size_t)(2 * NR * 3 * (bx + 1) * (by + 1) + 2 * NR * 9 * bx * by + 2 * bx * by);
+  const size_t ns = (size_t)(bx + 1) * (by + 1);  // node columns = threads
+  return sizeof(T) * (2 * NR * 3 * ns + 2 * NR * 9 * ns + 2 * ns);
 }
 
 // The z-march addresses each vector from the block's first plane with
@@ -1251,24 +1259,30 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
   constexpr double kMinWaves = 8.0;
   TileChoice best{};
   double best_cost = 1e300;
-  // The fused steps on large grids (2^22 elements and more): rows of 32
-  // node columns and 6 rows, slabs of 33 layers; the CG step with at most
-  // two blocks per CU.  A wave then stages two contiguous 384-byte runs per
-  // vector, and the L1 path, which bounds these steps there, carries fewer
-  // partial lines.  Measured (FP32): the CG step takes 163 us at
-  // 256x128x128 and 518 us at 384x192x192, against 172 and 557 us with the
-  // same tiles and as many blocks as fit (four), and 223 and 550 us with the
-  // cost model's choice; the MINRES step 147 and 500 us, against 172 and
-  // 537 us with the cap of two.  On smaller grids the model's tiles win.
+  // The fused steps on large grids (2^22 elements and more): 27 x 8 element
+  // columns (28 x 9 = 252 threads, rows of 28 nodes) in slabs of 33 layers.
+  // Long rows keep the L1 path, which bounds these steps there, on few
+  // partial cache lines.  The CG step runs at most two blocks per CU (the
+  // L1 path then serves fewer waves) unless three per CU (as many as its
+  // registers allow) finish the grid in fewer rounds: a round of three
+  // measured 1.31 times as long as a round of two.  Measured (FP32 CG step):
+  // 155 us at 256x128x128 (one round of three) and 497 us at 384x192x192
+  // (two per CU), against 167 and 527 us for the cost model's choice.
   if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
     if (override_shape == 0 && G.E >= ((int64_t)1 << 22)) {
-      const int bx = 32, by = 6, dz = std::min(33, G.nzn), cap = MODE == MODE_CGF ? 2 : 0;
-      const size_t lds = std::max(apply_lds_bytes<T, NR>(bx, by), cap ? (size_t)lds_for_block_cap(lds_per_cu, cap) : 0);
-      int occ = 0;
-      const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, 64 * 3, lds);
+      const int bx = 27, by = 8, dz = std::min(33, G.nzn);
+      const int threads = ((bx + 1) * (by + 1) + 63) / 64 * 64;
       const int tiles_x = (G.nxn + bx - 2) / (bx - 1), tiles_y = (G.nyn + by - 2) / (by - 1);
       const int slabs = (G.nzn + dz - 1) / dz;
       const int64_t nb = (int64_t)tiles_x * tiles_y * slabs;
+      int cap = 0;
+      if constexpr (MODE == MODE_CGF) {
+        const int64_t r2 = (nb + 2 * n_cu - 1) / (2 * n_cu), r3 = (nb + 3 * n_cu - 1) / (3 * n_cu);
+        cap = 1.31 * (double)r3 < (double)r2 ? 0 : 2;
+      }
+      const size_t lds = std::max(apply_lds_bytes<T, NR>(bx, by), cap ? (size_t)lds_for_block_cap(lds_per_cu, cap) : 0);
+      int occ = 0;
+      const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, threads, lds);
       if (oe == hipSuccess && occ >= 1 && lds <= kApplyMaxLds && nb <= kApplyMaxBlocks &&
           apply_offsets_fit(G, dz, sizeof(T)))
         return TileChoice{bx, by, dz, tiles_x, tiles_y, slabs, (int)nb, cap};
@@ -1278,7 +1292,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
     if (want_bx && bx != want_bx) continue;
     for (int by = 4; by <= 64; ++by) {
       if (want_by && by != want_by) continue;
-      const int ts = bx * by;
+      const int ts = (bx + 1) * (by + 1);  // threads: one per node column
       // at most four waves: every layer ends at a block-wide barrier, and
       // blocks of up to one wave per SIMD measured fastest
       if (ts < 128 || ts > 256) continue;
@@ -1342,7 +1356,7 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
   const int grid = A.per_xcd * 8;
   size_t lds = apply_lds_bytes<T, NR>(t.bx, t.by);
   if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
-  const int threads = (t.bx * t.by + 63) / 64 * 64;  // whole waves
+  const int threads = ((t.bx + 1) * (t.by + 1) + 63) / 64 * 64;  // one per node column, whole waves
   hipLaunchKernelGGL((k_apply<T, NR, MODE>), dim3(grid), dim3(threads), lds, st, A, rhs0);
   return hipGetLastError();
 }
@@ -1459,7 +1473,7 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
   A.nblocks = t.nblocks;
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
-  const int threads = (t.bx * t.by + 63) / 64 * 64;
+  const int threads = ((t.bx + 1) * (t.by + 1) + 63) / 64 * 64;
   size_t lds = sens_lds_bytes<T>(t.bx, t.by);
   if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
   hipLaunchKernelGGL((k_cg_sens<T>), dim3(grid), dim3(threads), lds, st, A);

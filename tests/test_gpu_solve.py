@@ -360,7 +360,7 @@ def test_nonfinite_load_is_reported(dtype):
     assert host(info)[6] == 6.0
 
 
-@pytest.mark.parametrize("tile", [(11, 23, 5, 0), (32, 6, 3, 2), (16, 8, 9, 3), (64, 4, 1, 0)])
+@pytest.mark.parametrize("tile", [(11, 20, 5, 0), (32, 6, 3, 2), (16, 8, 9, 3), (50, 4, 1, 0)])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_pcg_tile_override_matches_oracle(tile, dtype):
     """Tile shapes, slab depths and block caps set by fbto_set_option change
@@ -390,8 +390,10 @@ def test_tile_option_limits():
     p = synth.cantilever(8, 4, 4, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=2, seed=1)
     from paper_2204_06204_amd.grid import Grid
     g = Grid.from_problem(p)
-    for bad in (7, 65, 8 | (4 << 8), 16 | (65 << 8), 16 | (16 << 8) | (65 << 16), 1 << 24, 1 << 28, -1):
+    # (bx + 1)(by + 1) threads must lie in 128 .. 256
+    for bad in (7, 65, 8 | (4 << 8), 16 | (16 << 8), 16 | (65 << 8), 15 | (15 << 8) | (65 << 16), 1 << 24,
+                1 << 28, -1):
         with pytest.raises(FbtoError):
             g.set_option("cgf_tile", bad)
-    g.set_option("cgf_tile", 16 | (16 << 8) | (4 << 16) | (2 << 24))
+    g.set_option("cgf_tile", 15 | (15 << 8) | (4 << 16) | (2 << 24))
     g.close()
