@@ -799,8 +799,11 @@ fbto_status_t fbto_set_option(fbto_grid_t g, fbto_option_t option, int64_t value
       if (value < 0 || value >= ((int64_t)1 << 28)) return fail(FBTO_ERR_ARG, "tile value %lld out of range", (long long)value);
       const int bx = (int)(value & 0xff), by = (int)((value >> 8) & 0xff), dz = (int)((value >> 16) & 0xff);
       const int cap = (int)((value >> 24) & 0xf);
+      // the fused CG step has a thread per node column, (bx + 1) (by + 1);
+      // the other z-march kernels take the shape in both layouts
+      const int lo_t = option == FBTO_OPT_CGF_TILE ? (bx + 1) * (by + 1) : bx * by;
       if ((bx && (bx < 8 || bx > 64)) || (by && (by < 4 || by > 64)) || dz > 64 ||
-          (bx && by && ((bx + 1) * (by + 1) < 128 || (bx + 1) * (by + 1) > 256)))
+          (bx && by && (lo_t < 128 || (bx + 1) * (by + 1) > 256)))
         return fail(FBTO_ERR_ARG, "tile %d x %d x %d outside the kernel's limits", bx, by, dz);
       if (cap && (cap < 2 || lds_for_block_cap(g->lds_per_cu, cap) > (int)kApplyMaxLds))
         return fail(FBTO_ERR_ARG, "blocks per CU %d: not 2 or more, or needs more than %d bytes of LDS per block", cap,

@@ -291,9 +291,21 @@ struct MinresStage {
 // later values, lie beyond it, so an access there loads 0 or is dropped
 // without a cache request.
 constexpr uint32_t kOOR = 0x80000000u;
-// node columns a z-march thread stages per plane (one per thread: the
-// block has a thread for every node column of its tile)
-constexpr int kSlots = 1;
+// Thread layout of a z-march variant.  Node layout: one thread per node
+// column of the tile ((bx + 1) (by + 1) threads), each staging one node per
+// plane; the fused steps take it (fewer memory instructions per node; their
+// staging does the CG or MINRES vector update too).  Element layout: one
+// thread per element column (bx by threads), the tile's far column and row
+// staged by a second slot of threads 0 .. bx + by; the plain product, the
+// residual and the step-0 product take it (fewer threads for the same
+// elements, measured faster for them).
+template <int MODE>
+constexpr bool node_layout() { return MODE == MODE_CGF || MODE == MODE_MRF || MODE == MODE_SENSF; }
+// threads of a z-march block for a tile of bx x by element columns
+template <int MODE>
+constexpr int zmarch_threads(int bx, int by) {
+  return ((node_layout<MODE>() ? (bx + 1) * (by + 1) : bx * by) + 63) / 64 * 64;
+}
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t zrsrc(const void* p) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, 0x7FFFFFFF, 0x00020000);
 }
@@ -362,24 +374,28 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   if (lb >= A.nblocks) return;                    // whole block
   const Geo G = A.g;
   const int BX = A.bx, BY = A.by;
+  constexpr bool NL = node_layout<MODE>();
+  constexpr int kSlots = NL ? 1 : 2;  // node columns a thread stages per plane
   const int NW = BX + 1;          // LDS node row
-  const int NS = NW * (BY + 1);   // LDS nodes per plane = threads with a node
-  const int TS = NS;              // corner slots: one per thread (element threads write them)
+  const int NS = NW * (BY + 1);   // LDS nodes per plane
+  const int TW = NL ? NW : BX;    // threads per tile row
+  const int TS = NL ? NS : BX * BY;  // threads with a node (node layout) or an element (element layout)
   T* nodes = reinterpret_cast<T*>(apply_smem);   // [2][NR][3][NS]
   T* corners = nodes + 2 * NR * 3 * NS;         // [2][NR][9][TS]
   T* dcorn = corners + 2 * NR * 9 * TS;          // [2][TS] density sums of the diagonal
 
-  // One thread per node column of the tile: thread (tx, ty), tx <= BX,
-  // ty <= BY, stages node (x0 + tx, y0 + ty) of every plane, and for
-  // tx < BX, ty < BY computes element column (x0 + tx, y0 + ty) as well.
-  // The threads of the tile's far column and row (tx = BX or ty = BY) run
-  // the element code on neighbouring LDS values; nothing reads what they
-  // produce.  The block is padded to whole waves (the DPP reductions read
-  // every lane of a wave); padding threads mirror thread 0 and store nothing.
+  // Thread (tx, ty) of the tile computes element column (x0 + tx, y0 + ty)
+  // for tx < BX, ty < BY and stages node (x0 + tx, y0 + ty).  In the node
+  // layout the threads of the tile's far column and row (tx = BX or
+  // ty = BY) stage those nodes and run the element code on neighbouring LDS
+  // values; nothing reads what they produce.  In the element layout
+  // threads 0 .. BX + BY stage them in a second slot.  The block is padded
+  // to whole waves (the DPP reductions read every lane of a wave); padding
+  // threads mirror thread 0 and store nothing.
   const int tid = threadIdx.x;
-  const bool live = tid < NS;
+  const bool live = tid < TS;
   const int tl = live ? tid : 0;
-  const int ty = tl / NW, tx = tl - ty * NW;
+  const int ty = tl / TW, tx = tl - ty * TW;
   const int bxi = lb % A.tiles_x;
   const int t2 = lb / A.tiles_x;
   const int byi = t2 % A.tiles_y;
@@ -395,19 +411,26 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   // nodes whose four element columns are all in the tile: their outputs
   const bool writer = live && tx >= 1 && ty >= 1 && tx < BX && ty < BY && ex <= G.nx && ey <= G.ny;
 
-  // The node column staged by this thread (slot 0; the staging code keeps a
-  // second slot, compiled out, for layouts with more nodes than threads).
+  // Node columns staged by this thread: slot 0 its own (ex, ey); in the
+  // element layout slot 1 one node of the tile's far column / row (threads
+  // 0 .. BX + BY).  Padding threads stage thread 0's node again (the same
+  // value into the same LDS slot).
   // Every memory operation of the z-march is issued unconditionally (loads
   // and stores a thread does not need go out of range, see below).  With no
   // branch around them the compiler can
   // count the loads in flight and wait only for the ones it consumes, so
   // the planes prefetched for the next layers stay in flight.
-  constexpr bool has_extra = false;
+  const bool has_extra = !NL && tid <= BX + BY;
   int li[2], gcol[2];
-  li[0] = tl;  // padding threads stage thread 0's node again (the same value into the same slot)
+  li[0] = tx + NW * ty;
   gcol[0] = (ex >= 0 && ex <= G.nx && ey >= 0 && ey <= G.ny) ? ex + G.nxn * ey : -1;
-  li[1] = li[0];
-  gcol[1] = gcol[0];
+  {
+    const int lx = tid <= BY ? BX : tid - BY - 1;
+    const int ly = tid <= BY ? tid : BY;
+    const int i1 = x0 + lx, j1 = y0 + ly;
+    li[1] = has_extra ? lx + NW * ly : li[0];  // the own node again: the same value, same thread
+    gcol[1] = has_extra ? ((i1 >= 0 && i1 <= G.nx && j1 >= 0 && j1 <= G.ny) ? i1 + G.nxn * j1 : -1) : gcol[0];
+  }
 
   // Memory access of the z-march.  Every array is addressed through a buffer
   // resource based at the block's first plane ez0, with 32-bit byte offsets
@@ -853,7 +876,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
       const int n = wr ? gcol[0] + ez * plane : 0;
       const uint32_t ob = wr ? voff(gcol[0], ez) : kOOR;
       const unsigned m = wr ? (mq & 0xffu) : 0u;
-      const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - NW : tl, tlbb = wr ? tid - NW - 1 : tl;
+      const int tl1 = wr ? tid - 1 : tl, tlb = wr ? tid - TW : tl, tlbb = wr ? tid - TW - 1 : tl;
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const T* cr = corners + (cb * NR + r) * 9 * TS;
@@ -1045,7 +1068,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   const int NW = BX + 1;
   const int NS = NW * (BY + 1);
   T* nodes = reinterpret_cast<T*>(apply_smem);  // [2][3][NS]
-  // one thread per node column of the tile, as in k_apply
+  // one thread per node column of the tile (the node layout of k_apply)
+  constexpr int kSlots = 1;
   const int tid = threadIdx.x;
   const bool live = tid < NS;
   const int tl = live ? tid : 0;
@@ -1234,10 +1258,11 @@ static size_t sens_lds_bytes(int bx, int by) {
   return sizeof(T) * (size_t)(2 * 3 * (bx + 1) * (by + 1));
 }
 
-template <typename T, int NR>
+template <typename T, int NR, int MODE>
 static size_t apply_lds_bytes(int bx, int by) {
-  const size_t ns = (size_t)(bx + 1) * (by + 1);  // node columns = threads
-  return sizeof(T) * (2 * NR * 3 * ns + 2 * NR * 9 * ns + 2 * ns);
+  const size_t ns = (size_t)(bx + 1) * (by + 1);                      // nodes per plane
+  const size_t ts = node_layout<MODE>() ? ns : (size_t)bx * by;      // corner slots
+  return sizeof(T) * (2 * NR * 3 * ns + 2 * NR * 9 * ts + 2 * ts);
 }
 
 // The z-march addresses each vector from the block's first plane with
@@ -1271,7 +1296,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
   if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
     if (override_shape == 0 && G.E >= ((int64_t)1 << 22)) {
       const int bx = 27, by = 8, dz = std::min(33, G.nzn);
-      const int threads = ((bx + 1) * (by + 1) + 63) / 64 * 64;
+      const int threads = zmarch_threads<MODE>(bx, by);
       const int tiles_x = (G.nxn + bx - 2) / (bx - 1), tiles_y = (G.nyn + by - 2) / (by - 1);
       const int slabs = (G.nzn + dz - 1) / dz;
       const int64_t nb = (int64_t)tiles_x * tiles_y * slabs;
@@ -1280,7 +1305,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
         const int64_t r2 = (nb + 2 * n_cu - 1) / (2 * n_cu), r3 = (nb + 3 * n_cu - 1) / (3 * n_cu);
         cap = 1.31 * (double)r3 < (double)r2 ? 0 : 2;
       }
-      const size_t lds = std::max(apply_lds_bytes<T, NR>(bx, by), cap ? (size_t)lds_for_block_cap(lds_per_cu, cap) : 0);
+      const size_t lds = std::max(apply_lds_bytes<T, NR, MODE>(bx, by), cap ? (size_t)lds_for_block_cap(lds_per_cu, cap) : 0);
       int occ = 0;
       const hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_apply<T, NR, MODE>, threads, lds);
       if (oe == hipSuccess && occ >= 1 && lds <= kApplyMaxLds && nb <= kApplyMaxBlocks &&
@@ -1292,11 +1317,11 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
     if (want_bx && bx != want_bx) continue;
     for (int by = 4; by <= 64; ++by) {
       if (want_by && by != want_by) continue;
-      const int ts = (bx + 1) * (by + 1);  // threads: one per node column
+      const int ts = node_layout<MODE>() ? (bx + 1) * (by + 1) : bx * by;  // threads
       // at most four waves: every layer ends at a block-wide barrier, and
       // blocks of up to one wave per SIMD measured fastest
       if (ts < 128 || ts > 256) continue;
-      const size_t lds = MODE == MODE_SENSF ? sens_lds_bytes<T>(bx, by) : apply_lds_bytes<T, NR>(bx, by);
+      const size_t lds = MODE == MODE_SENSF ? sens_lds_bytes<T>(bx, by) : apply_lds_bytes<T, NR, MODE>(bx, by);
       if (lds > kApplyMaxLds) continue;
       const int waves = (ts + 63) / 64;
       int occ = 0;
@@ -1354,9 +1379,9 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
   A.nblocks = t.nblocks;
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
-  size_t lds = apply_lds_bytes<T, NR>(t.bx, t.by);
+  size_t lds = apply_lds_bytes<T, NR, MODE>(t.bx, t.by);
   if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
-  const int threads = ((t.bx + 1) * (t.by + 1) + 63) / 64 * 64;  // one per node column, whole waves
+  const int threads = zmarch_threads<MODE>(t.bx, t.by);  // whole waves
   hipLaunchKernelGGL((k_apply<T, NR, MODE>), dim3(grid), dim3(threads), lds, st, A, rhs0);
   return hipGetLastError();
 }
@@ -1473,7 +1498,7 @@ hipError_t launch_cg_sens(fbto_grid_s* g, const T* rho, const CgSet<T>& in, T* x
   A.nblocks = t.nblocks;
   A.per_xcd = (t.nblocks + 7) / 8;
   const int grid = A.per_xcd * 8;
-  const int threads = ((t.bx + 1) * (t.by + 1) + 63) / 64 * 64;
+  const int threads = zmarch_threads<MODE_SENSF>(t.bx, t.by);
   size_t lds = sens_lds_bytes<T>(t.bx, t.by);
   if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
   hipLaunchKernelGGL((k_cg_sens<T>), dim3(grid), dim3(threads), lds, st, A);
