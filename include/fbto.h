@@ -381,8 +381,11 @@ fbto_status_t fbto_project_volume_noalloc(fbto_prec_t prec, int64_t n_elem, cons
  *   FBTO_OPT_CGF_TILE     residual and CG products; the fused CG step):
  *                         bx | by << 8 | dz << 16 | cap << 24 (element
  *                         columns per tile row and column, 8 <= bx <= 64,
- *                         4 <= by <= 64, with one thread per node column:
- *                         128 <= (bx + 1) (by + 1) <= 256; slab depth
+ *                         4 <= by <= 64; the fused CG step has a thread
+ *                         per node column: 128 <= (bx + 1) (by + 1) <= 256;
+ *                         FBTO_OPT_APPLY_TILE also sets kernels with a
+ *                         thread per element column: bx by >= 128 and
+ *                         (bx + 1) (by + 1) <= 256; slab depth
  *                         dz 1 .. 64; a zero field is chosen by the cost
  *                         model; cap 2 .. 15 limits the blocks resident on
  *                         a CU by the LDS each block requests, 0 leaves
