@@ -171,16 +171,18 @@ def fused_step_timing(g, p, torch, reps=20, n1=9, n2=41):
     """Average duration of one fused CG step launch (FP32), the kernel that
     dominates the outer iteration.  A solve of n steps runs n - 1 fused
     launches beside a fixed set of other kernels, so the difference of the
-    average times of n2- and n1-step solves (HIP events on the launch
-    stream) over n2 - n1 is one fused launch."""
+    times of n2- and n1-step solves (HIP events on the launch stream) over
+    n2 - n1 is one fused launch.  The two solves alternate and the medians
+    of their times are taken, so that clock drift cancels."""
+    import statistics
     dev = torch.device("cuda:0")
     rho = torch.tensor(p.x0, dtype=torch.float32, device=dev)
     f = torch.tensor(p.loads[0], dtype=torch.float32, device=dev)
     u = torch.zeros_like(f)
     st = torch.cuda.current_stream()
-    def avg(n):
-        tot = 0.0
-        for i in range(reps + 2):
+    times = {n1: [], n2: []}
+    for i in range(reps + 2):
+        for n in (n2, n1):
             u.zero_()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
@@ -188,9 +190,8 @@ def fused_step_timing(g, p, torch, reps=20, n1=9, n2=41):
             e1.record(st)
             torch.cuda.synchronize()
             if i >= 2:
-                tot += e0.elapsed_time(e1) * 1e-3
-        return tot / reps
-    return (avg(n2) - avg(n1)) / (n2 - n1)
+                times[n].append(e0.elapsed_time(e1) * 1e-3)
+    return (statistics.median(times[n2]) - statistics.median(times[n1])) / (n2 - n1)
 
 
 def fixed_error(g, p, torch, rtol=1e-8):
