@@ -269,8 +269,8 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
   // step 0's product w = K z from the residual's z
   HIP_TRY(launch_apply_cg<T>(g, rho, z, set[0].r, set[0].w, nrhs, 0, st, &nb_a));
   int k = 0;
-  // FP32 on voxel grids: fused steps; FP64 and plane grids: unfused
-  const bool fused = sizeof(T) == 4 && g->dim == 3;
+  // voxel grids: fused steps (both precisions); plane grids: unfused
+  const bool fused = g->dim == 3;
   if (fused) {
     // fused steps: the update of step k and the product of step k + 1 in one pass
     for (; k + 1 < steps; ++k) {
@@ -286,8 +286,7 @@ fbto_status_t pcg_run(fbto_grid_s* g, const T* rho, const T* f, T* x, int nrhs, 
       }
     }
   } else {
-    // unfused steps: vector update, then the next product (FP64 keeps the
-    // register file for the element product)
+    // unfused steps (plane grids): vector update, then the next product
     for (; k + 1 < steps; ++k) {
       HIP_TRY(launch_cg_step<T>(g, x, x, set[0].r, z, z, set[0].w, set[0].p, set[0].s, invD, nullptr, nrhs, nb_a,
                                 cn.fn, k, rtol, st, &nb_v));

@@ -1509,21 +1509,17 @@ template <typename T>
 hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, const CgSet<T>& out,
                            const T* invD, int nrhs, int step, int n_apply, int n_fn, double rtol,
                            hipStream_t st, int* nb_out) {
-  if constexpr (sizeof(T) == 8) {
-    return hipErrorNotSupported;
-  } else {
-    ApplyArgs<T> A{};
-    A.rho = rho;
-    A.y = out.w;
-    A.invD = invD;
-    A.step = step;
-    A.xi = in.x; A.ri = in.r; A.pi = in.p; A.si = in.s; A.wi = in.w;
-    A.xo = out.x; A.ro = out.r; A.po = out.p; A.so = out.s;
-    A.n_apply = n_apply;
-    A.n_fn = n_fn;
-    A.rtol = rtol;
-    return launch_apply_mode<T, MODE_CGF>(g, A, nrhs, st, nb_out);
-  }
+  ApplyArgs<T> A{};
+  A.rho = rho;
+  A.y = out.w;
+  A.invD = invD;
+  A.step = step;
+  A.xi = in.x; A.ri = in.r; A.pi = in.p; A.si = in.s; A.wi = in.w;
+  A.xo = out.x; A.ro = out.r; A.po = out.p; A.so = out.s;
+  A.n_apply = n_apply;
+  A.n_fn = n_fn;
+  A.rtol = rtol;
+  return launch_apply_mode<T, MODE_CGF>(g, A, nrhs, st, nb_out);
 }
 
 template <typename T>
