@@ -378,8 +378,8 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
     int nb_v = 0, nb_a = 0;
     HIP_TRY(launch_minres<T>(g, 0, last, Y, R1, R2, W2, Wc, x, 0, 0, damp, st, &nb_v));
     int itn0 = 1;
-    if (sizeof(T) == 4 && g->dim == 3) {
-      // FP32: iterations 1 .. D fused (vector pass t with the product of
+    if (g->dim == 3) {
+      // voxel grids: iterations 1 .. D fused (vector pass t with the product of
       // t + 1); products alternate between two buffers, the Lanczos
       // vectors rotate through three (halo nodes read them while their
       // owners write the next one)

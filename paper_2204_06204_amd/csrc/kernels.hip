@@ -920,16 +920,26 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
             bload3(rs_d, A.invD ? ob : kOOR, dl);
           }
           const T D = ((dcol + dcorn[cb * TS + tl1]) + dcorn[cb * TS + tlb]) + dcorn[cb * TS + tlbb];
+          // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements,
+          // one value (and one division) for the node's three DOFs; springs
+          // and fixed DOFs (nodes with m != 0, rare) set single entries
+          const T d0 = (T)A.ke_diag * D;
+          T dinv0 = (T)0;
+          if (A.invD_out) dinv0 = d0 > (T)0 ? (T)1 / d0 : (T)0;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             rv[c] = fv[c] - acc[c];
-            if (A.invD_out) {  // Jacobi diagonal: ke_diag * sum of s over the node's 8 elements
-              T d = (T)A.ke_diag * D;
-              if (m & 8u)
-                for (int sI = 0; sI < A.nspring; ++sI)
-                  if (A.sdof[sI] == (int64_t)(3 * n + c)) d += A.sk[sI];
-              if ((m >> c) & 1u) d = (T)1;
-              dv[c] = d > (T)0 ? (T)1 / d : (T)0;
+            if (A.invD_out) {
+              T di = dinv0;
+              if (m) {
+                T d = d0;
+                if (m & 8u)
+                  for (int sI = 0; sI < A.nspring; ++sI)
+                    if (A.sdof[sI] == (int64_t)(3 * n + c)) d += A.sk[sI];
+                if ((m >> c) & 1u) d = (T)1;
+                di = d > (T)0 ? (T)1 / d : (T)0;
+              }
+              dv[c] = di;
             } else {
               dv[c] = dl[c];
             }
@@ -1526,20 +1536,16 @@ template <typename T>
 hipError_t launch_minres_fused(fbto_grid_s* g, const T* rho, int itn, const T* Y, const T* R1, const T* R2, T* R3,
                                const T* W, T* W2, T* x, T* Ynext, int n_apply, int n_kr, double damp,
                                hipStream_t st, int* nb_out) {
-  if constexpr (sizeof(T) == 8) {
-    return hipErrorNotSupported;
-  } else {
-    ApplyArgs<T> A{};
-    A.rho = rho;
-    A.y = Ynext;
-    A.step = itn;
-    A.mY = Y; A.mR1 = R1; A.mR2 = R2; A.mW = W;
-    A.mR3 = R3; A.mW2 = W2; A.mx = x;
-    A.n_apply = n_apply;
-    A.n_kr = n_kr;
-    A.damp = damp;
-    return launch_apply_mode<T, MODE_MRF>(g, A, 1, st, nb_out);
-  }
+  ApplyArgs<T> A{};
+  A.rho = rho;
+  A.y = Ynext;
+  A.step = itn;
+  A.mY = Y; A.mR1 = R1; A.mR2 = R2; A.mW = W;
+  A.mR3 = R3; A.mW2 = W2; A.mx = x;
+  A.n_apply = n_apply;
+  A.n_kr = n_kr;
+  A.damp = damp;
+  return launch_apply_mode<T, MODE_MRF>(g, A, 1, st, nb_out);
 }
 
 // ===========================================================================

@@ -400,19 +400,21 @@ def test_tile_option_limits():
 
 
 @pytest.mark.parametrize("tile", [(11, 20, 5), (32, 6, 3), (16, 8, 9)])
-def test_krylov_step_tile_override_matches_oracle(tile):
-    """The fused FP32 MINRES steps (one thread per node column) and the
-    residual kernels (one per element column) under tile overrides on a
-    ragged grid: the Krylov step still equals the oracle's."""
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_krylov_step_tile_override_matches_oracle(tile, dtype):
+    """The fused MINRES steps (one thread per node column) and the residual
+    kernels (one per element column) under tile overrides on a ragged grid:
+    the Krylov step still equals the oracle's."""
     bx, by, dz = tile
-    say(f"krylov tile {tile}")
+    say(f"krylov tile {tile} {dtype}")
     p = synth.cantilever(45, 14, 10, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=5, seed=6)
-    og, g, rho_t, s, K, D = _setup(p, torch.float32, 6)
+    og, g, rho_t, s, K, D = _setup(p, dtype, 6)
     g.set_option("apply_tile", bx | (by << 8) | (dz << 16))
     f = p.loads[0]
     u0 = np.zeros(p.ndof)
     deg = 6
-    u_t = dev(u0, torch.float32)
-    g.inner_solve(rho_t, dev(f, torch.float32), u_t, deg, method="krylov", omega=1.0)
+    u_t = dev(u0, dtype)
+    g.inner_solve(rho_t, dev(f, dtype), u_t, deg, method="krylov", omega=1.0)
     u_ref, _ = oracle.krylov_step_ref(lambda v: K @ v, f, u0, deg)
-    assert np.abs(host(u_t) - u_ref).max() <= 3e-4 * np.abs(u_ref).max()
+    tol = 1e-9 if dtype == torch.float64 else 3e-4
+    assert np.abs(host(u_t) - u_ref).max() <= tol * np.abs(u_ref).max()
