@@ -734,6 +734,20 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     }
   };
 
+  // The element stiffness constants.  The FP32 fused steps keep them in
+  // vector registers (copied once, here): in scalar registers they pushed
+  // the kernel past the scalar register file, and the spilled values came
+  // back by v_readlane in every layer.
+  Modal<T> km = A.km;
+  if constexpr (sizeof(T) == 4 && (MODE == MODE_CGF || MODE == MODE_MRF)) {
+    float* q = reinterpret_cast<float*>(&km);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(Modal<T>) / sizeof(float)); ++i) {
+      float v;
+      asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(q[i]));
+      q[i] = v;
+    }
+  }
   ApplyStage<T, NR> S[2];
   FusedStage<T> SF;
   MinresStage<T> SM;
@@ -827,10 +841,13 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const T s = scale_of(ez, rho_next);
     rho_next = load_rho(ez + 1);
     if constexpr (kOwnQ) load_own(ez + 1, oq[P ^ 1]);
-    if constexpr (MODE == MODE_CGF) {
-      issue_f(ez + 2, SF);
-    } else if constexpr (MODE == MODE_MRF) {
-      issue_m(ez + 2, SM);
+    if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
+      // the plane loads of the fused steps go out at a raised wave priority,
+      // ahead of the element products of the other waves on the SIMD
+      __builtin_amdgcn_s_setprio(2);
+      if constexpr (MODE == MODE_CGF) issue_f(ez + 2, SF);
+      else issue_m(ez + 2, SM);
+      __builtin_amdgcn_s_setprio(0);
     } else {
       issue(ez + 3, S[P ^ 1]);
     }
@@ -840,7 +857,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const bool emit = ez >= k0;  // uniform over the block
     T out[NR][4][3];
 #pragma unroll
-    for (int r = 0; r < NR; ++r) layer_product(F[P][r], F[P ^ 1][r], s, A.km, carry[r], out[r]);
+    for (int r = 0; r < NR; ++r) layer_product(F[P][r], F[P ^ 1][r], s, km, carry[r], out[r]);
     const int cb = ez & 1;
     if (emit && live) {
 #pragma unroll
