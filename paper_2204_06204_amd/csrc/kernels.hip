@@ -351,6 +351,19 @@ __device__ __forceinline__ void zstore1(__amdgpu_buffer_rsrc_t rs, uint32_t off,
 
 // A value that is the same in every lane of the wave, kept in a scalar
 // register (FP32; FP64 values stay in vector registers).
+// Wave priority around the plane loads of a z-march layer (FP32 only): the
+// loads then go out ahead of the element products of the other waves on the
+// SIMD.  Measured: FP32 fused steps 1.5-2.5% and the FP32 apply up to 2%
+// faster; the FP64 fused CG step at 256x128x128 ran 14% slower with it, so
+// FP64 keeps the default priority.
+template <typename T>
+__device__ __forceinline__ void loads_priority(bool raise) {
+  if constexpr (sizeof(T) == 4) {
+    if (raise) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(0);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_uniform(T v) {
   if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
@@ -841,16 +854,15 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
     const T s = scale_of(ez, rho_next);
     rho_next = load_rho(ez + 1);
     if constexpr (kOwnQ) load_own(ez + 1, oq[P ^ 1]);
-    if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
-      // the plane loads of the fused steps go out at a raised wave priority,
-      // ahead of the element products of the other waves on the SIMD
-      __builtin_amdgcn_s_setprio(2);
-      if constexpr (MODE == MODE_CGF) issue_f(ez + 2, SF);
-      else issue_m(ez + 2, SM);
-      __builtin_amdgcn_s_setprio(0);
+    loads_priority<T>(true);
+    if constexpr (MODE == MODE_CGF) {
+      issue_f(ez + 2, SF);
+    } else if constexpr (MODE == MODE_MRF) {
+      issue_m(ez + 2, SM);
     } else {
       issue(ez + 3, S[P ^ 1]);
     }
+    loads_priority<T>(false);
     const T dcol = s_below + s;  // this column's share of the lower-face nodes' diagonal
     s_below = s;
     read_face((ez + 1) & 1, F[P ^ 1], own[P ^ 1]);
@@ -1246,7 +1258,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
   auto layer = [&](auto parity, int ez) {
     constexpr int P = decltype(parity)::value;
     load_elem(ez + 1, ev[P ^ 1]);
+    loads_priority<T>(true);
     issue(ez + 2, S);
+    loads_priority<T>(false);
     read_face((ez + 1) & 1, F[P ^ 1]);
     {
       T c[3][8], z[3][8];
