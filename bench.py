@@ -554,8 +554,7 @@ def main():
                    + 3 * ndof * 4 + N + E * 4                   # step 0 product: z, r in; w out
                    + (m - 1) * bytes_fused                      # fused steps
                    + 8 * ndof * 4 + N + 3 * E * 4               # last step + sensitivity: x r p s w D^-1 f in, x out; rho, 1/Hs in, g out
-                   + 2 * E * 4                                  # filter transpose
-                   + 3 * E * 4                                  # step: x, g in, y out
+                   + 3 * E * 4                                  # filter transpose with the step: g, x in, y out
                    + 2 * E * 4                                  # projection: one or two working passes
                    + 3 * E * 4)                                 # final projection pass: y, x_old in, x out
 

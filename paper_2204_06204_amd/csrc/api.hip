@@ -450,11 +450,24 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
   if (s != FBTO_OK) return s;
   // element gradient already divided by Hs, so the filter transpose is a plain sum
   if (!sens_done) HIP_TRY(launch_sens<T>(g, rho, u, nullptr, nrhs, (T*)V.ge, (const T*)V.Hs, st));
-  HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 1, st));
   const double alpha_k = alpha0 * std::pow((double)k, -0.75);
-  HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
+  int nb_seed = 0;
+  hipError_t fe = hipErrorNotSupported;
+  if (sens_done) {
+    // the last CG step left the gradient's sum (slot GSUM, cn.dot partials):
+    // the filter and the step run as one pass
+    g->n_gsum = cn.dot;
+    fe = launch_filter_step<T>(g, (const T*)V.ge, x, (T*)V.y, 0.5 * alpha_k, mean_project, cn.dot, lo, 1.0, st,
+                               &nb_seed);
+    if (fe != hipSuccess && fe != hipErrorNotSupported) HIP_TRY(fe);
+  }
+  if (fe == hipErrorNotSupported) {
+    HIP_TRY(launch_filter<T>(g, 2, (const T*)V.ge, (T*)V.gx, 1, st));
+    HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
+    nb_seed = 0;
+  }
   HIP_TRY(launch_project<T>(proj_ws(g), g->geo.E, (const T*)V.y, x, lo, 1.0, vmax, 1, g->proj_passes_warm, x,
-                            nullptr, nullptr, st));
+                            nullptr, nullptr, st, nb_seed));
   const int nbE = vec_blocks(g->geo.E);
   HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
   return FBTO_OK;

@@ -276,6 +276,16 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
 template <typename T>
 hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
                        int mean_project, double lo, double hi, hipStream_t st);
+// The plain-sum filter of the element gradient ge fused with the design
+// step y = x - half_alpha (H ge - mean), leaving the projection's seed
+// partials (their count in *nb_seed).  The mean comes from nb_sum partials
+// in slot GSUM.  hipErrorNotSupported where the filter is not a z-march
+// (plane grids, stencils wider than 3): the caller then filters and steps
+// apart.
+template <typename T>
+hipError_t launch_filter_step(fbto_grid_s* g, const T* ge, const T* x, T* y, double half_alpha,
+                              int mean_project, int nb_sum, double lo, double hi, hipStream_t st,
+                              int* nb_seed);
 template <typename T>
 hipError_t launch_hs(fbto_grid_s* g, T* Hs, hipStream_t st);
 // Sort-based projection (project_sort.hip).  sort_ws_layout returns the
@@ -306,14 +316,15 @@ struct ProjWs {
   Scalars* sc;
 };
 // Projection of y onto {lo <= x <= hi, sum x <= vmax} with `passes` search
-// passes.  seeded: the seed partials (P_S0, P_YMAX, P_NACT) were left by
-// k_step and the search starts from the multiplier of the previous
+// passes.  seeded: the seed partials (P_S0, P_YMAX, P_NACT and evaluation
+// set 0) were left by the step, nb_seed of each (0: as many as the passes
+// write), and the search starts from the multiplier of the previous
 // projection; otherwise the seed pass runs and the search starts cold.
 // lam_out, status_out: device FP64 scalars, may be NULL.
 template <typename T>
 hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
                           int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
-                          hipStream_t st);
+                          hipStream_t st, int nb_seed = 0);
 template <typename T>
 hipError_t launch_convert(const void* in, void* out, int64_t n, int to_double, hipStream_t st);
 hipError_t launch_axpy64(double* u, const double* d, int64_t n, hipStream_t st);

@@ -1165,7 +1165,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     al = wave_uniform((T)alpha);
     be = wave_uniform((T)beta);
   };
-  double part[3] = {0.0, 0.0, 0.0};  // r'.r', max|r'|, f.x'
+  // r'.r', max|r'|, f.x', and the sum of the block's element sensitivities
+  double part[4] = {0.0, 0.0, 0.0, 0.0};
 
   auto owns = [&](int k) { return k >= 0 && k <= G.nz && writer && k >= k0 && k < kend; };
   auto issue = [&](int k, SensStage<T>& S) {
@@ -1279,8 +1280,11 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int q = 1; q < 8; ++q) en += (double)c[i][q] * (double)z[i][q];
-      const double val = -(double)simp_ds<T>(ev[P][0], A.sp) * en * (double)ev[P][1];
-      zstore1<T>(rs_do, eoff(ez), (T)val);
+      const double dc = -(double)simp_ds<T>(ev[P][0], A.sp) * en;  // d objective / d rho_e
+      zstore1<T>(rs_do, eoff(ez), (T)(dc * (double)ev[P][1]));
+      // The filter weights are symmetric, so the filtered gradient
+      // H^T (dc / Hs) sums to sum_e dc_e: its mean for the step, formed here.
+      part[3] += (elem_owner && ez >= k0 && ez < elem_end) ? dc : 0.0;
     }
     stage(S, ez & 1, ez + 2);
     __syncthreads();
@@ -1290,8 +1294,9 @@ __global__ void __launch_bounds__(kApplyMaxThreads)
     if (ez + 1 >= kend) break;
     layer(std::integral_constant<int, 1>{}, ez + 1);
   }
-  double* dst[3] = {pslot(A.P, P_RNF, 0, A.maxp), pslot(A.P, P_RIF, 0, A.maxp), pslot(A.P, P_DOT, 0, A.maxp)};
-  write_parts<3, 0x2u>(part, dst, lb);
+  double* dst[4] = {pslot(A.P, P_RNF, 0, A.maxp), pslot(A.P, P_RIF, 0, A.maxp), pslot(A.P, P_DOT, 0, A.maxp),
+                     pslot(A.P, P_GSUM, 0, A.maxp)};
+  write_parts<4, 0x2u>(part, dst, lb);
 }
 
 template <typename T>
@@ -2144,12 +2149,74 @@ __global__ void __launch_bounds__(kVecBlock)
 // neighbourhood in registers, so a slab of dz layers reads each input
 // (2R+1)^2 (dz + 2R) / dz times instead of (2R+1)^3.  Out-of-grid
 // neighbours load as 0 (the stencil is truncated at the boundary).
+// The evaluation of one search pass at lam for one entry: f(lam) and the
+// classification of the entry just right (+) and just left (-) of lam, plus
+// the nearest breakpoints on either side (slots of proj_decide).
+// (Written with selects only: branches here let the compiler pick v[9] or
+// v[10] by a dynamic index, which puts the array in scratch memory.)
+__device__ __forceinline__ void proj_eval(double (&v)[11], double yd, double lam, double lo, double hi) {
+  const double t = yd - lam;
+  v[0] += fmin(fmax(t, lo), hi);
+  const bool rU = t > hi, rL = !rU && t <= lo, rA = !rU && !rL;   // just right of lambda
+  v[3] += rU ? 1.0 : 0.0;
+  v[4] += rL ? 1.0 : 0.0;
+  v[1] += rA ? 1.0 : 0.0;
+  v[2] += rA ? yd : 0.0;
+  const bool lU = t >= hi, lL = !lU && t < lo, lA = !lU && !lL;   // just left of lambda
+  v[7] += lU ? 1.0 : 0.0;
+  v[8] += lL ? 1.0 : 0.0;
+  v[5] += lA ? 1.0 : 0.0;
+  v[6] += lA ? yd : 0.0;
+  const double b1 = yd - lo, b2 = yd - hi;
+  v[9] = fmax(v[9], fmax(b1 < lam ? b1 : -INFINITY, b2 < lam ? b2 : -INFINITY));
+  v[10] = fmax(v[10], fmax(b1 > lam ? -b1 : -INFINITY, b2 > lam ? -b2 : -INFINITY));
+}
+__device__ __forceinline__ void proj_eval_init(double (&v)[11]) {
+#pragma unroll
+  for (int i = 0; i < 11; ++i) v[i] = 0.0;
+  v[9] = -INFINITY;
+  v[10] = -INFINITY;
+}
+
+// The step's partials of one block in one reduction: the projection's seed
+// (sum clamp(y), max y, #interior: slots S0, YMAX, NACT) and the evaluation
+// at the warm-start multiplier (evaluation set 0, the next 11 slots).
+static_assert(P_YMAX == P_S0 + 1 && P_NACT == P_S0 + 2 && P_E0 == P_S0 + 3, "seed and set 0 are consecutive slots");
+template <int NTHR>
+__device__ __forceinline__ void step_parts(double (&v3)[3], double (&ev)[11], double* P, int maxp) {
+  double w[14];
+  double* dst[14];
+#pragma unroll
+  for (int i = 0; i < 14; ++i) {
+    w[i] = i < 3 ? v3[i] : ev[i - 3];
+    dst[i] = pslot(P, P_S0 + i, 0, maxp);
+  }
+  // max-reduced: max y (1) and the nearest breakpoints (3 + 9, 3 + 10)
+  write_parts<14, 0x3002u, NTHR>(w, dst, blockIdx.x);
+}
+
 constexpr int kFiltBX = 64, kFiltBY = 4, kFiltDZ = 4;
 
-template <typename T, int R>
+// The gradient step fused into the plain-sum filter (the transposed filter
+// after the 1/Hs fold): each filtered value g_e gives y_e = x_e -
+// half_alpha (g_e - mean), with the projection's seed and its evaluation at
+// the warm-start multiplier, as k_step forms them.  The mean comes from the
+// partials in slot GSUM (the sensitivity kernel's sum of the unfiltered
+// gradient, equal to the filtered one's since the weights are symmetric).
+template <typename T>
+struct FiltStep {
+  const T* x;
+  T* y;
+  double half_alpha;
+  int mean_project, nb_sum;
+  double lo, hi;
+  const Scalars* sc;
+};
+
+template <typename T, int R, bool STEP>
 __global__ void __launch_bounds__(kFiltBX * kFiltBY)
     k_filter_z(Geo G, int kind, const T* in, T* out, const T* Hsi, StencilW<T, R> W, int want_sum,
-               double* P, int maxp, int tiles_x, int tiles_y) {
+               double* P, int maxp, int tiles_x, int tiles_y, FiltStep<T> S) {
   constexpr int D = 2 * R + 1;
   const int tx = threadIdx.x % kFiltBX, ty = threadIdx.x / kFiltBX;
   const int b = blockIdx.x;
@@ -2187,7 +2254,28 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
         win[p][dy][dx] = ok ? v : (T)0;
       }
   }
+  // step: the design values of the slab's outputs, and the mean of g
+  T xv[kFiltDZ];
+  double mean = 0.0, lam_w = 0.0;
+  if constexpr (STEP) {
+#pragma unroll
+    for (int l = 0; l < kFiltDZ; ++l) {
+      const int ez = z0 + l;
+      xv[l] = S.x[(col && ez < z1) ? ex + G.nx * (ey + G.ny * ez) : 0];
+    }
+    lam_w = S.sc->lam_prev;
+    if (S.mean_project) {
+      double v[1];
+      const double* src[1] = {pslot(P, P_GSUM, 0, maxp)};
+      const int cnt[1] = {S.nb_sum};
+      reduce_parts<1, 0u, kFiltBX * kFiltBY>(v, src, cnt);
+      mean = v[0] / (double)G.E;
+    }
+  }
   double vs[1] = {0.0};
+  double v3[3] = {0.0, -INFINITY, 0.0};  // step: sum clamp(y), max y, #interior
+  double ev[11];                         // step: evaluation at lam_w
+  proj_eval_init(ev);
 #pragma unroll
   for (int l = 0; l < kFiltDZ; ++l) {
     const int ez = z0 + l;
@@ -2201,11 +2289,23 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
     if (col && ez < z1) {
       const int e = ex + G.nx * (ey + G.ny * ez);
       const T res = kind == FILT_FWD ? acc * Hsi[e] : acc;
-      out[e] = res;
-      vs[0] += (double)res;
+      if constexpr (STEP) {
+        const T ye = (T)((double)xv[l] - S.half_alpha * ((double)res - mean));
+        S.y[e] = ye;
+        const double yd = (double)ye;
+        v3[0] += fmin(fmax(yd, S.lo), S.hi);
+        v3[1] = fmax(v3[1], yd);
+        v3[2] += (yd > S.lo && yd < S.hi) ? 1.0 : 0.0;
+        proj_eval(ev, yd, lam_w, S.lo, S.hi);
+      } else {
+        out[e] = res;
+        vs[0] += (double)res;
+      }
     }
   }
-  if (want_sum) {
+  if constexpr (STEP) {
+    step_parts<kFiltBX * kFiltBY>(v3, ev, P, maxp);
+  } else if (want_sum) {
     double* dst[1] = {pslot(P, P_GSUM, 0, maxp)};
     write_parts<1, 0u>(vs, dst, blockIdx.x);
   }
@@ -2286,11 +2386,13 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
   if (R <= 1 && nbz <= g->max_partials) {
     if (want_sum) g->n_gsum = (int)nbz;
     if (R == 0)
-      hipLaunchKernelGGL((k_filter_z<T, 0>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out, Hsi,
-                         stencil_weights<T, 0>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y);
+      hipLaunchKernelGGL((k_filter_z<T, 0, false>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out,
+                         Hsi, stencil_weights<T, 0>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y,
+                         FiltStep<T>{});
     else
-      hipLaunchKernelGGL((k_filter_z<T, 1>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out, Hsi,
-                         stencil_weights<T, 1>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y);
+      hipLaunchKernelGGL((k_filter_z<T, 1, false>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, kind, in, out,
+                         Hsi, stencil_weights<T, 1>(r), want_sum, g->partials, g->max_partials, tiles_x, tiles_y,
+                         FiltStep<T>{});
     return hipGetLastError();
   }
   if (want_sum) g->n_gsum = nb;
@@ -2304,6 +2406,32 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
     hipLaunchKernelGGL((k_filter_wide<T>), dim3(nb), dim3(kVecBlock), 0, st, g->geo, kind, in, out, Hsi,
                        g->n_stencil, (const int*)g->stencil_off, stencil_w_of<T>(g), want_sum, g->partials,
                        g->max_partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_filter_step(fbto_grid_s* g, const T* ge, const T* x, T* y, double half_alpha,
+                              int mean_project, int nb_sum, double lo, double hi, hipStream_t st,
+                              int* nb_seed) {
+  if (g->dim == 2) return hipErrorNotSupported;
+  const double r = g->desc.filter_radius;
+  const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
+  const Geo& G = g->geo;
+  const int tiles_x = (G.nx + kFiltBX - 1) / kFiltBX, tiles_y = (G.ny + kFiltBY - 1) / kFiltBY;
+  const int64_t nbz = (int64_t)tiles_x * tiles_y * ((G.nz + kFiltDZ - 1) / kFiltDZ);
+  if (R > 1 || nbz > g->max_partials) return hipErrorNotSupported;
+  if (mean_project && (nb_sum < 1 || nb_sum > g->max_partials)) return hipErrorInvalidValue;
+  const FiltStep<T> S{x, y, half_alpha, mean_project, nb_sum, lo, hi, (const Scalars*)g->sc};
+  const T* Hsi = (const T*)vecs_of<T>(g).Hs;  // not read by the plain sum
+  if (R == 0)
+    hipLaunchKernelGGL((k_filter_z<T, 0, true>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, (int)FILT_SUM, ge,
+                       (T*)nullptr, Hsi, stencil_weights<T, 0>(r), 0, g->partials, g->max_partials, tiles_x,
+                       tiles_y, S);
+  else
+    hipLaunchKernelGGL((k_filter_z<T, 1, true>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, (int)FILT_SUM, ge,
+                       (T*)nullptr, Hsi, stencil_weights<T, 1>(r), 0, g->partials, g->max_partials, tiles_x,
+                       tiles_y, S);
+  *nb_seed = (int)nbz;
   return hipGetLastError();
 }
 
@@ -2327,36 +2455,6 @@ template hipError_t launch_hs<float>(fbto_grid_s*, float*, hipStream_t);
 // pass solves that piece exactly; if the solution leaves the piece (beyond
 // the nearest breakpoint) it becomes a Newton step safeguarded by the
 // bracket [a, b] with f(a) > vmax >= f(b), else bisection.
-// ===========================================================================
-// The evaluation of one search pass at lam for one entry: f(lam) and the
-// classification of the entry just right (+) and just left (-) of lam, plus
-// the nearest breakpoints on either side (slots of proj_decide).
-// (Written with selects only: branches here let the compiler pick v[9] or
-// v[10] by a dynamic index, which puts the array in scratch memory.)
-__device__ __forceinline__ void proj_eval(double (&v)[11], double yd, double lam, double lo, double hi) {
-  const double t = yd - lam;
-  v[0] += fmin(fmax(t, lo), hi);
-  const bool rU = t > hi, rL = !rU && t <= lo, rA = !rU && !rL;   // just right of lambda
-  v[3] += rU ? 1.0 : 0.0;
-  v[4] += rL ? 1.0 : 0.0;
-  v[1] += rA ? 1.0 : 0.0;
-  v[2] += rA ? yd : 0.0;
-  const bool lU = t >= hi, lL = !lU && t < lo, lA = !lU && !lL;   // just left of lambda
-  v[7] += lU ? 1.0 : 0.0;
-  v[8] += lL ? 1.0 : 0.0;
-  v[5] += lA ? 1.0 : 0.0;
-  v[6] += lA ? yd : 0.0;
-  const double b1 = yd - lo, b2 = yd - hi;
-  v[9] = fmax(v[9], fmax(b1 < lam ? b1 : -INFINITY, b2 < lam ? b2 : -INFINITY));
-  v[10] = fmax(v[10], fmax(b1 > lam ? -b1 : -INFINITY, b2 > lam ? -b2 : -INFINITY));
-}
-__device__ __forceinline__ void proj_eval_init(double (&v)[11]) {
-#pragma unroll
-  for (int i = 0; i < 11; ++i) v[i] = 0.0;
-  v[9] = -INFINITY;
-  v[10] = -INFINITY;
-}
-
 // The gradient step y = x - alpha/2 (g - mean g), with the seed of the
 // projection (sum clamp(y), max y, #interior) and its first evaluation, at
 // the multiplier of the previous projection (the warm start), into
@@ -2387,12 +2485,7 @@ __global__ void __launch_bounds__(kVecBlock)
     v[2] += (yd > lo && yd < hi) ? 1.0 : 0.0;
     proj_eval(ev, yd, lam_w, lo, hi);
   }
-  double* dst[3] = {pslot(P, P_S0, 0, maxp), pslot(P, P_YMAX, 0, maxp), pslot(P, P_NACT, 0, maxp)};
-  write_parts<3, 0x2u, kVecBlock>(v, dst, blockIdx.x);
-  double* edst[11];
-#pragma unroll
-  for (int i = 0; i < 11; ++i) edst[i] = pslot(P, P_E0 + i, 0, maxp);  // evaluation set 0
-  write_parts<11, 0x600u, kVecBlock>(ev, edst, blockIdx.x);
+  step_parts<kVecBlock>(v, ev, P, maxp);
 }
 
 __device__ __forceinline__ double* lslot(const ProjWs& W, int i) { return W.base + i * W.stride; }
@@ -2533,6 +2626,8 @@ template <typename T>
 __global__ void __launch_bounds__(kVecBlock)
     k_proj_pass(int64_t E, const T* y, double lo, double hi, double vmax, int pass, ProjWs W, int nb,
                 int warm_eval) {
+  // nb: the partials the decision reduces (on pass 0 the seed's, which the
+  // step may have written with another grid)
   Scalars* sc = W.sc;
   const double* in = sc->ps[pass & 1];
   double* out = sc->ps[(pass + 1) & 1];
@@ -2618,14 +2713,16 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
 template <typename T>
 hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
                           int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
-                          hipStream_t st) {
+                          hipStream_t st, int nb_seed) {
   const int nb = vec_blocks(E);
-  if (nb > W.maxp) return hipErrorInvalidValue;
+  if (nb > W.maxp || nb_seed > W.maxp) return hipErrorInvalidValue;
+  if (!seeded || nb_seed < 1) nb_seed = nb;
   if (!seeded) {
     hipLaunchKernelGGL((k_proj_init<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, W);
   }
   for (int p = 0; p < passes; ++p) {
-    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W, nb, seeded);
+    hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W,
+                       p == 0 ? nb_seed : nb, seeded);
   }
   hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W, nb,
                      passes, lam_out, status_out);
@@ -2782,7 +2879,9 @@ hipError_t launch_opt_finish(fbto_grid_s* g, int nrhs, int nb_dot, int nb_lo, in
   template hipError_t launch_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, double,       \
                                      double, hipStream_t);                                             \
   template hipError_t launch_project<T>(const ProjWs&, int64_t, const T*, T*, double, double, double, int, \
-                                        int, const T*, double*, double*, hipStream_t);
+                                        int, const T*, double*, double*, hipStream_t, int);               \
+  template hipError_t launch_filter_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, int, double, \
+                                            double, hipStream_t, int*);
 
 FBTO_INST(double)
 FBTO_INST(float)
