@@ -218,6 +218,33 @@ def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None, exact_rtol=None):
     return recs, xs, host(u)
 
 
+@pytest.mark.parametrize("radius", [1.5, 3.0])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_outer_gradient_mean_and_step(radius, dtype):
+    """One outer step against the oracle: the recorded mean of the filtered
+    gradient (before the mean projection) and the design after the step.
+    With r = 1.5 the step runs inside the transposed filter and takes the
+    mean from the sum the sensitivity kernel forms (equal, as the filter
+    weights are symmetric); with r = 3 the filter and the step are two
+    kernels and the mean is summed from the filtered gradient."""
+    from oracle.outer import default_alpha0
+    say(f"outer gradient mean r={radius} {dtype}")
+    p = synth.cantilever(20, 11, 9, volfrac=0.3, filter_radius=radius, outer_iters=1, inner_steps=5, seed=7)
+    ctx = OuterContext(p.nx, p.ny, p.nz, p.filter_radius, p.fixed_mask, p.springs)
+    F = np.atleast_2d(p.loads[0])
+    a0 = default_alpha0(ctx, p.x0, F, p.inner_steps, 0.0, 1.0, p.vmax)
+    x0 = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
+    u0 = np.zeros_like(F)
+    _, _, _, g_plain = outer_step_ref(ctx, x0, u0, F, 1, a0, p.inner_steps, 0.0, 1.0, p.vmax, mean_project=False)
+    x_ref, _, rec, _ = outer_step_ref(ctx, x0, u0, F, 1, a0, p.inner_steps, 0.0, 1.0, p.vmax)
+    recs, xs, _ = _run_gpu(p, 1, a0, dtype)
+    tol = 1e-10 if dtype == torch.float64 else 2e-5
+    scale = np.abs(g_plain).mean()
+    assert abs(recs[0][7] - g_plain.mean()) <= tol * scale, (recs[0][7], g_plain.mean())
+    assert np.abs(xs[0] - x_ref).max() <= (1e-9 if dtype == torch.float64 else 2e-5)
+    assert abs(recs[0][3] - rec.lam) <= (1e-9 if dtype == torch.float64 else 2e-5) * max(1.0, abs(rec.lam))
+
+
 def test_outer_trajectory_cfg1_fp64():
     """16x8x8 cantilever, 50 outer iterations x 5 PCG steps in FP64 against
     the oracle: compliance and design agree to 1e-9 relative."""
