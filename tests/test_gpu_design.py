@@ -220,13 +220,16 @@ def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None, exact_rtol=None):
 
 @pytest.mark.parametrize("radius", [1.5, 3.0])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-def test_outer_gradient_mean_and_step(radius, dtype):
+@pytest.mark.parametrize("mean_project", [True, False])
+def test_outer_gradient_mean_and_step(radius, dtype, mean_project):
     """One outer step against the oracle: the recorded mean of the filtered
     gradient (before the mean projection) and the design after the step.
     With r = 1.5 the step runs inside the transposed filter and takes the
     mean from the sum the sensitivity kernel forms (equal, as the filter
     weights are symmetric); with r = 3 the filter and the step are two
-    kernels and the mean is summed from the filtered gradient."""
+    kernels and the mean is summed from the filtered gradient.  Without the
+    mean projection the step uses the gradient as it is (the mean is still
+    recorded)."""
     from oracle.outer import default_alpha0
     say(f"outer gradient mean r={radius} {dtype}")
     p = synth.cantilever(20, 11, 9, volfrac=0.3, filter_radius=radius, outer_iters=1, inner_steps=5, seed=7)
@@ -236,8 +239,15 @@ def test_outer_gradient_mean_and_step(radius, dtype):
     x0 = oracle.project_volume_ref(p.x0, 0.0, 1.0, p.vmax)
     u0 = np.zeros_like(F)
     _, _, _, g_plain = outer_step_ref(ctx, x0, u0, F, 1, a0, p.inner_steps, 0.0, 1.0, p.vmax, mean_project=False)
-    x_ref, _, rec, _ = outer_step_ref(ctx, x0, u0, F, 1, a0, p.inner_steps, 0.0, 1.0, p.vmax)
-    recs, xs, _ = _run_gpu(p, 1, a0, dtype)
+    x_ref, _, rec, _ = outer_step_ref(ctx, x0, u0, F, 1, a0, p.inner_steps, 0.0, 1.0, p.vmax,
+                                      mean_project=mean_project)
+    g = _grid(p)
+    x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
+    u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+    info = torch.zeros(8, dtype=torch.float64, device=DEV)
+    g.outer_step(x, u, dev(p.loads[0], dtype), 1, a0, p.inner_steps, 0.0, p.vmax, mean_project=mean_project,
+                 info=info)
+    recs, xs = [host(info)], [host(x)]
     tol = 1e-10 if dtype == torch.float64 else 2e-5
     scale = np.abs(g_plain).mean()
     assert abs(recs[0][7] - g_plain.mean()) <= tol * scale, (recs[0][7], g_plain.mean())
