@@ -9,7 +9,9 @@ filter, SIMP scaling and Jacobi diagonal, 8 warm-started Jacobi-PCG steps
 mean-projected gradient step and FP64 projection onto the volume box.
 Inputs are seeded synthetic data resident in HBM before timing starts.
 Prints ONE JSON line (rank 0).  The value is outer iterations per second
-of the FP32 path (FP32 storage and arithmetic, FP64 reductions); the same
+of the FP32 path (FP32 storage and arithmetic, FP64 reductions), the K
+timed iterations run in one fbto_outer_steps call (`one_call_per_iteration`
+times them one fbto_outer_step call each); the same
 line carries the FP64 path, the K(rho)u rate in GDOF/s with its roofline
 fraction, the time to a fixed residual (FP32 + FP64 refinement vs FP64),
 and the CPU oracle timed on the host cores.  `roofline` is that of the
@@ -83,11 +85,14 @@ def parse():
     return ap.parse_args()
 
 
-def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None, alpha0=None, true_obj=True):
+def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None, alpha0=None, true_obj=True,
+               multi=False):
     """Times `steps` outer iterations after `warmup` untimed ones (Alg. 1
     with Jacobi-PCG, or with krylov=D Alg. 3 with the Krylov preconditioner
     of degree D, beta = 1, or with exact_rtol projected gradient descent
-    with the low-level problem solved to that relative residual)."""
+    with the low-level problem solved to that relative residual).  multi
+    (Alg. 1): the warm-up iterations in one fbto_outer_steps call, the timed
+    ones in another; else one fbto_outer_step call per iteration."""
     dev = torch.device("cuda:0")
     x = g.project_volume(torch.tensor(p.x0, dtype=dtype, device=dev), lo=0.0, hi=1.0, vmax=p.vmax)
     u = torch.zeros(p.ndof, dtype=dtype, device=dev)
@@ -95,6 +100,22 @@ def outer_loop(g, p, dtype, steps, warmup, torch, krylov=None, exact_rtol=None, 
     info = torch.zeros(8, dtype=torch.float64, device=dev)
     k = 1
     a0 = ALPHA0_CFG3 if alpha0 is None else alpha0
+    if multi:
+        assert krylov is None and exact_rtol is None
+        infos = torch.zeros(8 * max(steps, warmup, 1), dtype=torch.float64, device=dev)
+        if warmup:
+            g.outer_steps(x, u, f, k, warmup, a0, p.inner_steps, 0.0, p.vmax, info=infos)
+            k += warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.outer_steps(x, u, f, k, steps, a0, p.inner_steps, 0.0, p.vmax, info=infos)
+        k += steps
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        inf = infos[8 * (steps - 1):8 * steps].cpu().tolist()
+        return dt, {"compliance": inf[0], "dx_inf": inf[1], "r_inf": inf[2], "lambda": inf[3],
+                    "volume": inf[4], "status": inf[6], "k_last": k - 1,
+                    "true_compliance": true_compliance(g, p, x, torch) if true_obj else None}
     def step(k):
         if exact_rtol is not None:
             g.outer_step(x, u, f, k, a0, 100000, 0.0, p.vmax, info=info, method="exact", rtol=exact_rtol)
@@ -491,7 +512,7 @@ def main():
         elif args.profile_only == "project":
             print(json.dumps(projection_timing(torch)), flush=True)
         elif args.profile_only == "outer":
-            outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, true_obj=False)
+            outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, true_obj=False, multi=True)
         elif args.profile_only == "fused_large":
             # FP32 Jacobi-PCG solves of 41 steps (40 fused steps each) on the
             # 384x192x192 cantilever with one load case
@@ -522,9 +543,10 @@ def main():
         print(f"profile-only {args.profile_only} done", flush=True)
         return
 
-    dt32, st32 = outer_loop(g, p, torch.float32, args.steps, args.warmup, torch)
+    dt32, st32 = outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, multi=True)
+    dt32c, _ = outer_loop(g, p, torch.float32, args.steps, args.warmup, torch, true_obj=False)
     steps64 = max(10, args.steps // 2)
-    dt64, st64 = outer_loop(g, p, torch.float64, steps64, args.warmup // 2, torch)
+    dt64, st64 = outer_loop(g, p, torch.float64, steps64, args.warmup // 2, torch, multi=True)
     steps_cp = max(10, args.steps // 4)
     dtcp, stcp = outer_loop(g, p, torch.float32, steps_cp, args.warmup // 2, torch, krylov=KRYLOV_DEGREE)
     dtcp64, _ = outer_loop(g, p, torch.float64, steps_cp, args.warmup // 2, torch, krylov=KRYLOV_DEGREE,
@@ -584,7 +606,8 @@ def main():
         "data": "synthetic (seeded U[0.2,0.4] densities, unit tip load), no dataset",
         "config": {"workload": "hex8 cantilever 128x64x64 (524,288 elements, 1,635,075 DOFs), "
                                "one outer iteration = filter r=2 + 8 Jacobi-PCG steps + sensitivity "
-                               "+ filter^T + mean-projected step + FP64 volume projection",
+                               "+ filter^T + mean-projected step + FP64 volume projection; the timed "
+                               "iterations run in one fbto_outer_steps call",
                    "elements": E, "dofs": ndof, "inner_steps": p.inner_steps, "volfrac": p.volfrac,
                    "filter_radius": p.filter_radius, "alpha0": ALPHA0_CFG3,
                    "precision": "fp32 storage and arithmetic, fp64 dot products / norms / projection"},
@@ -600,6 +623,9 @@ def main():
             "fp64_cold_hbm_frac": bytes64 / t_apply64_cold / 1e9 / HBM_PEAK_GBS,
         },
         "apply_K_sizes": sizes,
+        "one_call_per_iteration": {"outer_iter_s": args.steps / dt32c, "ms_per_step": dt32c / args.steps * 1e3,
+                                   "note": "the same FP32 iterations, one fbto_outer_step call each (value: "
+                                           "the K timed iterations in one fbto_outer_steps call)"},
         "fp64_path": {"outer_iter_s": steps64 / dt64, "ms_per_step": dt64 / steps64 * 1e3},
         "cpfbto_path": {"outer_iter_s": steps_cp / dtcp, "ms_per_step": dtcp / steps_cp * 1e3,
                         "krylov_degree": KRYLOV_DEGREE, "beta": 1.0, "products_per_step": KRYLOV_DEGREE + 3,

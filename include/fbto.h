@@ -302,6 +302,19 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
                               int32_t inner_steps, int32_t mean_project, double lo,
                               double vmax, double* info, void* stream);
 
+/* Outer iterations k .. k + n_steps - 1 of Alg. 1 in one call: the same
+ * results as n_steps calls of fbto_outer_step, bitwise.  Since x changes
+ * only inside the call, the final projection pass of an iteration also
+ * filters the new x for the next one (voxel grids with a filter radius of at
+ * most 2), one pass over the elements fewer per iteration.
+ * info: device FP64 [n_steps][FBTO_OUTER_INFO], one record per iteration
+ * (may be NULL).  Errors: as fbto_outer_step; FBTO_ERR_ARG if n_steps < 1;
+ * an error stops the call after the iteration it occurred in. */
+fbto_status_t fbto_outer_steps(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
+                               const void* f, int32_t nrhs, int32_t k, int32_t n_steps,
+                               double alpha0, int32_t inner_steps, int32_t mean_project,
+                               double lo, double vmax, double* info, void* stream);
+
 /* One step of projected gradient descent with an exact low-level solve,
  * the baseline the paper compares against (Sec. 5): as fbto_outer_step,
  * but u is refined by Jacobi-PCG until ||f - K u||_2 <= rtol ||f||_2 (or

@@ -55,6 +55,8 @@ _SIGS = {
                                              _VP, _VP]),
     "fbto_outer_step": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                   C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
+    "fbto_outer_steps": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                   C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_exact": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,
                                         C.c_double, C.c_int32, C.c_int32, C.c_double, C.c_double, _VP, _VP]),
     "fbto_outer_step_krylov": (C.c_int, [_VP, C.c_int, _VP, _VP, _VP, C.c_int32, C.c_int32, C.c_double,

@@ -434,13 +434,21 @@ fbto_status_t krylov_run(fbto_grid_s* g, const T* rho, const T* f, T* u, int nrh
 // One outer iteration: Alg. 1 with `inner_steps` Jacobi-PCG steps, or
 // (krylov_degree >= 0) Alg. 3 with one Krylov-preconditioned step of that
 // degree and step beta.
+//
+// rho_ready (several iterations in one call): on entry, whether the filtered
+// density of x is already in V.rho (left by the previous iteration); on
+// return, whether this iteration left the next one's there.  fuse_next: the
+// final projection pass also filters the new design (another iteration
+// follows in the same call, so x does not change in between).
 template <typename T>
 fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k, double alpha0,
                         int inner_steps, int mean_project, double lo, double vmax, double* info,
-                        hipStream_t st, int krylov_degree = -1, double beta = 1.0, double inner_rtol = 0.0) {
+                        hipStream_t st, int krylov_degree = -1, double beta = 1.0, double inner_rtol = 0.0,
+                        bool* rho_ready = nullptr, bool fuse_next = false) {
   Vecs& V = vecs<T>(g);
   T* rho = (T*)V.rho;
-  HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
+  if (!(rho_ready && *rho_ready)) HIP_TRY(launch_filter<T>(g, 0, x, rho, 0, st));
+  if (rho_ready) *rho_ready = false;
   CgCounts cn{};
   bool sens_done = false;
   fbto_status_t s = krylov_degree >= 0
@@ -466,9 +474,19 @@ fbto_status_t outer_run(fbto_grid_s* g, T* x, T* u, const T* f, int nrhs, int k,
     HIP_TRY(launch_step<T>(g, x, (const T*)V.gx, (T*)V.y, 0.5 * alpha_k, mean_project, lo, 1.0, st));
     nb_seed = 0;
   }
-  HIP_TRY(launch_project<T>(proj_ws(g), g->geo.E, (const T*)V.y, x, lo, 1.0, vmax, 1, g->proj_passes_warm, x,
-                            nullptr, nullptr, st, nb_seed));
-  const int nbE = vec_blocks(g->geo.E);
+  int nbE = vec_blocks(g->geo.E);  // the final pass's volume partials
+  if (fuse_next && zmarch_filter(g)) {
+    // the search passes, then the final pass fused with the next iteration's
+    // forward filter
+    HIP_TRY(launch_project<T>(proj_ws(g), g->geo.E, (const T*)V.y, x, lo, 1.0, vmax, 1, g->proj_passes_warm, x,
+                              nullptr, nullptr, st, nb_seed, 1));
+    HIP_TRY(launch_proj_final_filter<T>(g, proj_ws(g), (const T*)V.y, x, rho, lo, 1.0, vmax, g->proj_passes_warm,
+                                        st, &nbE));
+    if (rho_ready) *rho_ready = true;
+  } else {
+    HIP_TRY(launch_project<T>(proj_ws(g), g->geo.E, (const T*)V.y, x, lo, 1.0, vmax, 1, g->proj_passes_warm, x,
+                              nullptr, nullptr, st, nb_seed));
+  }
   HIP_TRY(launch_pcg_finish(g, nrhs, cn.r, cn.fn, info, cn.dot, nbE, g->n_gsum, st));
   return FBTO_OK;
 }
@@ -1068,6 +1086,37 @@ fbto_status_t fbto_outer_step(fbto_grid_t g, fbto_prec_t prec, void* x, void* u,
                          mean_project, lo, vmax, info, st);
   }
   if (s) return s;
+  return ok();
+}
+
+fbto_status_t fbto_outer_steps(fbto_grid_t g, fbto_prec_t prec, void* x, void* u, const void* f,
+                               int32_t nrhs, int32_t k, int32_t n_steps, double alpha0, int32_t inner_steps,
+                               int32_t mean_project, double lo, double vmax, double* info, void* stream) {
+  if (check_grid(g) || check_prec(prec) || check_nrhs(g, nrhs)) return FBTO_ERR_ARG;
+  if (!x || !u || !f) return fail(FBTO_ERR_ARG, "x, u and f must be non-NULL");
+  if (k < 1) return fail(FBTO_ERR_ARG, "k is 1-based");
+  if (n_steps < 1) return fail(FBTO_ERR_ARG, "n_steps = %d: need at least one iteration", (int)n_steps);
+  if (n_steps > INT32_MAX - k) return fail(FBTO_ERR_ARG, "k + n_steps overflows");
+  if (inner_steps < 0) return fail(FBTO_ERR_ARG, "inner_steps must be >= 0");
+  if (!(std::isfinite(alpha0) && alpha0 >= 0.0)) return fail(FBTO_ERR_ARG, "alpha0 must be finite and >= 0");
+  if (!(std::isfinite(lo) && lo <= 1.0)) return fail(FBTO_ERR_ARG, "need lo <= 1");
+  if (vmax < lo * (double)g->geo.E)
+    return fail(FBTO_ERR_INFEASIBLE, "vmax = %g < lo * E = %g", vmax, lo * (double)g->geo.E);
+  hipStream_t st = (hipStream_t)stream;
+  fbto_status_t s = prec == FBTO_F64 ? ensure_vecs<double>(g) : ensure_vecs<float>(g);
+  if (s) return s;
+  bool rho_ready = false;  // the first iteration filters the caller's x
+  for (int32_t i = 0; i < n_steps; ++i) {
+    double* inf = info ? info + (int64_t)i * FBTO_OUTER_INFO : nullptr;
+    const bool fuse_next = i + 1 < n_steps;
+    if (prec == FBTO_F64)
+      s = outer_run<double>(g, (double*)x, (double*)u, (const double*)f, nrhs, k + i, alpha0, inner_steps,
+                            mean_project, lo, vmax, inf, st, -1, 1.0, 0.0, &rho_ready, fuse_next);
+    else
+      s = outer_run<float>(g, (float*)x, (float*)u, (const float*)f, nrhs, k + i, alpha0, inner_steps,
+                           mean_project, lo, vmax, inf, st, -1, 1.0, 0.0, &rho_ready, fuse_next);
+    if (s) return s;
+  }
   return ok();
 }
 

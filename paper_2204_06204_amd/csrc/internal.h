@@ -321,10 +321,20 @@ struct ProjWs {
 // write), and the search starts from the multiplier of the previous
 // projection; otherwise the seed pass runs and the search starts cold.
 // lam_out, status_out: device FP64 scalars, may be NULL.
+// skip_final: launch the search passes only (the caller runs the final
+// pass, fused with the next forward filter: launch_proj_final_filter).
 template <typename T>
 hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
                           int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
-                          hipStream_t st, int nb_seed = 0);
+                          hipStream_t st, int nb_seed = 0, int skip_final = 0);
+bool zmarch_filter(const fbto_grid_s* g);
+// The final pass (x updated in place, x_old = x) fused with the forward
+// filter of the new design into rho, after launch_project(.., skip_final),
+// where zmarch_filter(g) holds (else hipErrorNotSupported).  *nb_final: the
+// count of the volume partials (slots VOL, DX).
+template <typename T>
+hipError_t launch_proj_final_filter(fbto_grid_s* g, const ProjWs& W, const T* y, T* x, T* rho, double lo,
+                                    double hi, double vmax, int passes, hipStream_t st, int* nb_final);
 template <typename T>
 hipError_t launch_convert(const void* in, void* out, int64_t n, int to_double, hipStream_t st);
 hipError_t launch_axpy64(double* u, const double* d, int64_t n, hipStream_t st);

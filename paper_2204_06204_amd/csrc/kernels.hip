@@ -2213,17 +2213,36 @@ struct FiltStep {
   const Scalars* sc;
 };
 
-template <typename T, int R, bool STEP>
-__global__ void __launch_bounds__(kFiltBX * kFiltBY)
-    k_filter_z(Geo G, int kind, const T* in, T* out, const T* Hsi, StencilW<T, R> W, int want_sum,
-               double* P, int maxp, int tiles_x, int tiles_y, FiltStep<T> S) {
-  constexpr int D = 2 * R + 1;
+// Thread geometry of the z-march filter: tile b of 64 x 4 element columns
+// and kFiltDZ layers; the thread's column (ex, ey) and output layers
+// [z0, z1).
+struct FiltPos {
+  int ex, ey, z0, z1;
+  bool col;  // the column lies in the grid
+};
+__device__ __forceinline__ FiltPos filt_pos(const Geo& G, int tiles_x, int tiles_y) {
+  FiltPos q;
   const int tx = threadIdx.x % kFiltBX, ty = threadIdx.x / kFiltBX;
   const int b = blockIdx.x;
   const int bx = b % tiles_x, t2 = b / tiles_x, by = t2 % tiles_y, bz = t2 / tiles_y;
-  const int ex = bx * kFiltBX + tx, ey = by * kFiltBY + ty;
-  const int z0 = bz * kFiltDZ, z1 = min(z0 + kFiltDZ, G.nz);
-  const bool col = ex < G.nx && ey < G.ny;
+  q.ex = bx * kFiltBX + tx;
+  q.ey = by * kFiltBY + ty;
+  q.z0 = bz * kFiltDZ;
+  q.z1 = min(q.z0 + kFiltDZ, G.nz);
+  q.col = q.ex < G.nx && q.ey < G.ny;
+  return q;
+}
+
+// Every value the thread's outputs read (its kFiltDZ layers and R halo
+// planes on each side, (2R + 1)^2 columns), loaded up front: one memory
+// latency per block.  Values outside the grid are 0.  trans: each value
+// times Hsi.  proj: each value v becomes the design value clamp(v - lam,
+// lo, hi) (in FP64, rounded to T, as the projection's final pass writes it).
+template <typename T, int R>
+__device__ __forceinline__ void filt_window(const Geo& G, const FiltPos& q, const T* in, const T* Hsi, bool trans,
+                                            T (&win)[kFiltDZ + 2 * R][2 * R + 1][2 * R + 1], bool proj = false,
+                                            double lam = 0.0, double lo = 0.0, double hi = 0.0) {
+  constexpr int D = 2 * R + 1;
   const int plane = G.nx * G.ny;
   bool okxy[D][D];
   int offxy[D][D];
@@ -2231,17 +2250,13 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
   for (int dy = 0; dy < D; ++dy)
 #pragma unroll
     for (int dx = 0; dx < D; ++dx) {
-      const int jx = ex + dx - R, jy = ey + dy - R;
-      okxy[dy][dx] = col && jx >= 0 && jx < G.nx && jy >= 0 && jy < G.ny;
+      const int jx = q.ex + dx - R, jy = q.ey + dy - R;
+      okxy[dy][dx] = q.col && jx >= 0 && jx < G.nx && jy >= 0 && jy < G.ny;
       offxy[dy][dx] = okxy[dy][dx] ? jx + G.nx * jy : 0;
     }
-  // every plane the slab reads (its kFiltDZ layers and R halo planes on
-  // each side) is loaded up front: one memory latency per block
-  constexpr int NP = kFiltDZ + 2 * R;
-  T win[NP][D][D];  // [plane][dy][dx]
 #pragma unroll
-  for (int p = 0; p < NP; ++p) {
-    const int jz = z0 - R + p;
+  for (int p = 0; p < kFiltDZ + 2 * R; ++p) {
+    const int jz = q.z0 - R + p;
     const bool zok = jz >= 0 && jz < G.nz;
 #pragma unroll
     for (int dy = 0; dy < D; ++dy)
@@ -2250,18 +2265,43 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
         const bool ok = okxy[dy][dx] && zok;
         const int j = ok ? offxy[dy][dx] + jz * plane : 0;
         T v = in[j];
-        if (kind == FILT_TRANS) v *= Hsi[j];
+        if (trans) v *= Hsi[j];
+        if (proj) v = (T)fmin(fmax((double)v - lam, lo), hi);
         win[p][dy][dx] = ok ? v : (T)0;
       }
   }
+}
+
+// The stencil sum of output layer l of the window.
+template <typename T, int R>
+__device__ __forceinline__ T filt_sum(const StencilW<T, R>& W, const T (&win)[kFiltDZ + 2 * R][2 * R + 1][2 * R + 1],
+                                      int l) {
+  constexpr int D = 2 * R + 1;
+  T acc = (T)0;
+#pragma unroll
+  for (int dz = 0; dz < D; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < D; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < D; ++dx) acc += W.w[dx + D * (dy + D * dz)] * win[l + dz][dy][dx];
+  return acc;
+}
+
+template <typename T, int R, bool STEP>
+__global__ void __launch_bounds__(kFiltBX * kFiltBY)
+    k_filter_z(Geo G, int kind, const T* in, T* out, const T* Hsi, StencilW<T, R> W, int want_sum,
+               double* P, int maxp, int tiles_x, int tiles_y, FiltStep<T> S) {
+  const FiltPos q = filt_pos(G, tiles_x, tiles_y);
+  T win[kFiltDZ + 2 * R][2 * R + 1][2 * R + 1];  // [plane][dy][dx]
+  filt_window<T, R>(G, q, in, Hsi, kind == FILT_TRANS, win);
   // step: the design values of the slab's outputs, and the mean of g
   T xv[kFiltDZ];
   double mean = 0.0, lam_w = 0.0;
   if constexpr (STEP) {
 #pragma unroll
     for (int l = 0; l < kFiltDZ; ++l) {
-      const int ez = z0 + l;
-      xv[l] = S.x[(col && ez < z1) ? ex + G.nx * (ey + G.ny * ez) : 0];
+      const int ez = q.z0 + l;
+      xv[l] = S.x[(q.col && ez < q.z1) ? q.ex + G.nx * (q.ey + G.ny * ez) : 0];
     }
     lam_w = S.sc->lam_prev;
     if (S.mean_project) {
@@ -2278,16 +2318,10 @@ __global__ void __launch_bounds__(kFiltBX * kFiltBY)
   proj_eval_init(ev);
 #pragma unroll
   for (int l = 0; l < kFiltDZ; ++l) {
-    const int ez = z0 + l;
-    T acc = (T)0;
-#pragma unroll
-    for (int dz = 0; dz < D; ++dz)
-#pragma unroll
-      for (int dy = 0; dy < D; ++dy)
-#pragma unroll
-        for (int dx = 0; dx < D; ++dx) acc += W.w[dx + D * (dy + D * dz)] * win[l + dz][dy][dx];
-    if (col && ez < z1) {
-      const int e = ex + G.nx * (ey + G.ny * ez);
+    const int ez = q.z0 + l;
+    const T acc = filt_sum<T, R>(W, win, l);
+    if (q.col && ez < q.z1) {
+      const int e = q.ex + G.nx * (q.ey + G.ny * ez);
       const T res = kind == FILT_FWD ? acc * Hsi[e] : acc;
       if constexpr (STEP) {
         const T ye = (T)((double)xv[l] - S.half_alpha * ((double)res - mean));
@@ -2409,17 +2443,29 @@ hipError_t launch_filter(fbto_grid_s* g, int kind, const T* in, T* out, int want
   return hipGetLastError();
 }
 
+// Whether the grid's filter runs as the z-march filter (voxel grid, stencil
+// of radius R <= 1, its tiles within the partial slots): the variants fused
+// with the step and with the final projection pass need it.
+bool zmarch_filter(const fbto_grid_s* g) {
+  if (g->dim == 2) return false;
+  const double r = g->desc.filter_radius;
+  const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
+  const Geo& G = g->geo;
+  const int64_t tiles_x = (G.nx + kFiltBX - 1) / kFiltBX, tiles_y = (G.ny + kFiltBY - 1) / kFiltBY;
+  const int64_t nbz = tiles_x * tiles_y * ((G.nz + kFiltDZ - 1) / kFiltDZ);
+  return R <= 1 && nbz <= g->max_partials;
+}
+
 template <typename T>
 hipError_t launch_filter_step(fbto_grid_s* g, const T* ge, const T* x, T* y, double half_alpha,
                               int mean_project, int nb_sum, double lo, double hi, hipStream_t st,
                               int* nb_seed) {
-  if (g->dim == 2) return hipErrorNotSupported;
+  if (!zmarch_filter(g)) return hipErrorNotSupported;
   const double r = g->desc.filter_radius;
   const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
   const Geo& G = g->geo;
   const int tiles_x = (G.nx + kFiltBX - 1) / kFiltBX, tiles_y = (G.ny + kFiltBY - 1) / kFiltBY;
   const int64_t nbz = (int64_t)tiles_x * tiles_y * ((G.nz + kFiltDZ - 1) / kFiltDZ);
-  if (R > 1 || nbz > g->max_partials) return hipErrorNotSupported;
   if (mean_project && (nb_sum < 1 || nb_sum > g->max_partials)) return hipErrorInvalidValue;
   const FiltStep<T> S{x, y, half_alpha, mean_project, nb_sum, lo, hi, (const Scalars*)g->sc};
   const T* Hsi = (const T*)vecs_of<T>(g).Hs;  // not read by the plain sum
@@ -2701,6 +2747,87 @@ __global__ void __launch_bounds__(kVecBlock)
   write_parts<2, 0x2u, kVecBlock>(v, dst, blockIdx.x);
 }
 
+// The final pass fused with the forward filter of the next outer iteration:
+// both need only y and the multiplier.  Each thread writes x = clamp(y -
+// lam, lo, hi) at its own elements, as k_proj_final does, and rho = (H x) /
+// Hs there from the same values in the window around them, recomputed from
+// y, so that no block waits for another's x.  The multiplier, the status
+// and the partials (sum x, max |x - x_old|, x updated in place) are those of
+// k_proj_final; rho equals the forward filter of the new x bitwise.
+template <typename T, int R>
+__global__ void __launch_bounds__(kFiltBX * kFiltBY)
+    k_proj_final_filter(Geo G, const T* y, T* x, T* rho, const T* Hsi, StencilW<T, R> Wf, double lo, double hi,
+                        double vmax, ProjWs W, int nb, int passes, int tiles_x, int tiles_y) {
+  constexpr int D = 2 * R + 1;
+  const FiltPos q = filt_pos(G, tiles_x, tiles_y);
+  T xo[kFiltDZ];  // the design before the step at the own elements (only their owner reads them)
+#pragma unroll
+  for (int l = 0; l < kFiltDZ; ++l) {
+    const int ez = q.z0 + l;
+    xo[l] = x[(q.col && ez < q.z1) ? q.ex + G.nx * (q.ey + G.ny * ez) : 0];
+  }
+  Scalars* sc = W.sc;
+  const double* in = sc->ps[passes & 1];
+  double lam = in[0];
+  bool bad = false, unfinished = false;
+  if (in[3] == 0.0) {  // pass budget spent: decide from the last evaluation
+    const ProjDecision d =
+        proj_decide(W, nb, false, passes, lo, hi, vmax, sc->lam_prev, in[0], in[1], in[2]);
+    lam = d.done ? d.lam : d.b;
+    bad = d.bad;
+    unfinished = !d.done;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double status = sc->proj_status;  // 0, or FBTO_ERR_NONFINITE from a pass
+    if (bad) status = (double)FBTO_ERR_NONFINITE;
+    else if (unfinished && status == 0.0) status = (double)FBTO_INEXACT;
+    sc->proj_status = status;
+    sc->lam = lam;
+    sc->lam_prev = lam;
+  }
+  // the window of new design values, from y and the multiplier
+  T win[kFiltDZ + 2 * R][D][D];
+  filt_window<T, R>(G, q, y, nullptr, false, win, true, lam, lo, hi);
+  double v[2] = {0.0, 0.0};
+#pragma unroll
+  for (int l = 0; l < kFiltDZ; ++l) {
+    const int ez = q.z0 + l;
+    const T acc = filt_sum<T, R>(Wf, win, l);
+    if (q.col && ez < q.z1) {
+      const int e = q.ex + G.nx * (q.ey + G.ny * ez);
+      const T xe = win[l + R][R][R];
+      v[1] = fmax(v[1], fabs((double)xe - (double)xo[l]));
+      x[e] = xe;
+      v[0] += (double)xe;
+      rho[e] = acc * Hsi[e];
+    }
+  }
+  double* dst[2] = {lslot(W, L_VOL), lslot(W, L_DX)};
+  write_parts<2, 0x2u, kFiltBX * kFiltBY>(v, dst, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_proj_final_filter(fbto_grid_s* g, const ProjWs& W, const T* y, T* x, T* rho, double lo,
+                                    double hi, double vmax, int passes, hipStream_t st, int* nb_final) {
+  if (!zmarch_filter(g)) return hipErrorNotSupported;
+  const double r = g->desc.filter_radius;
+  const int R = r > 1.0 ? (int)std::ceil(r) - 1 : 0;
+  const Geo& G = g->geo;
+  const int tiles_x = (G.nx + kFiltBX - 1) / kFiltBX, tiles_y = (G.ny + kFiltBY - 1) / kFiltBY;
+  const int64_t nbz = (int64_t)tiles_x * tiles_y * ((G.nz + kFiltDZ - 1) / kFiltDZ);
+  if (nbz > W.maxp) return hipErrorInvalidValue;
+  const int nb = vec_blocks(G.E);  // the passes' partials
+  const T* Hsi = (const T*)vecs_of<T>(g).Hs;
+  if (R == 0)
+    hipLaunchKernelGGL((k_proj_final_filter<T, 0>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, y, x, rho, Hsi,
+                       stencil_weights<T, 0>(r), lo, hi, vmax, W, nb, passes, tiles_x, tiles_y);
+  else
+    hipLaunchKernelGGL((k_proj_final_filter<T, 1>), dim3(nbz), dim3(kFiltBX * kFiltBY), 0, st, G, y, x, rho, Hsi,
+                       stencil_weights<T, 1>(r), lo, hi, vmax, W, nb, passes, tiles_x, tiles_y);
+  *nb_final = (int)nbz;
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double half_alpha,
                        int mean_project, double lo, double hi, hipStream_t st) {
@@ -2713,7 +2840,7 @@ hipError_t launch_step(fbto_grid_s* g, const T* x, const T* gx, T* y, double hal
 template <typename T>
 hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double lo, double hi, double vmax,
                           int seeded, int passes, const T* x_old, double* lam_out, double* status_out,
-                          hipStream_t st, int nb_seed) {
+                          hipStream_t st, int nb_seed, int skip_final) {
   const int nb = vec_blocks(E);
   if (nb > W.maxp || nb_seed > W.maxp) return hipErrorInvalidValue;
   if (!seeded || nb_seed < 1) nb_seed = nb;
@@ -2724,6 +2851,7 @@ hipError_t launch_project(const ProjWs& W, int64_t E, const T* y, T* x, double l
     hipLaunchKernelGGL((k_proj_pass<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, lo, hi, vmax, p, W,
                        p == 0 ? nb_seed : nb, seeded);
   }
+  if (skip_final) return hipGetLastError();
   hipLaunchKernelGGL((k_proj_final<T>), dim3(nb), dim3(kVecBlock), 0, st, E, y, x, lo, hi, vmax, x_old, W, nb,
                      passes, lam_out, status_out);
   return hipGetLastError();
@@ -2879,7 +3007,9 @@ hipError_t launch_opt_finish(fbto_grid_s* g, int nrhs, int nb_dot, int nb_lo, in
   template hipError_t launch_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, double,       \
                                      double, hipStream_t);                                             \
   template hipError_t launch_project<T>(const ProjWs&, int64_t, const T*, T*, double, double, double, int, \
-                                        int, const T*, double*, double*, hipStream_t, int);               \
+                                        int, const T*, double*, double*, hipStream_t, int, int);          \
+  template hipError_t launch_proj_final_filter<T>(fbto_grid_s*, const ProjWs&, const T*, T*, T*, double, \
+                                                  double, double, int, hipStream_t, int*);               \
   template hipError_t launch_filter_step<T>(fbto_grid_s*, const T*, const T*, T*, double, int, int, double, \
                                             double, hipStream_t, int*);
 

@@ -233,6 +233,21 @@ class Grid:
         return x
 
 
+    def outer_steps(self, x, u, f, k: int, n_steps: int, alpha0: float, inner_steps: int, lo: float, vmax: float,
+                    mean_project: bool = True, info: Optional[torch.Tensor] = None, stream=None):
+        """Outer iterations k .. k + n_steps - 1 of Alg. 1 in one call
+        (fbto_outer_steps): the results of n_steps outer_step calls.  info:
+        float64 [n_steps * 8], one record per iteration."""
+        nr = self._nrhs(u)
+        if info is not None and info.numel() < 8 * int(n_steps):
+            raise ValueError("info needs 8 values per iteration")
+        check(self.lib.fbto_outer_steps(self.handle, _prec(x), _ptr(x, None, self.E, "x"), _ptr(u, x.dtype, None, "u"),
+                                        _ptr(f, x.dtype, u.numel(), "f"), nr, int(k), int(n_steps), float(alpha0),
+                                        int(inner_steps), 1 if mean_project else 0, float(lo), float(vmax),
+                                        _ptr(info, torch.float64, None, "info"), _stream(stream)), self.lib)
+        return x
+
+
 class PlaneGrid(Grid):
     """A plane grid of nx x ny Q4 elements with the separable Gaussian filter
     (fbto_setup_grid_2d); vectors are [nrhs][2N].  Every method of Grid

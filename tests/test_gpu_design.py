@@ -255,6 +255,41 @@ def test_outer_gradient_mean_and_step(radius, dtype, mean_project):
     assert abs(recs[0][3] - rec.lam) <= (1e-9 if dtype == torch.float64 else 2e-5) * max(1.0, abs(rec.lam))
 
 
+@pytest.mark.parametrize("radius", [1.5, 3.0])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_outer_steps_equal_single_steps(radius, dtype):
+    """fbto_outer_steps runs n iterations in one call; with r = 1.5 the final
+    projection pass of each iteration also filters the new design for the
+    next one.  The result must be that of n fbto_outer_step calls: x, u and
+    the records bitwise, but the volume (the same sum over other partial
+    groupings) to 1e-12.  A grid ragged against the filter's 64 x 4 x 4
+    tiles."""
+    say(f"outer_steps r={radius} {dtype}")
+    p = synth.cantilever(70, 13, 9, volfrac=0.3, filter_radius=radius, outer_iters=4, inner_steps=5, seed=8)
+    n, a0 = 4, 0.002
+    res = []
+    for multi in (False, True):
+        g = _grid(p)
+        x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
+        u = torch.zeros(p.ndof, dtype=dtype, device=DEV)
+        f = dev(p.loads[0], dtype)
+        info = torch.zeros(8 * n, dtype=torch.float64, device=DEV)
+        if multi:
+            g.outer_steps(x, u, f, 1, n, a0, p.inner_steps, 0.0, p.vmax, info=info)
+        else:
+            for k in range(1, n + 1):
+                g.outer_step(x, u, f, k, a0, p.inner_steps, 0.0, p.vmax, info=info[8 * (k - 1):8 * k])
+        res.append((host(x).copy(), host(u).copy(), host(info).reshape(n, 8).copy()))
+        g.close()
+    (x1, u1, i1), (x2, u2, i2) = res
+    assert np.array_equal(x1, x2) and np.array_equal(u1, u2)
+    vol = 4  # FBTO_OI_VOLUME
+    rest = [c for c in range(8) if c != vol]
+    assert np.array_equal(i1[:, rest], i2[:, rest]), (i1, i2)
+    assert np.abs(i1[:, vol] - i2[:, vol]).max() <= 1e-12 * p.vmax
+    assert (i1[:, 6] == 0).all()
+
+
 def test_outer_trajectory_cfg1_fp64():
     """16x8x8 cantilever, 50 outer iterations x 5 PCG steps in FP64 against
     the oracle: compliance and design agree to 1e-9 relative."""
