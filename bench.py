@@ -571,14 +571,14 @@ def main():
     traffic = measured_traffic("k_apply<float, 1, 3>", "outer_step_pmc.json")
     # algorithmic bytes of one outer iteration (FP32, m inner steps), kernel by kernel
     m = p.inner_steps
-    bytes_outer = (3 * E * 4                                    # filter: x, 1/Hs in, rho out
+    bytes_outer = (2 * E * 4                                    # filter, in the final pass below: 1/Hs in, rho out
                    + 5 * ndof * 4 + N + E * 4                   # residual: u, f in; r, z, D^-1 out
                    + 3 * ndof * 4 + N + E * 4                   # step 0 product: z, r in; w out
                    + (m - 1) * bytes_fused                      # fused steps
                    + 8 * ndof * 4 + N + 3 * E * 4               # last step + sensitivity: x r p s w D^-1 f in, x out; rho, 1/Hs in, g out
                    + 3 * E * 4                                  # filter transpose with the step: g, x in, y out
                    + 2 * E * 4                                  # projection: one or two working passes
-                   + 3 * E * 4)                                 # final projection pass: y, x_old in, x out
+                   + 3 * E * 4)                                 # final projection pass: y, x_old in, x out (and the filter's x)
 
     fixed = None if args.no_fixed_err else fixed_error(g, p, torch)
     sizes = None if args.no_sizes else apply_sizes(torch)
