@@ -149,8 +149,8 @@ def test_apply_argument_errors():
 @pytest.mark.parametrize("penal", [1.0, 3.5])
 def test_general_simp_exponent(penal, dtype):
     """SIMP exponents other than 3 (Sec. 3's power law with a general p):
-    K(rho)u, the sensitivity and eight fused FP32 / unfused FP64 PCG steps
-    against the oracle, densities including 0 and 1."""
+    K(rho)u, the sensitivity and eight fused PCG steps against the oracle,
+    densities including 0 and 1."""
     say(f"simp exponent {penal} {dtype}")
     p = _case(23, 9, 7, 31)
     p.penal = penal

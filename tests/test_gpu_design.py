@@ -290,6 +290,23 @@ def test_outer_steps_equal_single_steps(radius, dtype):
     assert (i1[:, 6] == 0).all()
 
 
+def test_outer_steps_argument_errors():
+    """fbto_outer_steps rejects an empty run and a 0-based k before any
+    launch, leaving x unchanged."""
+    from paper_2204_06204_amd import FbtoError
+    p = synth.cantilever(8, 4, 4, volfrac=0.3, filter_radius=1.5, outer_iters=1, inner_steps=2, seed=1)
+    g = _grid(p)
+    x = g.project_volume(dev(p.x0, torch.float32), lo=0.0, hi=1.0, vmax=p.vmax)
+    x0 = host(x).copy()
+    u = torch.zeros(p.ndof, dtype=torch.float32, device=DEV)
+    f = dev(p.loads[0], torch.float32)
+    for k, n in ((1, 0), (0, 2), (1, -3)):
+        with pytest.raises(FbtoError):
+            g.outer_steps(x, u, f, k, n, 0.01, 2, 0.0, p.vmax)
+    assert np.array_equal(host(x), x0)
+    g.close()
+
+
 def test_outer_trajectory_cfg1_fp64():
     """16x8x8 cantilever, 50 outer iterations x 5 PCG steps in FP64 against
     the oracle: compliance and design agree to 1e-9 relative."""
