@@ -218,13 +218,13 @@ def _run_gpu(p, iters, alpha0, dtype, g=None, krylov=None, exact_rtol=None):
     return recs, xs, host(u)
 
 
-@pytest.mark.parametrize("radius", [1.5, 3.0])
+@pytest.mark.parametrize("radius", [1.0, 1.5, 3.0])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 @pytest.mark.parametrize("mean_project", [True, False])
 def test_outer_gradient_mean_and_step(radius, dtype, mean_project):
     """One outer step against the oracle: the recorded mean of the filtered
     gradient (before the mean projection) and the design after the step.
-    With r = 1.5 the step runs inside the transposed filter and takes the
+    With r = 1 and 1.5 the step runs inside the transposed filter and takes the
     mean from the sum the sensitivity kernel forms (equal, as the filter
     weights are symmetric); with r = 3 the filter and the step are two
     kernels and the mean is summed from the filtered gradient.  Without the
@@ -255,7 +255,7 @@ def test_outer_gradient_mean_and_step(radius, dtype, mean_project):
     assert abs(recs[0][3] - rec.lam) <= (1e-9 if dtype == torch.float64 else 2e-5) * max(1.0, abs(rec.lam))
 
 
-@pytest.mark.parametrize("radius", [1.5, 3.0])
+@pytest.mark.parametrize("radius", [1.0, 1.5, 3.0])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
 def test_outer_steps_equal_single_steps(radius, dtype):
     """fbto_outer_steps runs n iterations in one call; with r = 1.5 the final
@@ -263,7 +263,8 @@ def test_outer_steps_equal_single_steps(radius, dtype):
     next one.  The result must be that of n fbto_outer_step calls: x, u and
     the records bitwise, but the volume (the same sum over other partial
     groupings) to 1e-12.  A grid ragged against the filter's 64 x 4 x 4
-    tiles."""
+    tiles; r = 1 and 1.5 fuse (a one- and a 27-point stencil), r = 3 does
+    not."""
     say(f"outer_steps r={radius} {dtype}")
     p = synth.cantilever(70, 13, 9, volfrac=0.3, filter_radius=radius, outer_iters=4, inner_steps=5, seed=8)
     n, a0 = 4, 0.002
