@@ -541,7 +541,8 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   // f.f) and max|r| over its owned nodes, at most 3 (dz + 1) terms per RHS,
   // accumulate in T and join the FP64 partials before the block reduction;
   // sums with terms of either sign (w.z) stay FP64 throughout.
-  //   RESID: r.r, max|r|, f.f   CG, CGF: r.z, r.r, max|r|
+  //   RESID: r.r, max|r|, f.f   CG, CGF: r.z, r.r (the step's coefficients
+  //   need no max|r|; the final residual's comes from the last step)
   T tpart[NR][3];
 #pragma unroll
   for (int r = 0; r < NR; ++r) tpart[r][0] = tpart[r][1] = tpart[r][2] = (T)0;
@@ -613,7 +614,6 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
           if (owner) {
             tpart[0][0] += rn[c] * zn;     // r.z
             tpart[0][1] += rn[c] * rn[c];  // r.r
-            tpart[0][2] = fmax(tpart[0][2], fabs(rn[c]));
           }
         }
       }
@@ -999,7 +999,6 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
               tpart[r][0] += own_t(rv * pv[c]);                             // r.z
               part[4 * r + 1] += own_only((double)acc[c] * (double)pv[c]);  // w.z
               tpart[r][1] += own_t(rv * rv);                                // r.r
-              tpart[r][2] = fmax(tpart[r][2], own_t(fabs(rv)));
             }
           }
           if constexpr (MODE == MODE_CGF || MODE == MODE_MRF) {
@@ -1027,21 +1026,18 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   if constexpr (MODE == MODE_CG || MODE == MODE_CGF) {
     // CG: step k's product -> set k & 1; CGF: step k + 1's -> set (k + 1) & 1
     const int par = (MODE == MODE_CG ? A.step : A.step + 1) & 1;
-    double* dst[4 * NR];
+    double* dst[3 * NR];
+    double v[3 * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      dst[4 * r + 0] = pslot(A.P, P_RZ0 + par, rhs0 + r, A.maxp);
-      dst[4 * r + 1] = pslot(A.P, P_PQ0 + par, rhs0 + r, A.maxp);
-      dst[4 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
-      dst[4 * r + 3] = pslot(A.P, P_RI0 + par, rhs0 + r, A.maxp);
+      dst[3 * r + 0] = pslot(A.P, P_RZ0 + par, rhs0 + r, A.maxp);
+      dst[3 * r + 1] = pslot(A.P, P_PQ0 + par, rhs0 + r, A.maxp);
+      dst[3 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
+      v[3 * r + 0] = (double)tpart[r][0];
+      v[3 * r + 1] = part[4 * r + 1];
+      v[3 * r + 2] = (double)tpart[r][1];
     }
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      part[4 * r + 0] = (double)tpart[r][0];
-      part[4 * r + 2] = (double)tpart[r][1];
-      part[4 * r + 3] = (double)tpart[r][2];
-    }
-    write_parts<4 * NR, 0x8888u>(part, dst, lb);
+    write_parts<3 * NR, 0u>(v, dst, lb);
   }
   if constexpr (MODE == MODE_MRF) {
     // ||y||^2 -> the norm slot of iteration t; <K y, y> and <R2, y> -> the
