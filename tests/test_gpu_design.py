@@ -291,6 +291,35 @@ def test_outer_steps_equal_single_steps(radius, dtype):
     assert (i1[:, 6] == 0).all()
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_outer_steps_multiload_equal_single_steps(dtype):
+    """Several load cases (the sensitivity and the step then run as separate
+    kernels; the final pass still filters the next design): fbto_outer_steps
+    gives the results of single fbto_outer_step calls bitwise."""
+    say(f"outer_steps multi-load {dtype}")
+    p = synth.multiload_cantilever(24, 12, 12, seed=3, filter_radius=1.5)
+    n, a0 = 3, 0.002
+    res = []
+    for multi in (False, True):
+        g = _grid(p, max_rhs=p.nrhs)
+        x = g.project_volume(dev(p.x0, dtype), lo=0.0, hi=1.0, vmax=p.vmax)
+        u = torch.zeros(p.nrhs * p.ndof, dtype=dtype, device=DEV)
+        f = dev(p.loads.ravel(), dtype)
+        info = torch.zeros(8 * n, dtype=torch.float64, device=DEV)
+        if multi:
+            g.outer_steps(x, u, f, 1, n, a0, p.inner_steps, 0.0, p.vmax, info=info)
+        else:
+            for k in range(1, n + 1):
+                g.outer_step(x, u, f, k, a0, p.inner_steps, 0.0, p.vmax, info=info[8 * (k - 1):8 * k])
+        res.append((host(x).copy(), host(u).copy(), host(info).reshape(n, 8).copy()))
+        g.close()
+    (x1, u1, i1), (x2, u2, i2) = res
+    assert np.array_equal(x1, x2) and np.array_equal(u1, u2)
+    rest = [c for c in range(8) if c != 4]
+    assert np.array_equal(i1[:, rest], i2[:, rest])
+    assert np.abs(i1[:, 4] - i2[:, 4]).max() <= 1e-12 * p.vmax
+
+
 def test_outer_steps_argument_errors():
     """fbto_outer_steps rejects an empty run and a 0-based k before any
     launch, leaving x unchanged."""
