@@ -568,7 +568,7 @@ def main():
     # each), read the mask byte per node and one density per element
     bytes_fused = 11 * ndof * 4 + N + E * 4
     achieved = bytes_fused / t_fused / 1e9
-    traffic = measured_traffic("k_apply<float, 1, 3>", "outer_step_pmc.json")
+    traffic = measured_traffic("k_apply<float, 1, 3, false>", "outer_step_pmc.json")
     # algorithmic bytes of one outer iteration (FP32, m inner steps), kernel by kernel
     m = p.inner_steps
     bytes_outer = (2 * E * 4                                    # filter, in the final pass below: 1/Hs in, rho out

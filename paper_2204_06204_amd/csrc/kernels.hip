@@ -378,7 +378,9 @@ constexpr int apply_min_waves() {
   return (sizeof(T) == 4 && NR == 1 && (MODE == MODE_CGF || MODE == MODE_MRF)) ? 3 : 1;
 }
 
-template <typename T, int NR, int MODE>
+// RR (fused CG step): form r.r for the tolerance test; solves of a fixed
+// step count (rtol = 0) read no r.r and run the variant without it.
+template <typename T, int NR, int MODE, bool RR = true>
 __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_per_eu(apply_min_waves<T, NR, MODE>())))
     k_apply(ApplyArgs<T> A, int rhs0) {
   extern __shared__ __align__(16) unsigned char apply_smem[];
@@ -613,7 +615,7 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
           xn[c] = S.x[c] + al * pn[c];
           if (owner) {
             tpart[0][0] += rn[c] * zn;     // r.z
-            tpart[0][1] += rn[c] * rn[c];  // r.r
+            if constexpr (RR) tpart[0][1] += rn[c] * rn[c];  // r.r
           }
         }
       }
@@ -1026,18 +1028,21 @@ __global__ void __launch_bounds__(kApplyMaxThreads) __attribute__((amdgpu_waves_
   if constexpr (MODE == MODE_CG || MODE == MODE_CGF) {
     // CG: step k's product -> set k & 1; CGF: step k + 1's -> set (k + 1) & 1
     const int par = (MODE == MODE_CG ? A.step : A.step + 1) & 1;
-    double* dst[3 * NR];
-    double v[3 * NR];
+    constexpr int NV = RR ? 3 : 2;  // r.z, w.z (, r.r)
+    double* dst[NV * NR];
+    double v[NV * NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
-      dst[3 * r + 0] = pslot(A.P, P_RZ0 + par, rhs0 + r, A.maxp);
-      dst[3 * r + 1] = pslot(A.P, P_PQ0 + par, rhs0 + r, A.maxp);
-      dst[3 * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
-      v[3 * r + 0] = (double)tpart[r][0];
-      v[3 * r + 1] = part[4 * r + 1];
-      v[3 * r + 2] = (double)tpart[r][1];
+      dst[NV * r + 0] = pslot(A.P, P_RZ0 + par, rhs0 + r, A.maxp);
+      dst[NV * r + 1] = pslot(A.P, P_PQ0 + par, rhs0 + r, A.maxp);
+      v[NV * r + 0] = (double)tpart[r][0];
+      v[NV * r + 1] = part[4 * r + 1];
+      if constexpr (RR) {
+        dst[NV * r + 2] = pslot(A.P, P_RN0 + par, rhs0 + r, A.maxp);
+        v[NV * r + 2] = (double)tpart[r][1];
+      }
     }
-    write_parts<3 * NR, 0u>(v, dst, lb);
+    write_parts<NV * NR, 0u>(v, dst, lb);
   }
   if constexpr (MODE == MODE_MRF) {
     // ||y||^2 -> the norm slot of iteration t; <K y, y> and <R2, y> -> the
@@ -1401,7 +1406,7 @@ static TileChoice choose_tile(const Geo& G, int n_cu, int lds_per_cu, int overri
   return best;
 }
 
-template <typename T, int NR, int MODE>
+template <typename T, int NR, int MODE, bool RR = true>
 static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs0, hipStream_t st,
                                  int* nb_out) {
   TileChoice& t = g->tiles[sizeof(T) == 8 ? 1 : 0][NR - 1][MODE];
@@ -1424,11 +1429,11 @@ static hipError_t launch_apply_t(fbto_grid_s* g, const ApplyArgs<T>& A0, int rhs
   size_t lds = apply_lds_bytes<T, NR, MODE>(t.bx, t.by);
   if (t.cap) lds = std::max(lds, (size_t)lds_for_block_cap(g->lds_per_cu, t.cap));
   const int threads = zmarch_threads<MODE>(t.bx, t.by);  // whole waves
-  hipLaunchKernelGGL((k_apply<T, NR, MODE>), dim3(grid), dim3(threads), lds, st, A, rhs0);
+  hipLaunchKernelGGL((k_apply<T, NR, MODE, RR>), dim3(grid), dim3(threads), lds, st, A, rhs0);
   return hipGetLastError();
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool RR = true>
 static hipError_t launch_apply_mode(fbto_grid_s* g, ApplyArgs<T> A, int nrhs, hipStream_t st, int* nb_out) {
   A.g = g->geo;
   A.mask = g->mask;
@@ -1443,7 +1448,7 @@ static hipError_t launch_apply_mode(fbto_grid_s* g, ApplyArgs<T> A, int nrhs, hi
   // one RHS per launch: the per-RHS state of the z-march (two face-mode
   // sets, the modal carry, staged loads) fills the register file at NR = 1
   hipError_t e = hipSuccess;
-  for (int r0 = 0; r0 < nrhs && e == hipSuccess; ++r0) e = launch_apply_t<T, 1, MODE>(g, A, r0, st, nb_out);
+  for (int r0 = 0; r0 < nrhs && e == hipSuccess; ++r0) e = launch_apply_t<T, 1, MODE, RR>(g, A, r0, st, nb_out);
   return e;
 }
 
@@ -1561,7 +1566,9 @@ hipError_t launch_cg_fused(fbto_grid_s* g, const T* rho, const CgSet<T>& in, con
   A.n_apply = n_apply;
   A.n_fn = n_fn;
   A.rtol = rtol;
-  return launch_apply_mode<T, MODE_CGF>(g, A, nrhs, st, nb_out);
+  // r.r only for the tolerance test
+  return rtol > 0.0 ? launch_apply_mode<T, MODE_CGF, true>(g, A, nrhs, st, nb_out)
+                    : launch_apply_mode<T, MODE_CGF, false>(g, A, nrhs, st, nb_out);
 }
 
 template <typename T>
